@@ -1,0 +1,180 @@
+/*
+ * csc.h -- C ABI of the Characteristic/Scan Conversion (CSC) narrow-band signed
+ * distance library for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Roosing, Strickson, Nikiforakis, "Fast Distance Fields for Fluid
+ * Dynamics Mesh Generation on Graphics Hardware" (2019). Every face, edge and
+ * vertex of a closed, consistently oriented triangle surface gets a
+ * characteristic polyhedron (Section 3, Section 8); each polyhedron is
+ * scan-converted onto the grid cells it contains (Section 5) and every cell keeps
+ * the smallest distance to a feature whose polyhedron contains it (Alg. 1,
+ * Section 2; Section 10). The sign comes from the angle-weighted pseudonormal of
+ * the closest feature (Section 4.1.3, Eq. 8).
+ *
+ * Conventions (all entry points):
+ *   - Pointers named *_d are device pointers owned by the caller (for example
+ *     torch tensors); they must stay valid until the work queued on `stream`
+ *     has finished. `stream` is a hipStream_t (NULL: the default stream).
+ *   - Every call queues its device work asynchronously on `stream`; arguments
+ *     are checked on the host first and nothing is queued when a check fails.
+ *   - Return value: CSC_OK (0) or one of the error codes below. No C++
+ *     exception crosses this interface.
+ *   - Grid: cell (i, j, k) has centre origin + (i + 1/2, j + 1/2, k + 1/2) * h and
+ *     linear index i + n[0] * (j + n[1] * k). A cell is in the band when its
+ *     distance to the surface is strictly below band_cells * h (Section 10:
+ *     values are written only below the user maximum distance).
+ *   - Feature ids: faces 0..F-1 in input order; edges F + e, where e numbers the
+ *     half-edges 3f+j whose start vertex index is below their end vertex index,
+ *     in face-major order; vertices F + E + v.
+ *   - Surface: vertices float32 [nv][3]; triangles int32 [nf][3], counter-clockwise
+ *     seen from outside (Section 7); closed, 2-manifold, no zero-area face
+ *     (Section 4, Section 6).
+ */
+#ifndef CSC_H
+#define CSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum csc_status {
+  CSC_OK = 0,
+  CSC_INVALID_ARG = 1,             /* null pointer, size <= 0, non-finite grid value, index out of range,
+                                      repeated vertex in a triangle, non-finite coordinate, bad size */
+  CSC_NONMANIFOLD = 2,             /* an edge is not shared by exactly two triangles (open surface) */
+  CSC_INCONSISTENT_ORIENTATION = 3,/* a directed edge occurs twice (flipped or duplicated triangle) */
+  CSC_DEGENERATE_FACE = 4,         /* a triangle of zero area */
+  CSC_GRID_TOO_LARGE = 5,          /* more than 2^31 - 1 cells, or more than 2^24 bricks */
+  CSC_OUT_OF_MEMORY = 6,
+  CSC_HIP_ERROR = 7,               /* a HIP runtime call failed (see csc_last_hip_error) */
+  CSC_WORKSPACE_TOO_SMALL = 8,
+  CSC_UNSUPPORTED_DEVICE = 9       /* the current device is not gfx950 */
+};
+
+typedef struct csc_grid {
+  double origin[3];   /* corner of cell (0, 0, 0) */
+  double h;           /* cell size, > 0 */
+  int32_t n[3];       /* cells per axis, each > 0 */
+  float band_cells;   /* band half-width in cells, > 0 */
+} csc_grid;
+
+typedef struct csc_options {
+  float eps_rel;            /* slack of the inclusion tests as a fraction of h (Section 10: 1e-4..1e-3).
+                               Only which cells are tested depends on it, never a value. Default 1e-3. */
+  int32_t ruff_mode;        /* vertices with a normal pointing away from the pseudonormal (Section 3.3):
+                               0 hemisphere (default, Section 4.1.3), 1 cone over the positive normals */
+  int32_t saddle_mode;      /* saddle vertices (Section 3.2): 0 cone and its reflection (default),
+                               1 hemispheres on both sides, 2 no extrusion (ablation only) */
+  int32_t force_both_sides; /* 1: extrude every non-flat edge and every vertex on both sides */
+} csc_options;
+
+typedef struct csc_features csc_features; /* opaque, library-owned, device resident */
+
+/* Counts gathered while building the features (valid after a successful build). */
+typedef struct csc_feature_info {
+  int64_t n_vertices, n_faces, n_edges;
+  int64_t n_edge_polyhedra, n_vertex_polyhedra;   /* faces give one prism each */
+  int64_t edges_convex, edges_concave, edges_flat, edges_unknown;
+  int64_t vertices_convex, vertices_concave, vertices_flat, vertices_saddle, vertices_ruff;
+  int64_t n_bricks;                               /* allocated 8^3-cell bricks of the band store */
+  int64_t max_band_cells;                         /* upper bound of the band size (n_bricks * 512) */
+} csc_feature_info;
+
+/*
+ * Build the features and their characteristic polyhedra (Section 7, Section 8):
+ * edge/face adjacency, unit face normals, angle-weighted pseudonormals (Eq. 8),
+ * edge classes (exact orientation predicate on the float inputs) and vertex
+ * classes, cone apertures and ruff flags (double precision), the lists of edge
+ * and vertex polyhedra, and the set of 8^3-cell bricks the band can touch.
+ *
+ * verts_d: float32 [nv][3]; tris_d: int32 [nf][3]. Both stay owned by the caller
+ * and are read again by csc_scan_convert and csc_sdf_backward, so they must
+ * outlive the handle and must not change while it is in use.
+ * grid: cell geometry and band width. opt: NULL for defaults.
+ * out: if *out is a handle from an earlier call, it is rebuilt in place (its
+ * device memory is reused when large enough); else a new handle is made.
+ * Synchronises `stream` once (to read back error flags and counts).
+ * Errors: INVALID_ARG, NONMANIFOLD, INCONSISTENT_ORIENTATION, DEGENERATE_FACE,
+ * GRID_TOO_LARGE, OUT_OF_MEMORY, HIP_ERROR, UNSUPPORTED_DEVICE. On error a new
+ * handle is not returned (*out unchanged) and a reused handle is left unusable
+ * until rebuilt.
+ */
+int csc_build_features(const float* verts_d, int64_t nv, const int32_t* tris_d, int64_t nf,
+                       const csc_grid* grid, const csc_options* opt, void* stream, csc_features** out);
+
+/* Copy the counts of a built handle into *info. */
+int csc_features_info(const csc_features* f, csc_feature_info* info);
+
+/* Device workspace (bytes) csc_scan_convert needs, and the largest band size it
+ * can return (the length the sdf/feat/cell outputs must have). */
+int csc_scan_convert_workspace(const csc_features* f, size_t* bytes, int64_t* max_band_cells);
+
+/*
+ * Scan-convert every polyhedron (Section 5, Alg. 2: inclusion by the half-space
+ * test with slack, cones and hemispheres by their discriminant, Eq. 10), compute
+ * the exact distance from each contained cell centre to the polyhedron's feature
+ * (closed triangle, segment or point), keep per cell the smallest
+ * (distance, feature id) pair (Alg. 1) and drop cells at distance >= band_cells*h;
+ * then sign each band cell with the pseudonormal of its closest feature
+ * (Section 4.1.3) and write the band as a compact list.
+ *
+ * workspace_d: ws_bytes >= csc_scan_convert_workspace() bytes of device memory.
+ * sdf_d (float32), feat_d (int32), cell_d (int32 linear index): arrays of
+ * max_band_cells entries; the first *n_band_d entries are written, ordered by
+ * brick and within a brick by linear cell index (deterministic).
+ * n_band_d: device int64 scalar receiving the band size.
+ * dense_d: NULL, or float32 [n[2]][n[1]][n[0]] receiving the dense field with
+ * +infinity off the band (Alg. 1 initial value).
+ * The result is bitwise identical from run to run.
+ * Errors: INVALID_ARG, WORKSPACE_TOO_SMALL, HIP_ERROR.
+ */
+int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d, int32_t* feat_d,
+                     int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream);
+
+/*
+ * Adjoint of the band values with respect to the vertex positions. For each of
+ * the n_band band cells c (sdf_d, feat_d, cell_d as written by csc_scan_convert):
+ * with q the closest point of the cell centre on feature feat_d[c] and w_k the
+ * barycentric weights of q on the feature's vertices, SDF = s |c - q| and
+ * dSDF/dx_k = -s w_k (c - q) / |c - q| (the closest feature is held fixed);
+ * grad_verts_d[k] += grad_sdf_d[c] * dSDF/dx_k. Cells at zero distance add
+ * nothing. grad_verts_d: float32 [nv][3], accumulated (not cleared); the sum
+ * order of the float atomics varies from run to run.
+ * Errors: INVALID_ARG, HIP_ERROR.
+ */
+int csc_sdf_backward(const csc_features* f, const float* sdf_d, const int32_t* feat_d, const int32_t* cell_d,
+                     int64_t n_band, const float* grad_sdf_d, float* grad_verts_d, void* stream);
+
+/* Release a handle and its device memory (waits for nothing; the caller must
+ * make sure no queued work still uses it). NULL is accepted. */
+void csc_features_free(csc_features* f);
+
+/* Static, human-readable text of a status code. */
+const char* csc_error_string(int code);
+
+/* Text of the last HIP runtime error seen by this thread ("" if none). */
+const char* csc_last_hip_error(void);
+
+/*
+ * Host-side evaluation of the classification predicates the build uses on the
+ * device (same code), for diagnostics and tests; no device is needed.
+ * csc_classify_edge: a->b counter-clockwise in the left face with third vertex
+ * c1, third vertex c2 of the right face; returns 0 flat, 1 convex, 2 concave,
+ * 3 unknown (coordinates too far apart in magnitude for the exact evaluation).
+ * csc_classify_vertex: vertex v and its incident triangles given as the two
+ * other corners (ring[2i], ring[2i+1]) in counter-clockwise order; writes the
+ * unit pseudonormal axis[3] and the cone aperture cosine *cos_t, returns the
+ * class bits (1 outward extrusion, 2 inward, 4 outward is a hemisphere,
+ * 8 inward is a hemisphere, 16 convex, 32 concave, 64 flat, 128 saddle, 256 ruff).
+ */
+int csc_classify_edge(const float a[3], const float b[3], const float c1[3], const float c2[3]);
+int csc_classify_vertex(const float v[3], const float* ring, int32_t n_faces, const csc_options* opt,
+                        double axis[3], double* cos_t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSC_H */

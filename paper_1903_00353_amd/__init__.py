@@ -1,0 +1,310 @@
+"""Python binding of ``libcsc.so``: the Characteristic/Scan Conversion narrow-band
+signed distance field on MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the library's
+HIP kernels. PyTorch supplies device memory and the current stream. There is no
+fallback: if the library is missing or the device is not gfx950 the calls raise.
+
+Entry points mirror ``include/csc.h``: ``csc_build_features``,
+``csc_features_info``, ``csc_scan_convert_workspace``, ``csc_scan_convert``,
+``csc_sdf_backward``, ``csc_features_free``, ``csc_error_string``,
+``csc_classify_edge``, ``csc_classify_vertex``; plus the conveniences ``sdf``
+(one call, returns tensors) and ``CSCFunction`` (autograd with respect to the
+vertex positions).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libcsc.so")
+
+CSC_STATUS = {0: "OK", 1: "INVALID_ARG", 2: "NONMANIFOLD", 3: "INCONSISTENT_ORIENTATION", 4: "DEGENERATE_FACE",
+              5: "GRID_TOO_LARGE", 6: "OUT_OF_MEMORY", 7: "HIP_ERROR", 8: "WORKSPACE_TOO_SMALL",
+              9: "UNSUPPORTED_DEVICE"}
+
+
+class CscError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = f"{where}: {CSC_STATUS.get(code, code)} ({_lib_error_string(code)})"
+        if code == 7:
+            msg += f" [{lib().csc_last_hip_error().decode()}]"
+        super().__init__(msg)
+
+
+class csc_grid(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("h", C.c_double), ("n", C.c_int32 * 3), ("band_cells", C.c_float)]
+
+
+class csc_options(C.Structure):
+    _fields_ = [("eps_rel", C.c_float), ("ruff_mode", C.c_int32), ("saddle_mode", C.c_int32),
+                ("force_both_sides", C.c_int32)]
+
+
+class csc_feature_info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "n_vertices", "n_faces", "n_edges", "n_edge_polyhedra", "n_vertex_polyhedra",
+        "edges_convex", "edges_concave", "edges_flat", "edges_unknown",
+        "vertices_convex", "vertices_concave", "vertices_flat", "vertices_saddle", "vertices_ruff",
+        "n_bricks", "max_band_cells")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspace", "csc_scan_convert",
+           "csc_sdf_backward", "csc_features_free", "csc_error_string", "csc_last_hip_error",
+           "csc_classify_edge", "csc_classify_vertex"]
+
+_lib = None
+
+
+def lib():
+    """Load libcsc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1903_00353_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.csc_build_features.restype = C.c_int
+    L.csc_build_features.argtypes = [P, C.c_int64, P, C.c_int64, C.POINTER(csc_grid), C.POINTER(csc_options), P,
+                                     C.POINTER(C.c_void_p)]
+    L.csc_features_info.restype = C.c_int
+    L.csc_features_info.argtypes = [P, C.POINTER(csc_feature_info)]
+    L.csc_scan_convert_workspace.restype = C.c_int
+    L.csc_scan_convert_workspace.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]
+    L.csc_scan_convert.restype = C.c_int
+    L.csc_scan_convert.argtypes = [P, P, C.c_size_t, P, P, P, P, P, P]
+    L.csc_sdf_backward.restype = C.c_int
+    L.csc_sdf_backward.argtypes = [P, P, P, P, C.c_int64, P, P, P]
+    L.csc_features_free.restype = None
+    L.csc_features_free.argtypes = [P]
+    L.csc_error_string.restype = C.c_char_p
+    L.csc_error_string.argtypes = [C.c_int]
+    L.csc_last_hip_error.restype = C.c_char_p
+    L.csc_last_hip_error.argtypes = []
+    L.csc_classify_edge.restype = C.c_int
+    L.csc_classify_edge.argtypes = [P, P, P, P]
+    L.csc_classify_vertex.restype = C.c_int
+    L.csc_classify_vertex.argtypes = [P, P, C.c_int32, C.POINTER(csc_options), P, P]
+    _lib = L
+    return L
+
+
+def _lib_error_string(code: int) -> str:
+    return lib().csc_error_string(code).decode()
+
+
+def csc_error_string(code: int) -> str:
+    return _lib_error_string(code)
+
+
+def make_grid(grid) -> csc_grid:
+    """csc_grid from any object with ``n``, ``h``, ``band`` (and optional ``origin``)."""
+    g = csc_grid()
+    o = getattr(grid, "origin", (0.0, 0.0, 0.0))
+    for k in range(3):
+        g.origin[k] = float(o[k])
+        g.n[k] = int(grid.n[k])
+    g.h = float(grid.h)
+    g.band_cells = float(grid.band)
+    return g
+
+
+def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0) -> csc_options:
+    return csc_options(float(eps_rel), int(ruff_mode), int(saddle_mode), int(force_both_sides))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise CscError(code, where)
+
+
+class Features:
+    """A built feature handle (``csc_features``). Keeps the mesh tensors alive."""
+
+    def __init__(self, handle: C.c_void_p, verts, tris, grid: csc_grid, options):
+        self.handle = handle
+        self.verts, self.tris, self.grid, self.options = verts, tris, grid, options
+
+    def info(self) -> dict:
+        inf = csc_feature_info()
+        _check(lib().csc_features_info(self.handle, C.byref(inf)), "csc_features_info")
+        return inf.as_dict()
+
+    def free(self):
+        if self.handle:
+            lib().csc_features_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _check_mesh(verts, tris):
+    import torch
+    if not (isinstance(verts, torch.Tensor) and isinstance(tris, torch.Tensor)):
+        raise TypeError("verts and tris must be torch tensors")
+    if verts.device.type != "cuda" or tris.device.type != "cuda":
+        raise ValueError("verts and tris must be device tensors")
+    if verts.dtype != torch.float32 or tris.dtype != torch.int32:
+        raise TypeError("verts must be float32 and tris int32")
+    if verts.dim() != 2 or verts.shape[1] != 3 or tris.dim() != 2 or tris.shape[1] != 3:
+        raise ValueError("verts must be [V,3] and tris [F,3]")
+    if not (verts.is_contiguous() and tris.is_contiguous()):
+        raise ValueError("verts and tris must be contiguous")
+
+
+def csc_build_features(verts, tris, grid, options=None, stream=None, reuse: Features | None = None) -> Features:
+    _check_mesh(verts, tris)
+    g = make_grid(grid)
+    opt = options if options is not None else make_options()
+    h = C.c_void_p(reuse.handle if reuse is not None and reuse.handle else None)
+    code = lib().csc_build_features(_ptr(verts), verts.shape[0], _ptr(tris), tris.shape[0], C.byref(g),
+                                    C.byref(opt), _stream(stream), C.byref(h))
+    if code != 0:
+        if reuse is not None:
+            reuse.verts, reuse.tris = verts, tris
+        raise CscError(code, "csc_build_features")
+    if reuse is not None:
+        reuse.handle, reuse.verts, reuse.tris, reuse.grid, reuse.options = h, verts, tris, g, opt
+        return reuse
+    return Features(h, verts, tris, g, opt)
+
+
+def csc_scan_convert_workspace(f: Features):
+    nbytes, mx = C.c_size_t(), C.c_int64()
+    _check(lib().csc_scan_convert_workspace(f.handle, C.byref(nbytes), C.byref(mx)), "csc_scan_convert_workspace")
+    return int(nbytes.value), int(mx.value)
+
+
+@dataclasses.dataclass
+class Band:
+    sdf: "object"      # float32 [M]
+    feat: "object"     # int32 [M]
+    cell: "object"     # int32 [M]
+    n_band: int
+
+
+def csc_scan_convert(f: Features, workspace=None, out=None, dense=None, stream=None, sync_count=True):
+    """Run the scan conversion. ``out`` = (sdf, feat, cell, n_band) preallocated
+    device tensors of max_band_cells entries (+ an int64 scalar) or None. Returns a
+    ``Band`` whose tensors are sliced to the band size (reading it synchronises)
+    unless ``sync_count`` is False (then full-length tensors and n_band = -1)."""
+    import torch
+    nbytes, mx = csc_scan_convert_workspace(f)
+    dev = f.verts.device
+    if workspace is None:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = (torch.empty(max(mx, 1), dtype=torch.float32, device=dev),
+               torch.empty(max(mx, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(mx, 1), dtype=torch.int32, device=dev),
+               torch.zeros(1, dtype=torch.int64, device=dev))
+    sdf, feat, cell, nb = out
+    code = lib().csc_scan_convert(f.handle, _ptr(workspace), workspace.numel(), _ptr(sdf), _ptr(feat), _ptr(cell),
+                                  _ptr(nb), _ptr(dense), _stream(stream))
+    _check(code, "csc_scan_convert")
+    if not sync_count:
+        return Band(sdf, feat, cell, -1)
+    m = int(nb.item())
+    return Band(sdf[:m], feat[:m], cell[:m], m)
+
+
+def csc_sdf_backward(f: Features, band: Band, grad_sdf, grad_verts=None, stream=None):
+    import torch
+    if grad_verts is None:
+        grad_verts = torch.zeros_like(f.verts)
+    n = band.n_band if band.n_band >= 0 else band.sdf.numel()
+    code = lib().csc_sdf_backward(f.handle, _ptr(band.sdf), _ptr(band.feat), _ptr(band.cell), int(n),
+                                  _ptr(grad_sdf.contiguous()), _ptr(grad_verts), _stream(stream))
+    _check(code, "csc_sdf_backward")
+    return grad_verts
+
+
+def csc_features_info(f: Features) -> dict:
+    return f.info()
+
+
+def csc_features_free(f: Features):
+    f.free()
+
+
+def csc_classify_edge(a, b, c1, c2) -> int:
+    arrs = [np.ascontiguousarray(x, dtype=np.float32) for x in (a, b, c1, c2)]
+    return int(lib().csc_classify_edge(*[x.ctypes.data_as(C.c_void_p) for x in arrs]))
+
+
+def csc_classify_vertex(v, ring, options=None):
+    """ring: [n][2][3] other corners of each incident triangle (counter-clockwise)."""
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    ring = np.ascontiguousarray(ring, dtype=np.float32).reshape(-1, 6)
+    ax = np.zeros(3)
+    ct = C.c_double()
+    opt = options if options is not None else make_options()
+    bits = lib().csc_classify_vertex(v.ctypes.data_as(C.c_void_p), ring.ctypes.data_as(C.c_void_p), ring.shape[0],
+                                     C.byref(opt), ax.ctypes.data_as(C.c_void_p), C.byref(ct))
+    return int(bits), ax, float(ct.value)
+
+
+def sdf(verts, tris, grid, options=None, dense=False):
+    """Narrow-band SDF of one mesh: returns (sdf, feat, cell[, dense]) device tensors."""
+    import torch
+    f = csc_build_features(verts, tris, grid, options)
+    d = None
+    if dense:
+        d = torch.empty(int(grid.n[2]) * int(grid.n[1]) * int(grid.n[0]), dtype=torch.float32, device=verts.device)
+    band = csc_scan_convert(f, dense=d)
+    out = (band.sdf.clone(), band.feat.clone(), band.cell.clone())
+    f.free()
+    return out + ((d.view(int(grid.n[2]), int(grid.n[1]), int(grid.n[0])),) if dense else ())
+
+
+def _autograd():
+    import torch
+
+    class CSCFunction(torch.autograd.Function):
+        """(verts, tris, grid) -> band SDF values; differentiable in verts only."""
+
+        @staticmethod
+        def forward(ctx, verts, tris, grid, options=None):
+            f = csc_build_features(verts.detach(), tris, grid, options)
+            band = csc_scan_convert(f)
+            ctx.f, ctx.band = f, band
+            ctx.mark_non_differentiable(band.feat, band.cell)
+            return band.sdf, band.feat, band.cell
+
+        @staticmethod
+        def backward(ctx, g_sdf, g_feat=None, g_cell=None):
+            gv = csc_sdf_backward(ctx.f, ctx.band, g_sdf.contiguous().float())
+            return gv, None, None, None
+
+    return CSCFunction
+
+
+def __getattr__(name):
+    if name == "CSCFunction":
+        cls = _autograd()
+        globals()["CSCFunction"] = cls
+        return cls
+    raise AttributeError(name)

@@ -1,0 +1,109 @@
+// Adjoint of the band values with respect to the vertex positions.
+//
+// With the closest feature of each band cell held fixed (the minimum over
+// features is attained there: envelope theorem), SDF(c) = s |c - q| with
+// q = sum_k w_k x_k on the feature, so dSDF/dx_k = -s w_k (c - q) / |c - q|.
+// Each band cell scatters grad_sdf(c) * dSDF/dx_k into its 1-3 vertices.
+#include "geometry.h"
+#include "internal.h"
+
+namespace csc {
+
+struct BwdArgs {
+  const float* V;
+  const int32_t* T;
+  const int4* edges;
+  const float* sdf;
+  const int32_t* feat;
+  const int32_t* cell;
+  const float* gsdf;
+  float* grad;
+  int64_t n, nf, ne, nv;
+  double o[3];
+  double h;
+  int nx, ny;
+};
+
+__device__ inline f3 relb(const float* V, int64_t i, d3 c) {
+  return tof(mkd((double)V[3 * i] - c.x, (double)V[3 * i + 1] - c.y, (double)V[3 * i + 2] - c.z));
+}
+
+__global__ __launch_bounds__(256) void k_backward(BwdArgs P) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const float gs = P.gsdf[i];
+  if (gs == 0.f) return;
+  const int32_t lin = P.cell[i], id = P.feat[i];
+  const int ci = lin % P.nx, cj = (lin / P.nx) % P.ny, ck = lin / (P.nx * P.ny);
+  const d3 c = mkd(P.o[0] + (ci + 0.5) * P.h, P.o[1] + (cj + 0.5) * P.h, P.o[2] + (ck + 0.5) * P.h);
+  const f3 zero = mk(0.f, 0.f, 0.f);
+  f3 q;
+  float w[3];
+  int64_t vid[3];
+  int m;
+  if (id < P.nf) {
+    for (int j = 0; j < 3; j++) vid[j] = P.T[3 * (int64_t)id + j];
+    closest_triangle(zero, relb(P.V, vid[0], c), relb(P.V, vid[1], c), relb(P.V, vid[2], c), q, w);
+    m = 3;
+  } else if (id < P.nf + P.ne) {
+    int4 E = P.edges[id - P.nf];
+    vid[0] = E.x;
+    vid[1] = E.y;
+    float t;
+    q = closest_segment(zero, relb(P.V, E.x, c), relb(P.V, E.y, c), t);
+    w[0] = 1.f - t;
+    w[1] = t;
+    m = 2;
+  } else {
+    vid[0] = id - P.nf - P.ne;
+    q = relb(P.V, vid[0], c);
+    w[0] = 1.f;
+    m = 1;
+  }
+  const float d = norm3(q);
+  if (!(d > 0.f)) return;
+  const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
+  // c - q = -q in this frame; g = s (c - q) / |c - q|
+  const f3 g = q * (-s / d);
+  for (int k = 0; k < m; k++) {
+    const float f = -gs * w[k];
+    if (f == 0.f) continue;
+    float* dst = P.grad + 3 * vid[k];
+    atomicAdd(dst, f * g.x);
+    atomicAdd(dst + 1, f * g.y);
+    atomicAdd(dst + 2, f * g.z);
+  }
+}
+
+}  // namespace csc
+
+using namespace csc;
+
+extern "C" int csc_sdf_backward(const csc_features* f, const float* sdf_d, const int32_t* feat_d,
+                                const int32_t* cell_d, int64_t n_band, const float* grad_sdf_d, float* grad_verts_d,
+                                void* stream) {
+  if (!f || !f->valid || n_band < 0 || !grad_verts_d) return CSC_INVALID_ARG;
+  if (n_band > 0 && (!sdf_d || !feat_d || !cell_d || !grad_sdf_d)) return CSC_INVALID_ARG;
+  if (n_band > f->n_bricks * BRICK_CELLS) return CSC_INVALID_ARG;
+  if (n_band == 0) return CSC_OK;
+  BwdArgs A;
+  A.V = f->verts;
+  A.T = f->tris;
+  A.edges = f->edges;
+  A.sdf = sdf_d;
+  A.feat = feat_d;
+  A.cell = cell_d;
+  A.gsdf = grad_sdf_d;
+  A.grad = grad_verts_d;
+  A.n = n_band;
+  A.nf = f->nf;
+  A.ne = f->ne;
+  A.nv = f->nv;
+  for (int k = 0; k < 3; k++) A.o[k] = f->grid.origin[k];
+  A.h = f->grid.h;
+  A.nx = f->grid.n[0];
+  A.ny = f->grid.n[1];
+  k_backward<<<grid_1d(n_band, 256), 256, 0, (hipStream_t)stream>>>(A);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CSC_OK : fail_hip(e);
+}

@@ -1,0 +1,225 @@
+"""Device path against the CPU oracle (agreement rules in tests/parity.py).
+Every call goes through the C ABI of libcsc.so via the Python binding."""
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+from meshgen import Grid
+from parity import assert_parity, compare
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1903_00353_amd as P  # noqa: E402
+
+
+def run_device(v, f, grid, options=None):
+    verts = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    tris = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    feats = P.csc_build_features(verts, tris, grid, options)
+    band = P.csc_scan_convert(feats)
+    torch.cuda.synchronize()
+    return feats, band
+
+
+def to_np(band):
+    return band.cell.cpu().numpy(), band.sdf.cpu().numpy(), band.feat.cpu().numpy()
+
+
+def check(v, f, grid, options=None, exact=False, k_range=None):
+    print(f"[case] F={f.shape[0]} n={grid.n} h={grid.h} band={grid.band} k_range={k_range}", flush=True)
+    om = oracle.OracleMesh(v, f)
+    o = om.band(grid) if k_range is None else om.band(grid, *k_range)
+    feats, band = run_device(v, f, grid, options)
+    cell, sdf, feat = to_np(band)
+    rep = compare(om, grid, o, cell, sdf, feat, k_range=k_range, exact_membership=exact)
+    print(rep, feats.info(), flush=True)
+    return rep, feats, band, om, o
+
+
+def test_cube_exact():
+    v, f = meshgen.cube()
+    g = Grid.unit(64, 3)
+    rep, feats, band, om, o = check(v, f, g, exact=True)
+    assert_parity(rep, exact_membership=True)
+    assert band.n_band == 36832
+    inf = feats.info()
+    assert (inf["n_faces"], inf["n_edges"], inf["n_vertices"]) == (12, 18, 8)
+    assert (inf["edges_convex"], inf["edges_concave"], inf["edges_flat"]) == (12, 0, 6)
+    assert inf["vertices_convex"] == 8 and inf["vertices_saddle"] == 0
+    assert inf["n_edge_polyhedra"] == 12 and inf["n_vertex_polyhedra"] == 8
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_config_parity(configs, k):
+    name, meshes, grids = configs(k)
+    v, f = meshes[0]
+    rep, feats, band, om, o = check(v, f, grids[0])
+    assert_parity(rep)
+
+
+def test_large_sphere_sampled_planes(configs):
+    """1024^3, 5.2M triangles: every cell of three 4-plane slabs against the oracle."""
+    name, meshes, grids = configs(5)
+    v, f = meshes[0]
+    g = grids[0]
+    om = oracle.OracleMesh(v, f)
+    feats, band = run_device(v, f, g)
+    cell, sdf, feat = to_np(band)
+    for k0 in (200, 512, 830):
+        o = om.band(g, k0, k0 + 4)
+        rep = compare(om, g, o, cell, sdf, feat, k_range=(k0, k0 + 4))
+        print(k0, rep, flush=True)
+        assert rep["n_oracle"] > 1000
+        assert_parity(rep)
+
+
+def test_batch_meshes_individually(configs):
+    """Meshes of the 64-mesh batch (non-dyadic grids), one of each kind, one at a time."""
+    name, meshes, grids = configs(4)
+    for m in (0, 1, 2, 31, 61):
+        rep, *_ = check(*meshes[m], grids[m])
+        assert_parity(rep)
+
+
+def test_ragged_offset_grid():
+    """Non-cubic grid, non-dyadic h, offset origin, mesh partly outside the grid."""
+    v, f = meshgen.icosphere(3, 0.3, 2e-3, seed=9)
+    g = Grid(n=(37, 50, 29), h=1.0 / 41.0, band=2.5, origin=(0.05, -0.1, 0.12))
+    rep, *_ = check(v, f, g)
+    assert rep["n_oracle"] > 100
+    assert_parity(rep)
+
+
+def test_empty_and_tiny_grids():
+    v, f = meshgen.icosphere(2, 0.3)
+    g = Grid(n=(16, 16, 16), h=1 / 64, band=3, origin=(5.0, 5.0, 5.0))
+    feats, band = run_device(v, f, g)
+    assert band.n_band == 0
+    g1 = Grid(n=(1, 1, 1), h=0.1, band=3, origin=(0.75, 0.45, 0.45))  # one cell near the sphere
+    rep, *_ = check(v, f, g1)
+    assert_parity(rep)
+    assert rep["n_oracle"] == 1
+
+
+def test_deterministic(configs):
+    name, meshes, grids = configs(2)
+    v, f = meshes[0]
+    a = to_np(run_device(v, f, grids[0])[1])
+    b = to_np(run_device(v, f, grids[0])[1])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_dense_output_matches_band():
+    v, f = meshgen.cube()
+    g = Grid.unit(64, 3)
+    verts, tris = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    sdf, feat, cell, dense = P.sdf(verts, tris, g, dense=True)
+    d = dense.cpu().numpy().ravel()
+    c = cell.cpu().numpy()
+    assert np.array_equal(d[c], sdf.cpu().numpy())
+    mask = np.ones(d.size, bool)
+    mask[c] = False
+    assert np.all(np.isinf(d[mask]) & (d[mask] > 0))
+
+
+def test_saddle_ablation_leaves_holes(configs):
+    """Without saddle extrusions (Section 3.2; the paper's rabbit-ear failure) the noisy
+    torus is not covered: cells go missing or get values from farther features."""
+    name, meshes, grids = configs(3)
+    v, f = meshes[0]
+    rep, feats, *_ = check(v, f, grids[0], options=P.make_options(saddle_mode=2))
+    assert feats.info()["vertices_saddle"] > 0
+    assert rep["missing"] > 0 or rep["max_err_d"] > 1e-5
+
+
+def _bad(kind):
+    v, f = meshgen.cube()
+    v, f = v.copy(), f.copy()
+    if kind == "open":
+        f = f[2:]
+    elif kind == "flipped":
+        f[0] = f[0, [0, 2, 1]]
+    elif kind == "index":
+        f[3, 1] = 99
+    elif kind == "repeat":
+        f[3, 1] = f[3, 0]
+    elif kind == "nan":
+        v[5, 2] = np.nan
+    elif kind == "degenerate":
+        a, c = f[0, 0], f[0, 2]          # move corner 1 of face 0 onto the midpoint of corners 0 and 2
+        v[f[0, 1]] = (v[a] + v[c]) / 2
+    return v, f
+
+
+@pytest.mark.parametrize("kind,code", [("open", 2), ("flipped", 3), ("index", 1), ("repeat", 1), ("nan", 1),
+                                       ("degenerate", 4)])
+def test_invalid_surfaces_are_rejected(kind, code):
+    v, f = _bad(kind)
+    verts, tris = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    with pytest.raises(P.CscError) as ei:
+        P.csc_build_features(verts, tris, Grid.unit(32, 3))
+    assert ei.value.code == code
+
+
+def test_backward_matches_oracle_gradient(configs):
+    name, meshes, grids = configs(2)
+    v, f = meshes[0]
+    g = grids[0]
+    feats, band = run_device(v, f, g)
+    cell, sdf, feat = to_np(band)
+    gs = torch.from_numpy(2.0 * sdf).cuda()  # d(sum SDF^2)/dSDF
+    gv = P.csc_sdf_backward(feats, band, gs).cpu().numpy().astype(np.float64)
+    om = oracle.OracleMesh(v, f)
+    ref = om.grad(g, cell, feat, np.sign(sdf), 2.0 * sdf.astype(np.float64))
+    rel = np.linalg.norm(gv - ref) / np.linalg.norm(ref)
+    print("rel l2", rel, "max abs", np.abs(gv - ref).max() / np.abs(ref).max(), flush=True)
+    assert rel <= 1e-4
+    assert np.abs(gv - ref).max() <= 1e-3 * np.abs(ref).max()
+
+
+def test_backward_matches_finite_differences():
+    """Device gradient of L = sum SDF^2 against FP64 central differences of the oracle
+    distance over the device band set (cells at a kink excluded from both sides)."""
+    v, f = meshgen.icosphere(3, 0.3, 3e-3, seed=5)
+    g = Grid.unit(48, 3)
+    verts, tris = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    feats = P.csc_build_features(verts, tris, g)
+    band = P.csc_scan_convert(feats)
+    cell, sdf, feat = to_np(band)
+    om = oracle.OracleMesh(v, f)
+    d0, _ = om.cells_dist(g, cell)
+    rng = np.random.default_rng(17)
+    delta = 1e-3 * g.h
+    worst = 0.0
+    for s in range(32):
+        vi, ax = int(rng.integers(om.nv)), int(rng.integers(3))
+        Vp, Vm = om.V.copy(), om.V.copy()
+        Vp[vi, ax] += delta
+        Vm[vi, ax] -= delta
+        dp, _ = om.cells_dist(g, cell, V64=Vp)
+        dm, _ = om.cells_dist(g, cell, V64=Vm)
+        kink = np.abs(dp + dm - 2 * d0) > 1e-3 * delta
+        up = np.where(kink, 0.0, 2.0 * sdf).astype(np.float32)
+        gv = P.csc_sdf_backward(feats, band, torch.from_numpy(up).cuda()).cpu().numpy()
+        fd = np.sum(((dp ** 2 - dm ** 2) / (2 * delta))[~kink])
+        err = abs(gv[vi, ax] - fd)
+        worst = max(worst, err / (1e-3 * abs(fd) + 1e-5 * 1.0))
+        assert err <= 1e-3 * abs(fd) + 1e-5 * max(1.0, abs(fd)), (vi, ax, gv[vi, ax], fd)
+    print("worst normalised fd error", worst)
+
+
+def test_autograd_function():
+    v, f = meshgen.icosphere(3, 0.3, 3e-3, seed=5)
+    g = Grid.unit(48, 3)
+    verts = torch.from_numpy(v).cuda().requires_grad_(True)
+    tris = torch.from_numpy(f).cuda()
+    sdf, feat, cell = P.CSCFunction.apply(verts, tris, g)
+    loss = (sdf.double() ** 2).sum()
+    loss.backward()
+    feats = P.csc_build_features(verts.detach(), tris, g)
+    band = P.csc_scan_convert(feats)
+    ref = P.csc_sdf_backward(feats, band, 2.0 * band.sdf)
+    assert torch.allclose(verts.grad, ref, rtol=1e-5, atol=1e-6 * ref.abs().max().item())

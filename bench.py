@@ -1,0 +1,228 @@
+#!/usr/bin/env python
+"""Throughput of the CSC narrow-band SDF path on one MI355X.
+
+One step = the whole hot path over one synthetic mesh already resident in HBM:
+feature build (adjacency, classes, polyhedron lists, bricks), scan conversion of
+every polyhedron with the packed atomicMin, sign pass and band compaction, then
+the adjoint of loss = sum of SDF^2 over the band into the vertex gradient.
+value = band cells / second of that forward+backward step.
+
+Prints one JSON line (rank 0). See --help for the workloads.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "narrow-band cells/sec (fwd, fwd+bwd), batched vs per-mesh, at 1e-5·h error"
+WORKLOADS = {
+    # name: (config number, description)
+    "sh_sphere9_1024": (5, "displaced sphere: icosphere L9 (5,242,880 triangles), SH degree 16 at 5%, "
+                           "1024^3 grid, band 3 cells, fwd+bwd of sum SDF^2, per-mesh"),
+    "noisy_torus_512": (3, "noisy torus: 360,000 triangles, tube-normal noise U(+-0.01), 512^3 grid, band 3, fwd+bwd"),
+    "icosphere5_jitter_256": (2, "jittered icosphere L5: 20,480 triangles, 256^3 grid, band 4, fwd+bwd"),
+}
+PEAK_HBM_GBS = 8000.0
+SINGLE_KERNEL_STAGES = ["init_keys", "scan_faces", "scan_edges", "scan_vertices", "sign", "backward"]
+KERNEL_SYMBOL = {"init_keys": "k_fill_u64", "scan_faces": "k_scan<0>", "scan_edges": "k_scan<1>",
+                 "scan_vertices": "k_scan<2>", "sign": "k_sign", "backward": "k_backward"}
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for name in ("scanconv.hip", "geometry.h", "backward.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1903_00353_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel: str):
+    """Measured HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_sha") != kernel_source_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
+    """Bytes the method itself must move per launch of each single-kernel stage."""
+    F, E = info["n_faces"], info["n_edges"]
+    if stage == "init_keys":
+        return 8 * info["n_bricks"] * 512
+    if stage == "scan_faces":   # triangles, vertices, face normals, one u64 per atomic
+        return 12 * F + 12 * nv + 12 * F + 8 * atomics[0]
+    if stage == "scan_edges":   # edge records, vertices, normals, atomics
+        return 16 * info["n_edge_polyhedra"] + 12 * nv + 12 * F + 8 * atomics[1]
+    if stage == "scan_vertices":
+        return 16 * info["n_vertex_polyhedra"] + 12 * nv + 8 * atomics[2]
+    if stage == "sign":         # one key read and (sdf, id, cell) written per band cell
+        return 20 * band_cells
+    if stage == "backward":     # (sdf, id, cell, dL/dSDF) read, 3 floats added per weighted vertex
+        return 16 * band_cells + 12 * vert_refs
+    raise KeyError(stage)
+
+
+def cpu_baseline(v, f, grid, budget_s=15.0):
+    """The oracle as it stands on the host cores, on z-slabs through the middle of
+    the grid until about budget_s seconds of band computation have been spent."""
+    import oracle
+    om = oracle.OracleMesh(v, f)
+    n2 = int(grid.n[2])
+    step = 16
+    mid = n2 // 2
+    cells, spent, planes, threads, i = 0, 0.0, 0, 1, 0
+    while spent < budget_s and planes < n2:
+        off = ((i + 1) // 2) * step * (1 if i % 2 else -1)  # slabs outward from the middle: 0, +16, -16, ...
+        k0 = max(0, min(n2 - step, mid + off))
+        t0 = time.perf_counter()
+        b = om.band(grid, k0, k0 + step)
+        spent += time.perf_counter() - t0
+        cells += int(((b["flags"] & oracle.FLAG_IN_BAND) > 0).sum())
+        threads = b["threads"]
+        planes += step
+        i += 1
+    return {"value": cells / spent, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"{planes} z-planes of {n2} through the middle of the grid ({cells} band cells, "
+                      f"{spent:.1f} s); FP64 exact distance with bounding-box cull, pseudonormal sign; "
+                      f"one-time edge table and normals excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sh_sphere9_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this implementation runs on one GPU; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
+                          "launches": 3}))
+        return
+
+    import meshgen
+    import paper_1903_00353_amd as P
+
+    cfg, desc = WORKLOADS[args.workload]
+    name, meshes, grids = meshgen.make_config(cfg)
+    v, f = meshes[0]
+    g = grids[0]
+    dev = torch.device("cuda:0")
+    verts = torch.from_numpy(v).to(dev)
+    tris = torch.from_numpy(f).to(dev)
+    feats = P.csc_build_features(verts, tris, g)
+    info = feats.info()
+    nbytes, mx = P.csc_scan_convert_workspace(feats)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = (torch.empty(mx, dtype=torch.float32, device=dev), torch.empty(mx, dtype=torch.int32, device=dev),
+           torch.empty(mx, dtype=torch.int32, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+    gs = torch.empty(mx, dtype=torch.float32, device=dev)
+    gv = torch.zeros_like(verts)
+
+    def forward():
+        P.csc_build_features(verts, tris, g, reuse=feats)
+        return P.csc_scan_convert(feats, ws, out, sync_count=False)
+
+    def step():
+        band = forward()
+        torch.mul(out[0], 2.0, out=gs)
+        gv.zero_()
+        P.csc_sdf_backward(feats, band, gs, gv, n_band_d=out[3])
+
+    # diagnostics (untimed): atomics per scan kernel, band size and vertex references
+    atomics = P.csc_scan_convert_count(feats, ws)
+    forward()
+    torch.cuda.synchronize()
+    M = int(out[3].item())
+    feat_ids = out[1][:M].cpu().numpy()
+    F, E = info["n_faces"], info["n_edges"]
+    vert_refs = int(3 * (feat_ids < F).sum() + 2 * ((feat_ids >= F) & (feat_ids < F + E)).sum()
+                    + (feat_ids >= F + E).sum())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.csc_timing_reset()
+    P.csc_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.csc_timing_enable(False)
+    stages = P.csc_timing_read()
+    # forward-only throughput (untimed by events)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        forward()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_fwd = (t3 - t2) * 1e3 / args.steps
+    avg = {k: (ms / c if c else 0.0) for k, (ms, c) in stages.items()}
+    dom = max(SINGLE_KERNEL_STAGES, key=lambda k: avg[k])
+    alg = algorithmic_bytes(dom, info, atomics, M, vert_refs, verts.shape[0])
+    achieved = alg / (avg[dom] * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, dom)
+    res = {
+        "metric": METRIC,
+        "value": M / (ms_step * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "faces": F, "vertices": int(verts.shape[0]),
+                   "grid": list(g.n), "band_cells": g.band, "band_size": M, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "algorithmic_bytes": alg, "avg_ms": avg[dom]},
+        "fwd": {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd},
+        "stages_ms": {k: round(x, 4) for k, x in avg.items()},
+        "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2]},
+        "features": info,
+        "kernel_source_sha": kernel_source_sha(),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(v, f, g, args.cpu_budget)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

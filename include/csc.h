@@ -136,17 +136,43 @@ int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, 
 
 /*
  * Adjoint of the band values with respect to the vertex positions. For each of
- * the n_band band cells c (sdf_d, feat_d, cell_d as written by csc_scan_convert):
+ * the band cells c (sdf_d, feat_d, cell_d as written by csc_scan_convert):
  * with q the closest point of the cell centre on feature feat_d[c] and w_k the
  * barycentric weights of q on the feature's vertices, SDF = s |c - q| and
  * dSDF/dx_k = -s w_k (c - q) / |c - q| (the closest feature is held fixed);
  * grad_verts_d[k] += grad_sdf_d[c] * dSDF/dx_k. Cells at zero distance add
  * nothing. grad_verts_d: float32 [nv][3], accumulated (not cleared); the sum
  * order of the float atomics varies from run to run.
+ * n_band: number of band cells, or (with n_band_d) an upper bound on it.
+ * n_band_d: NULL, or the device int64 written by csc_scan_convert; the count is
+ * then read on the device, so no host synchronisation is needed in between.
  * Errors: INVALID_ARG, HIP_ERROR.
  */
 int csc_sdf_backward(const csc_features* f, const float* sdf_d, const int32_t* feat_d, const int32_t* cell_d,
-                     int64_t n_band, const float* grad_sdf_d, float* grad_verts_d, void* stream);
+                     int64_t n_band, const int64_t* n_band_d, const float* grad_sdf_d, float* grad_verts_d,
+                     void* stream);
+
+/*
+ * Diagnostics: run only the key initialisation and the three scan launches and
+ * return the number of packed atomicMin operations each issued (counts[0] faces,
+ * counts[1] edges, counts[2] vertices). Synchronises `stream`. The band store in
+ * the workspace is left as after a scan, but no band list is written.
+ */
+int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_bytes, int64_t counts[3],
+                           void* stream);
+
+/*
+ * Per-stage timing with HIP events recorded on the stream of each call (stages:
+ * 0 build_features, 1 init_keys, 2 scan_faces, 3 scan_edges, 4 scan_vertices,
+ * 5 brick_count, 6 sign, 7 backward). While enabled, every call records a pair
+ * of events around each stage; csc_timing_read waits for the recorded events and
+ * returns the accumulated milliseconds and call counts of the first n stages.
+ * Process-wide; not meant for concurrent callers.
+ */
+int csc_timing_enable(int on);
+int csc_timing_reset(void);
+int csc_timing_read(double* ms, int64_t* calls, int32_t n);
+const char* csc_timing_stage_name(int32_t stage);
 
 /* Release a handle and its device memory (waits for nothing; the caller must
  * make sure no queued work still uses it). NULL is accepted. */

@@ -59,7 +59,9 @@ class csc_feature_info(C.Structure):
 
 EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspace", "csc_scan_convert",
            "csc_sdf_backward", "csc_features_free", "csc_error_string", "csc_last_hip_error",
-           "csc_classify_edge", "csc_classify_vertex"]
+           "csc_classify_edge", "csc_classify_vertex", "csc_scan_convert_count", "csc_timing_enable",
+           "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name"]
+N_STAGES = 8
 
 _lib = None
 
@@ -83,7 +85,17 @@ def lib():
     L.csc_scan_convert.restype = C.c_int
     L.csc_scan_convert.argtypes = [P, P, C.c_size_t, P, P, P, P, P, P]
     L.csc_sdf_backward.restype = C.c_int
-    L.csc_sdf_backward.argtypes = [P, P, P, P, C.c_int64, P, P, P]
+    L.csc_sdf_backward.argtypes = [P, P, P, P, C.c_int64, P, P, P, P]
+    L.csc_scan_convert_count.restype = C.c_int
+    L.csc_scan_convert_count.argtypes = [P, P, C.c_size_t, P, P]
+    L.csc_timing_enable.restype = C.c_int
+    L.csc_timing_enable.argtypes = [C.c_int]
+    L.csc_timing_reset.restype = C.c_int
+    L.csc_timing_reset.argtypes = []
+    L.csc_timing_read.restype = C.c_int
+    L.csc_timing_read.argtypes = [P, P, C.c_int32]
+    L.csc_timing_stage_name.restype = C.c_char_p
+    L.csc_timing_stage_name.argtypes = [C.c_int32]
     L.csc_features_free.restype = None
     L.csc_features_free.argtypes = [P]
     L.csc_error_string.restype = C.c_char_p
@@ -179,7 +191,8 @@ def csc_build_features(verts, tris, grid, options=None, stream=None, reuse: Feat
     _check_mesh(verts, tris)
     g = make_grid(grid)
     opt = options if options is not None else make_options()
-    h = C.c_void_p(reuse.handle if reuse is not None and reuse.handle else None)
+    prev = reuse.handle if reuse is not None else None
+    h = C.c_void_p(prev.value if isinstance(prev, C.c_void_p) else prev)
     code = lib().csc_build_features(_ptr(verts), verts.shape[0], _ptr(tris), tris.shape[0], C.byref(g),
                                     C.byref(opt), _stream(stream), C.byref(h))
     if code != 0:
@@ -231,15 +244,50 @@ def csc_scan_convert(f: Features, workspace=None, out=None, dense=None, stream=N
     return Band(sdf[:m], feat[:m], cell[:m], m)
 
 
-def csc_sdf_backward(f: Features, band: Band, grad_sdf, grad_verts=None, stream=None):
+def csc_sdf_backward(f: Features, band: Band, grad_sdf, grad_verts=None, stream=None, n_band_d=None):
+    """Accumulate d(sum grad_sdf * SDF)/d(verts) into grad_verts (new zeros if None).
+    With ``n_band_d`` (the device count from csc_scan_convert) the band size is read
+    on the device and the band tensors may be the full-length outputs."""
     import torch
     if grad_verts is None:
         grad_verts = torch.zeros_like(f.verts)
-    n = band.n_band if band.n_band >= 0 else band.sdf.numel()
+    n = band.n_band if (band.n_band >= 0 and n_band_d is None) else band.sdf.numel()
     code = lib().csc_sdf_backward(f.handle, _ptr(band.sdf), _ptr(band.feat), _ptr(band.cell), int(n),
-                                  _ptr(grad_sdf.contiguous()), _ptr(grad_verts), _stream(stream))
+                                  _ptr(n_band_d), _ptr(grad_sdf.contiguous()), _ptr(grad_verts), _stream(stream))
     _check(code, "csc_sdf_backward")
     return grad_verts
+
+
+def csc_scan_convert_count(f: Features, workspace=None, stream=None):
+    """Atomics issued by the face, edge and vertex scans (diagnostic; synchronises)."""
+    import torch
+    nbytes, _ = csc_scan_convert_workspace(f)
+    if workspace is None:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f.verts.device)
+    counts = (C.c_int64 * 3)()
+    _check(lib().csc_scan_convert_count(f.handle, _ptr(workspace), workspace.numel(), counts, _stream(stream)),
+           "csc_scan_convert_count")
+    return [int(x) for x in counts]
+
+
+def csc_timing_enable(on: bool = True):
+    _check(lib().csc_timing_enable(1 if on else 0), "csc_timing_enable")
+
+
+def csc_timing_reset():
+    _check(lib().csc_timing_reset(), "csc_timing_reset")
+
+
+def csc_timing_read() -> dict:
+    """{stage name: (total ms, calls)} accumulated since the last reset."""
+    ms = (C.c_double * N_STAGES)()
+    calls = (C.c_int64 * N_STAGES)()
+    _check(lib().csc_timing_read(ms, calls, N_STAGES), "csc_timing_read")
+    return {lib().csc_timing_stage_name(i).decode(): (float(ms[i]), int(calls[i])) for i in range(N_STAGES)}
+
+
+def csc_timing_stage_name(i: int) -> str:
+    return lib().csc_timing_stage_name(i).decode()
 
 
 def csc_features_info(f: Features) -> dict:

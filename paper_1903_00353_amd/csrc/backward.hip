@@ -17,6 +17,7 @@ struct BwdArgs {
   const int32_t* feat;
   const int32_t* cell;
   const float* gsdf;
+  const int64_t* n_dev;  // optional device-side band size
   float* grad;
   int64_t n, nf, ne, nv;
   double o[3];
@@ -28,50 +29,82 @@ __device__ inline f3 relb(const float* V, int64_t i, d3 c) {
   return tof(mkd((double)V[3 * i] - c.x, (double)V[3 * i + 1] - c.y, (double)V[3 * i + 2] - c.z));
 }
 
-__global__ __launch_bounds__(256) void k_backward(BwdArgs P) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
-  const float gs = P.gsdf[i];
-  if (gs == 0.f) return;
-  const int32_t lin = P.cell[i], id = P.feat[i];
-  const int ci = lin % P.nx, cj = (lin / P.nx) % P.ny, ck = lin / (P.nx * P.ny);
-  const d3 c = mkd(P.o[0] + (ci + 0.5) * P.h, P.o[1] + (cj + 0.5) * P.h, P.o[2] + (ck + 0.5) * P.h);
-  const f3 zero = mk(0.f, 0.f, 0.f);
-  f3 q;
-  float w[3];
-  int64_t vid[3];
-  int m;
-  if (id < P.nf) {
-    for (int j = 0; j < 3; j++) vid[j] = P.T[3 * (int64_t)id + j];
-    closest_triangle(zero, relb(P.V, vid[0], c), relb(P.V, vid[1], c), relb(P.V, vid[2], c), q, w);
-    m = 3;
-  } else if (id < P.nf + P.ne) {
-    int4 E = P.edges[id - P.nf];
-    vid[0] = E.x;
-    vid[1] = E.y;
-    float t;
-    q = closest_segment(zero, relb(P.V, E.x, c), relb(P.V, E.y, c), t);
-    w[0] = 1.f - t;
-    w[1] = t;
-    m = 2;
-  } else {
-    vid[0] = id - P.nf - P.ne;
-    q = relb(P.V, vid[0], c);
-    w[0] = 1.f;
-    m = 1;
+constexpr int BW_THREADS = 256;
+constexpr int BW_SLOTS = 1024;  // > 3 * BW_THREADS insertions: probing always ends
+
+// One band cell per thread. Each block first sums its cells' contributions per
+// vertex in an LDS hash table (band cells are ordered by brick, so a block's cells
+// share most of their vertices), then adds one value per vertex and axis globally.
+__global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
+  __shared__ int s_key[BW_SLOTS];
+  __shared__ float s_acc[3][BW_SLOTS];
+  for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
+    s_key[k] = -1;
+    s_acc[0][k] = 0.f;
+    s_acc[1][k] = 0.f;
+    s_acc[2][k] = 0.f;
   }
-  const float d = norm3(q);
-  if (!(d > 0.f)) return;
-  const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
-  // c - q = -q in this frame; g = s (c - q) / |c - q|
-  const f3 g = q * (-s / d);
-  for (int k = 0; k < m; k++) {
-    const float f = -gs * w[k];
-    if (f == 0.f) continue;
-    float* dst = P.grad + 3 * vid[k];
-    atomicAdd(dst, f * g.x);
-    atomicAdd(dst + 1, f * g.y);
-    atomicAdd(dst + 2, f * g.z);
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)BW_THREADS + threadIdx.x;
+  int64_t lim = P.n;
+  if (P.n_dev && *P.n_dev < lim) lim = *P.n_dev;
+  const float gs = i < lim ? P.gsdf[i] : 0.f;
+  if (gs != 0.f) {
+    const int32_t lin = P.cell[i], id = P.feat[i];
+    const int ci = lin % P.nx, cj = (lin / P.nx) % P.ny, ck = lin / (P.nx * P.ny);
+    const d3 c = mkd(P.o[0] + (ci + 0.5) * P.h, P.o[1] + (cj + 0.5) * P.h, P.o[2] + (ck + 0.5) * P.h);
+    const f3 zero = mk(0.f, 0.f, 0.f);
+    f3 q;
+    float w[3] = {0.f, 0.f, 0.f};
+    int32_t vid[3] = {0, 0, 0};
+    int m;
+    if (id < P.nf) {
+      for (int j = 0; j < 3; j++) vid[j] = P.T[3 * (int64_t)id + j];
+      closest_triangle(zero, relb(P.V, vid[0], c), relb(P.V, vid[1], c), relb(P.V, vid[2], c), q, w);
+      m = 3;
+    } else if (id < P.nf + P.ne) {
+      int4 E = P.edges[id - P.nf];
+      vid[0] = E.x;
+      vid[1] = E.y;
+      float t;
+      q = closest_segment(zero, relb(P.V, E.x, c), relb(P.V, E.y, c), t);
+      w[0] = 1.f - t;
+      w[1] = t;
+      m = 2;
+    } else {
+      vid[0] = (int32_t)(id - P.nf - P.ne);
+      q = relb(P.V, vid[0], c);
+      w[0] = 1.f;
+      m = 1;
+    }
+    const float d = norm3(q);
+    if (d > 0.f) {
+      const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
+      // c - q = -q in this frame; g = s (c - q) / |c - q|
+      const f3 g = q * (-s / d);
+      for (int k = 0; k < m; k++) {
+        const float f = -gs * w[k];
+        if (f == 0.f) continue;
+        unsigned h = ((unsigned)vid[k] * 2654435761u) >> 22;
+        while (true) {
+          int old = atomicCAS(&s_key[h], -1, vid[k]);
+          if (old == -1 || old == vid[k]) break;
+          h = (h + 1) & (BW_SLOTS - 1);
+        }
+        atomicAdd(&s_acc[0][h], f * g.x);
+        atomicAdd(&s_acc[1][h], f * g.y);
+        atomicAdd(&s_acc[2][h], f * g.z);
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
+    const int v = s_key[k];
+    if (v < 0) continue;
+    float* dst = P.grad + 3 * (int64_t)v;
+    atomicAdd(dst, s_acc[0][k]);
+    atomicAdd(dst + 1, s_acc[1][k]);
+    atomicAdd(dst + 2, s_acc[2][k]);
   }
 }
 
@@ -80,8 +113,8 @@ __global__ __launch_bounds__(256) void k_backward(BwdArgs P) {
 using namespace csc;
 
 extern "C" int csc_sdf_backward(const csc_features* f, const float* sdf_d, const int32_t* feat_d,
-                                const int32_t* cell_d, int64_t n_band, const float* grad_sdf_d, float* grad_verts_d,
-                                void* stream) {
+                                const int32_t* cell_d, int64_t n_band, const int64_t* n_band_d,
+                                const float* grad_sdf_d, float* grad_verts_d, void* stream) {
   if (!f || !f->valid || n_band < 0 || !grad_verts_d) return CSC_INVALID_ARG;
   if (n_band > 0 && (!sdf_d || !feat_d || !cell_d || !grad_sdf_d)) return CSC_INVALID_ARG;
   if (n_band > f->n_bricks * BRICK_CELLS) return CSC_INVALID_ARG;
@@ -94,6 +127,7 @@ extern "C" int csc_sdf_backward(const csc_features* f, const float* sdf_d, const
   A.feat = feat_d;
   A.cell = cell_d;
   A.gsdf = grad_sdf_d;
+  A.n_dev = n_band_d;
   A.grad = grad_verts_d;
   A.n = n_band;
   A.nf = f->nf;
@@ -103,7 +137,8 @@ extern "C" int csc_sdf_backward(const csc_features* f, const float* sdf_d, const
   A.h = f->grid.h;
   A.nx = f->grid.n[0];
   A.ny = f->grid.n[1];
-  k_backward<<<grid_1d(n_band, 256), 256, 0, (hipStream_t)stream>>>(A);
+  StageTimer t(TS_BACKWARD, (hipStream_t)stream);
+  k_backward<<<grid_1d(n_band, BW_THREADS), BW_THREADS, 0, (hipStream_t)stream>>>(A);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);
 }

@@ -17,12 +17,10 @@ __device__ inline d3 vload_d(const float* V, int64_t i) {
 }
 __device__ inline f3 vload_f(const float* V, int64_t i) { return mk(V[3 * i], V[3 * i + 1], V[3 * i + 2]); }
 
-// wave-aggregated counter increment (one atomic per wave)
-__device__ inline void count_if(bool c, int64_t* ctr) {
-  unsigned long long m = __ballot(c);
-  if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1 && m)
-    atomicAdd((unsigned long long*)ctr, (unsigned long long)__popcll(m));
-}
+// corner c = 3f + j (32-bit: 3F < 2^31): vertex after / before it in its face, and
+// the half-edge entering it (prev -> corner)
+__device__ inline int32_t next_corner(int32_t c) { int32_t j = c % 3; return c - j + (j == 2 ? 0 : j + 1); }
+__device__ inline int32_t prev_corner(int32_t c) { int32_t j = c % 3; return c - j + (j == 0 ? 2 : j - 1); }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -35,30 +33,64 @@ __global__ void k_check_verts(const float* __restrict__ V, int64_t nv, uint32_t*
   if (!isfinite(V[i])) atomicOr(err, ERR_NONFINITE);
 }
 
-// index range / repeated-corner checks and per-vertex corner counts
-__global__ void k_count_corners(const int32_t* __restrict__ T, int64_t nf, int64_t nv, int32_t* cnt, uint32_t* err) {
-  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (f >= nf) return;
-  int32_t a = T[3 * f], b = T[3 * f + 1], c = T[3 * f + 2];
-  if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) { atomicOr(err, ERR_INDEX); return; }
-  if (a == b || b == c || a == c) { atomicOr(err, ERR_REPEAT); return; }
-  atomicAdd(&cnt[a], 1);
-  atomicAdd(&cnt[b], 1);
-  atomicAdd(&cnt[c], 1);
-}
+constexpr int CC_THREADS = 256;
+constexpr int CC_SLOTS = 1024;  // > 3 * CC_THREADS insertions
 
-__global__ void k_scatter_faces(const int32_t* __restrict__ T, int64_t nf, const int32_t* __restrict__ off,
-                                int32_t* cursor, int32_t* vf) {
-  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (f >= nf) return;
-  for (int j = 0; j < 3; j++) {
-    int32_t v = T[3 * f + j];
-    int32_t p = atomicAdd(&cursor[v], 1);
-    vf[off[v] + p] = (int32_t)f;
+// Index range / repeated-corner checks and per-vertex corner counts. A block first
+// counts its corners per vertex in an LDS hash table, then reserves one range per
+// vertex with a single global atomic; each corner gets base + its rank in the block.
+__global__ __launch_bounds__(CC_THREADS) void k_count_corners(const int32_t* __restrict__ T, int64_t nf, int64_t nv,
+                                                             int32_t* cnt, int32_t* slot, uint32_t* err) {
+  __shared__ int s_key[CC_SLOTS], s_cnt[CC_SLOTS], s_base[CC_SLOTS];
+  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS) {
+    s_key[k] = -1;
+    s_cnt[k] = 0;
+  }
+  __syncthreads();
+  const int64_t f = blockIdx.x * (int64_t)CC_THREADS + threadIdx.x;
+  bool ok = false;
+  int32_t v3[3] = {0, 0, 0};
+  int hs[3] = {0, 0, 0}, rank[3] = {0, 0, 0};
+  if (f < nf) {
+    v3[0] = T[3 * f];
+    v3[1] = T[3 * f + 1];
+    v3[2] = T[3 * f + 2];
+    if (v3[0] < 0 || v3[1] < 0 || v3[2] < 0 || v3[0] >= nv || v3[1] >= nv || v3[2] >= nv) atomicOr(err, ERR_INDEX);
+    else if (v3[0] == v3[1] || v3[1] == v3[2] || v3[0] == v3[2]) atomicOr(err, ERR_REPEAT);
+    else ok = true;
+  }
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      unsigned h = ((unsigned)v3[j] * 2654435761u) >> 22;
+      while (true) {
+        int old = atomicCAS(&s_key[h], -1, v3[j]);
+        if (old == -1 || old == v3[j]) break;
+        h = (h + 1) & (CC_SLOTS - 1);
+      }
+      hs[j] = (int)h;
+      rank[j] = atomicAdd(&s_cnt[h], 1);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS)
+    if (s_key[k] >= 0) s_base[k] = atomicAdd(&cnt[s_key[k]], s_cnt[k]);
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) slot[3 * f + j] = s_base[hs[j]] + rank[j];
   }
 }
 
-// deterministic order of each vertex's incident faces (ascending index)
+// vertex -> corner table: corner 3f+j stored in the segment of vertex T[3f+j]
+__global__ void k_scatter_corners(const int32_t* __restrict__ T, int64_t nh, const int32_t* __restrict__ off,
+                                  const int32_t* __restrict__ slot, int32_t* vc) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nh) return;
+  vc[off[T[c]] + slot[c]] = (int32_t)c;
+}
+
+// deterministic order of each vertex's incident corners (ascending index)
 __global__ void k_sort_segments(const int32_t* __restrict__ off, int32_t* vf, int64_t nv) {
   int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= nv) return;
@@ -70,50 +102,90 @@ __global__ void k_sort_segments(const int32_t* __restrict__ off, int32_t* vf, in
   }
 }
 
-// twin of half-edge h = 3f+j (u -> w): the unique half-edge w -> u in another face around u
-__global__ void k_twins(const int32_t* __restrict__ T, int64_t nf, const int32_t* __restrict__ off,
-                        const int32_t* __restrict__ vf, int32_t* twin, uint32_t* err) {
-  int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (h >= 3 * nf) return;
-  int64_t f = h / 3;
-  int j = (int)(h - 3 * f);
-  int32_t u = T[3 * f + j], w = T[3 * f + (j + 1) % 3];
-  int32_t match = -1, nmatch = 0, dup = 0;
-  for (int32_t s = off[u]; s < off[u + 1]; s++) {
-    int32_t g = vf[s];
-    if (g == f) continue;
-    for (int jj = 0; jj < 3; jj++) {
-      int32_t x = T[3 * (int64_t)g + jj], y = T[3 * (int64_t)g + (jj + 1) % 3];
-      if (x == w && y == u) { nmatch++; match = 3 * g + jj; }
-      if (x == u && y == w) dup++;
+constexpr int VK_THREADS = 128;
+constexpr int VK_MAXD = 16;  // fans up to this degree are staged in LDS
+
+// Per vertex u, over its fan of corners (staged in LDS):
+//  * twins: the out-edge u -> w of corner c (half-edge c) pairs with the unique
+//    in-edge w -> u of another corner around u; none or several: not a closed
+//    2-manifold; two out-edges to the same w: inconsistent orientation;
+//  * pseudonormal N = sum alpha_i n_i (Eq. 8), class from the side of each
+//    neighbour against the plane through u with normal N (Section 3.1-3.2,
+//    Section 8.3), cone aperture and ruff test from the normals (Section 3.3,
+//    Section 4.2), all in double precision; number of vertex polyhedra.
+__global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__ V, const int32_t* __restrict__ T,
+                                                      int64_t nv, const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ vc, int ruff_mode, int saddle_mode,
+                                                      int force_both, int32_t* twin, float4* vinfo, uint32_t* vbits,
+                                                      int32_t* count, uint32_t* err) {
+  __shared__ int32_t s_c[VK_MAXD][VK_THREADS], s_n[VK_MAXD][VK_THREADS], s_p[VK_MAXD][VK_THREADS];
+  const int t = threadIdx.x;
+  const int64_t v = blockIdx.x * (int64_t)VK_THREADS + t;
+  if (v >= nv) return;
+  const int32_t s0 = off[v], d = off[v + 1] - s0;
+  const bool staged = d <= VK_MAXD;
+  if (staged) {
+    for (int k = 0; k < d; k++) {
+      int32_t c = vc[s0 + k];
+      s_c[k][t] = c;
+      s_n[k][t] = T[next_corner(c)];
+      s_p[k][t] = T[prev_corner(c)];
     }
   }
-  if (dup) atomicOr(err, ERR_ORIENT);
-  if (nmatch != 1) atomicOr(err, ERR_NONMANIFOLD);
-  twin[h] = nmatch == 1 ? match : -1;
+  auto C_ = [&](int k) { return staged ? s_c[k][t] : vc[s0 + k]; };
+  auto N_ = [&](int k) { return staged ? s_n[k][t] : T[next_corner(vc[s0 + k])]; };
+  auto P_ = [&](int k) { return staged ? s_p[k][t] : T[prev_corner(vc[s0 + k])]; };
+  uint32_t e = 0;
+  for (int i = 0; i < d; i++) {
+    const int32_t w = N_(i);
+    int32_t match = -1, nmatch = 0;
+    for (int k = 0; k < d; k++) {
+      if (k != i && N_(k) == w) e |= ERR_ORIENT;
+      if (P_(k) == w) {
+        nmatch++;
+        match = prev_corner(C_(k));
+      }
+    }
+    if (nmatch != 1) e |= ERR_NONMANIFOLD;
+    twin[C_(i)] = nmatch == 1 ? match : -1;
+  }
+  if (e) atomicOr(err, e);
+  const d3 pv = vload_d(V, v);
+  VertexAccum acc;
+  for (int k = 0; k < d; k++) acc.add_face(pv, vload_d(V, N_(k)), vload_d(V, P_(k)));
+  VertexTest vt;
+  vt.init(acc.n_alpha);
+  for (int k = 0; k < d; k++) {
+    const d3 p1 = vload_d(V, N_(k)), p2 = vload_d(V, P_(k));
+    vt.neighbour(pv, p1);
+    vt.normal(pv, p1, p2);
+  }
+  VertexClass cl = vt.finish(ruff_mode, saddle_mode, force_both);
+  if (d == 0) cl.bits = 0;  // isolated vertex: no feature
+  float cf = (float)cl.cos_t;
+  if ((double)cf > cl.cos_t) cf = nextafterf(cf, -2.f);  // the stored cone contains the exact one
+  vinfo[v] = make_float4((float)cl.axis.x, (float)cl.axis.y, (float)cl.axis.z, cf);
+  vbits[v] = cl.bits;
+  count[v] = ((cl.bits & V_POS) ? 1 : 0) + ((cl.bits & V_NEG) ? 1 : 0);
 }
 
-__global__ void k_owned(const int32_t* __restrict__ T, int64_t nf, int32_t* flag) {
+__global__ void k_owned(const int32_t* __restrict__ T, int64_t nh, int32_t* flag) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (h >= 3 * nf) return;
-  int64_t f = h / 3;
-  int j = (int)(h - 3 * f);
-  flag[h] = T[3 * f + j] < T[3 * f + (j + 1) % 3] ? 1 : 0;
+  if (h >= nh) return;
+  flag[h] = T[h] < T[next_corner((int32_t)h)] ? 1 : 0;
 }
 
 // (an open or non-manifold surface can own more or fewer than 3F/2 half-edges: such
 // a build is rejected after the final readback, and nothing is written past ne)
-__global__ void k_edges(const int32_t* __restrict__ T, int64_t nf, int64_t ne, const int32_t* __restrict__ twin,
+__global__ void k_edges(const int32_t* __restrict__ T, int64_t nh, int64_t ne, const int32_t* __restrict__ twin,
                         const int32_t* __restrict__ eid, int4* edges, int32_t* face_edges) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (h >= 3 * nf) return;
-  int64_t f = h / 3;
-  int j = (int)(h - 3 * f);
-  int32_t u = T[3 * f + j], w = T[3 * f + (j + 1) % 3];
+  if (h >= nh) return;
+  int32_t u = T[h], w = T[next_corner((int32_t)h)];
   int32_t t = twin[h];
   if (u < w) {
     int32_t e = eid[h];
-    if (e < ne) edges[e] = make_int4(u, w, (int)f, t >= 0 ? t / 3 : -1);
+    if (e < ne) edges[e] = make_int4(u, w, (int)(h / 3), t >= 0 ? t / 3 : -1);
     face_edges[h] = e < ne ? e : -1;
   } else {
     int32_t e = t >= 0 ? eid[t] : -1;
@@ -143,26 +215,57 @@ __device__ inline int32_t third_vertex(const int32_t* T, int64_t f, int32_t a, i
 
 // edge class (exact orientation of the four float corners) and the sides to extrude
 __global__ void k_edge_class(const float* __restrict__ V, const int32_t* __restrict__ T, const int4* __restrict__ edges,
-                             int64_t ne, int force_both, uint8_t* cls, int32_t* count, int64_t* stats) {
+                             int64_t ne, int force_both, uint8_t* cls, int32_t* count) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int c = -1, sides = 0;
-  if (e < ne) {
-    int4 E = edges[e];
-    if (E.x >= 0 && E.z >= 0 && E.w >= 0) {
-      int32_t c1 = third_vertex(T, E.z, E.x, E.y), c2 = third_vertex(T, E.w, E.x, E.y);
-      c = classify_edge(vload_f(V, E.x), vload_f(V, E.y), vload_f(V, c1), vload_f(V, c2));
-      if (c == EDGE_CONVEX) sides = 1;
-      else if (c == EDGE_CONCAVE) sides = 2;
-      else if (c == EDGE_UNKNOWN) sides = 3;
-      if (force_both) sides = 3;
-    }
-    cls[e] = (uint8_t)((c < 0 ? 0 : c) | (sides << 2));
-    count[e] = __popc(sides);
+  if (e >= ne) return;
+  int c = 0, sides = 0;
+  int4 E = edges[e];
+  if (E.x >= 0 && E.z >= 0 && E.w >= 0) {
+    int32_t c1 = third_vertex(T, E.z, E.x, E.y), c2 = third_vertex(T, E.w, E.x, E.y);
+    c = classify_edge(vload_f(V, E.x), vload_f(V, E.y), vload_f(V, c1), vload_f(V, c2));
+    if (c == EDGE_CONVEX) sides = 1;
+    else if (c == EDGE_CONCAVE) sides = 2;
+    else if (c == EDGE_UNKNOWN) sides = 3;
+    if (force_both) sides = 3;
   }
-  count_if(c == EDGE_CONVEX, &stats[ST_E_CONVEX]);
-  count_if(c == EDGE_CONCAVE, &stats[ST_E_CONCAVE]);
-  count_if(c == EDGE_FLAT, &stats[ST_E_FLAT]);
-  count_if(c == EDGE_UNKNOWN, &stats[ST_E_UNKNOWN]);
+  cls[e] = (uint8_t)(c | (sides << 2));
+  count[e] = __popc(sides);
+}
+
+// class statistics: one LDS histogram per block, one global add per bin and block
+__global__ __launch_bounds__(256) void k_class_stats(const uint8_t* __restrict__ ecls, int64_t ne,
+                                                     const uint32_t* __restrict__ vbits, int64_t nv, int64_t* stats) {
+  __shared__ int h[16];
+  if (threadIdx.x < 16) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int loc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ne; i += stride) {
+    int c = ecls[i] & 3;
+    loc[0] += c == EDGE_CONVEX;
+    loc[1] += c == EDGE_CONCAVE;
+    loc[2] += c == EDGE_FLAT;
+    loc[3] += c == EDGE_UNKNOWN;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += stride) {
+    uint32_t b = vbits[i];
+    loc[4] += (b & V_CONVEX) != 0;
+    loc[5] += (b & V_CONCAVE) != 0;
+    loc[6] += (b & V_FLAT) != 0;
+    loc[7] += (b & V_SADDLE) != 0;
+    loc[8] += (b & V_RUFF) != 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; k++) {
+    int x = loc[k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if ((threadIdx.x & 63) == 0 && x) atomicAdd(&h[k], x);
+  }
+  __syncthreads();
+  const int map[9] = {ST_E_CONVEX, ST_E_CONCAVE, ST_E_FLAT, ST_E_UNKNOWN, ST_V_CONVEX,
+                      ST_V_CONCAVE, ST_V_FLAT,   ST_V_SADDLE, ST_V_RUFF};
+  if (threadIdx.x < 9 && h[threadIdx.x])
+    atomicAdd((unsigned long long*)&stats[map[threadIdx.x]], (unsigned long long)h[threadIdx.x]);
 }
 
 __global__ void k_edge_queue(const uint8_t* __restrict__ cls, int64_t ne, const int32_t* __restrict__ off, int32_t* q) {
@@ -174,48 +277,6 @@ __global__ void k_edge_queue(const uint8_t* __restrict__ cls, int64_t ne, const 
   if (sides & 2) q[p++] = (int32_t)((e << 1) | 1);
 }
 
-// vertex pseudonormal (Eq. 8), class (Section 3.1-3.3, Section 8.3) and cone aperture (Section 4.2)
-__global__ void k_vertex_class(const float* __restrict__ V, const int32_t* __restrict__ T,
-                               const int32_t* __restrict__ off, const int32_t* __restrict__ vf, int64_t nv,
-                               int ruff_mode, int saddle_mode, int force_both, float4* vinfo, uint32_t* vbits,
-                               int32_t* count, int64_t* stats) {
-  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  uint32_t bits = 0;
-  if (v < nv) {
-    d3 pv = vload_d(V, v);
-    VertexAccum acc;
-    int32_t s0 = off[v], s1 = off[v + 1];
-    for (int32_t s = s0; s < s1; s++) {
-      int64_t g = vf[s];
-      int jj = T[3 * g] == v ? 0 : (T[3 * g + 1] == v ? 1 : 2);
-      acc.add_face(pv, vload_d(V, T[3 * g + (jj + 1) % 3]), vload_d(V, T[3 * g + (jj + 2) % 3]));
-    }
-    VertexTest t;
-    t.init(acc.n_alpha);
-    for (int32_t s = s0; s < s1; s++) {
-      int64_t g = vf[s];
-      int jj = T[3 * g] == v ? 0 : (T[3 * g + 1] == v ? 1 : 2);
-      d3 p1 = vload_d(V, T[3 * g + (jj + 1) % 3]), p2 = vload_d(V, T[3 * g + (jj + 2) % 3]);
-      t.neighbour(pv, p1);
-      t.normal(pv, p1, p2);
-    }
-    VertexClass vc = t.finish(ruff_mode, saddle_mode, force_both);
-    if (s1 == s0) vc.bits = 0;  // isolated vertex: no feature
-    float cf = (float)vc.cos_t;
-    if ((double)cf > vc.cos_t) cf = nextafterf(cf, -2.f);  // the stored cone contains the exact one
-    vinfo[v] = make_float4((float)vc.axis.x, (float)vc.axis.y, (float)vc.axis.z, cf);
-    vbits[v] = vc.bits;
-    bits = vc.bits;
-    count[v] = ((bits & V_POS) ? 1 : 0) + ((bits & V_NEG) ? 1 : 0);
-  }
-  bool ok = v < nv;
-  count_if(ok && (bits & V_CONVEX), &stats[ST_V_CONVEX]);
-  count_if(ok && (bits & V_CONCAVE), &stats[ST_V_CONCAVE]);
-  count_if(ok && (bits & V_FLAT), &stats[ST_V_FLAT]);
-  count_if(ok && (bits & V_SADDLE), &stats[ST_V_SADDLE]);
-  count_if(ok && (bits & V_RUFF), &stats[ST_V_RUFF]);
-}
-
 __global__ void k_vertex_queue(const uint32_t* __restrict__ vbits, int64_t nv, const int32_t* __restrict__ off, int32_t* q) {
   int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= nv) return;
@@ -225,28 +286,66 @@ __global__ void k_vertex_queue(const uint32_t* __restrict__ vbits, int64_t nv, c
   if (b & V_NEG) q[p++] = (int32_t)((v << 1) | 1);
 }
 
-// every brick within band*h (+ one cell of margin) of a triangle's bounding box
+// Bricks within band*h (+ one cell) of each triangle's bounding box. A triangle
+// whose dilated box stays within the 3x3x3 bricks around the brick of its
+// centroid only seeds that brick (the dilation below covers the rest); larger
+// ones mark every brick of their box directly.
 __global__ void k_mark_bricks(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf, csc_grid g,
-                              int nbx, int nby, int nbz, int32_t* flag) {
+                              int nbx, int nby, int nbz, uint8_t* seed, int32_t* flag) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  double r = (double)g.band_cells * g.h + g.h;
-  int lo[3], hi[3];
+  const double r = (double)g.band_cells * g.h + g.h, ih = 1.0 / g.h;
+  int lo[3], hi[3], cb[3];
   const int nbk[3] = {nbx, nby, nbz};
+  bool small = true;
   for (int ax = 0; ax < 3; ax++) {
     double x0 = V[3 * T[3 * f] + ax], x1 = V[3 * T[3 * f + 1] + ax], x2 = V[3 * T[3 * f + 2] + ax];
     double mn = fmin(x0, fmin(x1, x2)) - r, mx = fmax(x0, fmax(x1, x2)) + r;
-    double a = floor((mn - g.origin[ax]) / g.h - 0.5), b = ceil((mx - g.origin[ax]) / g.h - 0.5);
-    if (a < 0) a = 0;
-    if (b > g.n[ax] - 1) b = g.n[ax] - 1;
+    double a = floor((mn - g.origin[ax]) * ih - 0.5), b = ceil((mx - g.origin[ax]) * ih - 0.5);
+    a = fmax(a, 0.0);
+    b = fmin(b, (double)(g.n[ax] - 1));
     if (a > b) return;
     lo[ax] = (int)a / BRICK;
     hi[ax] = (int)b / BRICK;
-    if (hi[ax] >= nbk[ax]) hi[ax] = nbk[ax] - 1;
+    double cc = floor(floor(((x0 + x1 + x2) / 3.0 - g.origin[ax]) * ih) / BRICK);  // brick of the centroid's cell
+    cb[ax] = (int)fmax(-2.0, fmin(cc, (double)nbk[ax] + 1));
+    small = small && cb[ax] >= 0 && cb[ax] < nbk[ax] && lo[ax] >= cb[ax] - 1 && hi[ax] <= cb[ax] + 1;
+  }
+  if (small) {
+    uint8_t* p = &seed[cb[0] + (int64_t)nbx * (cb[1] + (int64_t)nby * cb[2])];
+    if (*p == 0) *p = 1;
+    return;
   }
   for (int z = lo[2]; z <= hi[2]; z++)
     for (int y = lo[1]; y <= hi[1]; y++)
-      for (int x = lo[0]; x <= hi[0]; x++) flag[x + (int64_t)nbx * (y + (int64_t)nby * z)] = 1;
+      for (int x = lo[0]; x <= hi[0]; x++) {
+        int32_t* p = &flag[x + (int64_t)nbx * (y + (int64_t)nby * z)];
+        if (*p == 0) *p = 1;
+      }
+}
+
+// flag every brick with a seed among its 27 neighbours
+__global__ void k_dilate_bricks(const uint8_t* __restrict__ seed, int nbx, int nby, int nbz, int32_t* flag) {
+  int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= (int64_t)nbx * nby * nbz) return;
+  if (flag[b]) return;
+  const int x = (int)(b % nbx), y = (int)((b / nbx) % nby), z = (int)(b / ((int64_t)nbx * nby));
+  for (int dz = -1; dz <= 1; dz++) {
+    int zz = z + dz;
+    if (zz < 0 || zz >= nbz) continue;
+    for (int dy = -1; dy <= 1; dy++) {
+      int yy = y + dy;
+      if (yy < 0 || yy >= nby) continue;
+      for (int dx = -1; dx <= 1; dx++) {
+        int xx = x + dx;
+        if (xx < 0 || xx >= nbx) continue;
+        if (seed[xx + (int64_t)nbx * (yy + (int64_t)nby * zz)]) {
+          flag[b] = 1;
+          return;
+        }
+      }
+    }
+  }
 }
 
 __global__ void k_brick_fix(const int32_t* __restrict__ flag, int32_t* index, int32_t* list, int64_t n) {
@@ -404,43 +503,45 @@ extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_
     if (e_ != hipSuccess) return fail(fail_hip(e_)); \
   } while (0)
 
+  StageTimer timer(TS_BUILD, s);
   // 1. validation and corner counts; the first readback guards every indexed access below
   CK(hipMemsetAsync(F->d_stats, 0, sizeof(int64_t) * ST_COUNT, s));
   CK(hipMemsetAsync(F->d_err, 0, sizeof(uint32_t), s));
   k_fill_i32<<<grid_1d(nv + 1, B), B, 0, s>>>(F->t_a, nv + 1, 0);
   k_check_verts<<<grid_1d(3 * nv, B), B, 0, s>>>(verts_d, nv, F->d_err);
-  k_count_corners<<<grid_1d(nf, B), B, 0, s>>>(tris_d, nf, nv, F->t_a, F->d_err);
+  k_count_corners<<<grid_1d(nf, CC_THREADS), CC_THREADS, 0, s>>>(tris_d, nf, nv, F->t_a, F->t_c, F->d_err);
   CK(hipGetLastError());
   CK(hipMemcpyAsync(F->h_stats + ST_COUNT, F->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   uint32_t err0 = *(uint32_t*)(F->h_stats + ST_COUNT);
   if (err0 & (ERR_INDEX | ERR_REPEAT | ERR_NONFINITE)) return fail(CSC_INVALID_ARG);
 
-  // 2. vertex -> face table (count, scan, scatter, sort)
+  // 2. vertex -> corner table (scan of the counts, scatter into the counted slots, sort)
   CK(exclusive_scan(F->t_a, F->vtx_off, nv + 1, F->t_scan, nullptr, nullptr, s));
-  k_fill_i32<<<grid_1d(nv + 1, B), B, 0, s>>>(F->t_a, nv + 1, 0);
-  k_scatter_faces<<<grid_1d(nf, B), B, 0, s>>>(tris_d, nf, F->vtx_off, F->t_a, F->vtx_faces);
+  k_scatter_corners<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nh, F->vtx_off, F->t_c, F->vtx_faces);
   k_sort_segments<<<grid_1d(nv, B), B, 0, s>>>(F->vtx_off, F->vtx_faces, nv);
-  // 3. twins and edge numbering
-  k_twins<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nf, F->vtx_off, F->vtx_faces, F->t_a, F->d_err);
-  k_owned<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nf, F->t_b);
+  // 3. per vertex: twins, pseudonormal, class, cone; then edge numbering
+  k_vertex<<<grid_1d(nv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, tris_d, nv, F->vtx_off, F->vtx_faces, o.ruff_mode,
+                                                        o.saddle_mode, o.force_both_sides, F->t_a, F->vinfo,
+                                                        F->vbits, F->t_c, F->d_err);
+  CK(exclusive_scan(F->t_c, F->t_c, nv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
+  k_vertex_queue<<<grid_1d(nv, B), B, 0, s>>>(F->vbits, nv, F->t_c, F->vpoly);
+  k_owned<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nh, F->t_b);
   k_fill_i32<<<grid_1d(4 * (ne + 1), B), B, 0, s>>>((int32_t*)F->edges, 4 * (ne + 1), -1);
   CK(exclusive_scan(F->t_b, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
-  k_edges<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nf, ne, F->t_a, F->t_b, F->edges, F->face_edges);
-  // 4. geometry and classes
+  k_edges<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nh, ne, F->t_a, F->t_b, F->edges, F->face_edges);
+  // 4. face normals and edge classes
   k_face_geom<<<grid_1d(nf, B), B, 0, s>>>(verts_d, tris_d, nf, F->face_n, F->d_err);
-  k_edge_class<<<grid_1d(ne, B), B, 0, s>>>(verts_d, tris_d, F->edges, ne, o.force_both_sides, F->edge_cls, F->t_c,
-                                             F->d_stats);
+  k_edge_class<<<grid_1d(ne, B), B, 0, s>>>(verts_d, tris_d, F->edges, ne, o.force_both_sides, F->edge_cls, F->t_c);
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
-  k_vertex_class<<<grid_1d(nv, B), B, 0, s>>>(verts_d, tris_d, F->vtx_off, F->vtx_faces, nv, o.ruff_mode,
-                                               o.saddle_mode, o.force_both_sides, F->vinfo, F->vbits, F->t_a,
-                                               F->d_stats);
-  CK(exclusive_scan(F->t_a, F->t_a, nv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
-  k_vertex_queue<<<grid_1d(nv, B), B, 0, s>>>(F->vbits, nv, F->t_a, F->vpoly);
+  k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, nv, F->d_stats);
   // 5. band bricks
   k_fill_i32<<<grid_1d(nbt, B), B, 0, s>>>(F->t_b, nbt, 0);
-  k_mark_bricks<<<grid_1d(nf, B), B, 0, s>>>(verts_d, tris_d, nf, *grid, nb[0], nb[1], nb[2], F->t_b);
+  k_fill_i32<<<grid_1d((nbt + 3) / 4, B), B, 0, s>>>(F->t_a, (nbt + 3) / 4, 0);
+  k_mark_bricks<<<grid_1d(nf, B), B, 0, s>>>(verts_d, tris_d, nf, *grid, nb[0], nb[1], nb[2], (uint8_t*)F->t_a,
+                                             F->t_b);
+  k_dilate_bricks<<<grid_1d(nbt, B), B, 0, s>>>((const uint8_t*)F->t_a, nb[0], nb[1], nb[2], F->t_b);
   CK(exclusive_scan(F->t_b, F->brick_index, nbt, F->t_scan, &F->d_stats[ST_NBRICKS], nullptr, s));
   k_brick_fix<<<grid_1d(nbt, B), B, 0, s>>>(F->t_b, F->brick_index, F->brick_list, nbt);
   CK(hipGetLastError());

@@ -60,38 +60,21 @@ __host__ __device__ inline int grow_expansion(int n, double* e, double b) {
   return m;
 }
 
-// Sign of (d - a) . ((b - a) x (c - a)) for single-precision points, evaluated
-// exactly: +1, -1 or 0. Returns 2 if a coordinate difference is not exact in
-// double precision (coordinates more than 2^29 apart in magnitude); callers
-// treat that as "unknown".
-__host__ __device__ inline int orient3d_sign(f3 a, f3 b, f3 c, f3 d) {
-  double u[3], v[3], w[3], err;
-  const float A[3] = {a.x, a.y, a.z}, B[3] = {b.x, b.y, b.z}, Cc[3] = {c.x, c.y, c.z}, D[3] = {d.x, d.y, d.z};
-  for (int k = 0; k < 3; k++) {
-    two_sum((double)B[k], -(double)A[k], u[k], err); if (err != 0.0) return 2;
-    two_sum((double)Cc[k], -(double)A[k], v[k], err); if (err != 0.0) return 2;
-    two_sum((double)D[k], -(double)A[k], w[k], err); if (err != 0.0) return 2;
-  }
-  // det = sum over the six signed products w_i u_j v_k of the cofactor expansion
-  const int I[6] = {0, 0, 1, 1, 2, 2}, J[6] = {1, 2, 2, 0, 0, 1}, K[6] = {2, 1, 0, 2, 1, 0};
-  const double S[6] = {1, -1, 1, -1, 1, -1};
-  double det = 0.0, perm = 0.0;
-  for (int t = 0; t < 6; t++) {
-    double p = S[t] * w[I[t]] * u[J[t]] * v[K[t]];
-    det += p;
-    perm += fabs(p);
-  }
-  // static filter: the rounding error of the sum above is far below 1e-12 * perm
-  if (det > 1e-12 * perm) return 1;
-  if (det < -1e-12 * perm) return -1;
-  if (perm == 0.0) return 0;
+// Exact sign of w . (u x v) for double vectors whose components are exact
+// (differences of floats): each of the six cofactor products is split into four
+// doubles by two_prod, and all 24 are summed into one expansion. Kept out of line:
+// it runs only when the filter below cannot decide.
+__host__ __device__ __attribute__((noinline)) inline int orient3d_exact(double ux, double uy, double uz, double vx,
+                                                                      double vy, double vz, double wx, double wy,
+                                                                      double wz) {
+  const double P[6][3] = {{wx, uy, vz}, {-wx, uz, vy}, {wy, uz, vx}, {-wy, ux, vz}, {wz, ux, vy}, {-wz, uy, vx}};
   double e[32];
   int n = 0;
   for (int t = 0; t < 6; t++) {
     double p, pe, p1, e1, p2, e2;
-    two_prod(S[t] * w[I[t]], u[J[t]], p, pe);
-    two_prod(p, v[K[t]], p1, e1);
-    two_prod(pe, v[K[t]], p2, e2);
+    two_prod(P[t][0], P[t][1], p, pe);
+    two_prod(p, P[t][2], p1, e1);
+    two_prod(pe, P[t][2], p2, e2);
     n = grow_expansion(n, e, p1);
     n = grow_expansion(n, e, e1);
     n = grow_expansion(n, e, p2);
@@ -99,6 +82,35 @@ __host__ __device__ inline int orient3d_sign(f3 a, f3 b, f3 c, f3 d) {
   }
   double top = e[n - 1];
   return top > 0 ? 1 : (top < 0 ? -1 : 0);
+}
+
+// Sign of (d - a) . ((b - a) x (c - a)) for single-precision points, evaluated
+// exactly: +1, -1 or 0. Returns 2 if a coordinate difference is not exact in
+// double precision (coordinates more than 2^29 apart in magnitude); callers
+// treat that as "unknown".
+__host__ __device__ inline int orient3d_sign(f3 a, f3 b, f3 c, f3 d) {
+  double ux, uy, uz, vx, vy, vz, wx, wy, wz, e0, e1, e2, e3, e4, e5, e6, e7, e8;
+  two_sum((double)b.x, -(double)a.x, ux, e0);
+  two_sum((double)b.y, -(double)a.y, uy, e1);
+  two_sum((double)b.z, -(double)a.z, uz, e2);
+  two_sum((double)c.x, -(double)a.x, vx, e3);
+  two_sum((double)c.y, -(double)a.y, vy, e4);
+  two_sum((double)c.z, -(double)a.z, vz, e5);
+  two_sum((double)d.x, -(double)a.x, wx, e6);
+  two_sum((double)d.y, -(double)a.y, wy, e7);
+  two_sum((double)d.z, -(double)a.z, wz, e8);
+  if (e0 != 0.0 || e1 != 0.0 || e2 != 0.0 || e3 != 0.0 || e4 != 0.0 || e5 != 0.0 || e6 != 0.0 || e7 != 0.0 ||
+      e8 != 0.0)
+    return 2;
+  const double t0 = wx * uy * vz, t1 = -(wx * uz * vy), t2 = wy * uz * vx, t3 = -(wy * ux * vz),
+               t4 = wz * ux * vy, t5 = -(wz * uy * vx);
+  const double det = ((t0 + t1) + (t2 + t3)) + (t4 + t5);
+  const double perm = fabs(t0) + fabs(t1) + fabs(t2) + fabs(t3) + fabs(t4) + fabs(t5);
+  // static filter: the rounding error of the sum above is far below 1e-12 * perm
+  if (det > 1e-12 * perm) return 1;
+  if (det < -1e-12 * perm) return -1;
+  if (perm == 0.0) return 0;
+  return orient3d_exact(ux, uy, uz, vx, vy, vz, wx, wy, wz);
 }
 
 // -------------------------------------------------------- feature classes
@@ -135,14 +147,13 @@ struct VertexClass {
 // normal against N (Section 3.3, Section 4.2).
 struct VertexAccum {
   d3 n_alpha = {0, 0, 0};
+  // corner at v of a triangle (v, p1, p2): alpha = atan2(|e1 x e2|, e1 . e2)
   __host__ __device__ inline void add_face(d3 v, d3 p1, d3 p2) {
     d3 e1 = p1 - v, e2 = p2 - v;
     d3 n = cross(e1, e2);
     double ln = len(n);
     if (!(ln > 0)) return;
-    double c = dot(e1, e2) / (len(e1) * len(e2));
-    c = c > 1 ? 1 : (c < -1 ? -1 : c);
-    n_alpha = n_alpha + n * (acos(c) / ln);
+    n_alpha = n_alpha + n * (atan2(ln, dot(e1, e2)) / ln);
   }
 };
 

@@ -33,6 +33,25 @@ hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* t
                           int32_t* total_i32, hipStream_t s);
 
 int fail_hip(hipError_t e);  // records the HIP error text, returns CSC_HIP_ERROR
+
+// timed stages (csc_timing_*)
+enum { TS_BUILD = 0, TS_INIT, TS_SCAN_FACE, TS_SCAN_EDGE, TS_SCAN_VERT, TS_COUNT, TS_SIGN, TS_BACKWARD, N_STAGES };
+
+// Records a pair of events around its scope on stream s when timing is enabled.
+class StageTimer {
+ public:
+  StageTimer(int stage, hipStream_t s);
+  ~StageTimer();
+  StageTimer(const StageTimer&) = delete;
+  StageTimer& operator=(const StageTimer&) = delete;
+
+ private:
+  int stage_;
+  hipStream_t s_;
+  void* a_ = nullptr;
+  void* b_ = nullptr;
+  bool active_ = false;
+};
 int check_device();          // CSC_OK or CSC_UNSUPPORTED_DEVICE / CSC_HIP_ERROR
 
 inline unsigned grid_1d(int64_t n, int block) {
@@ -56,7 +75,7 @@ struct csc_features {
   size_t arena_bytes = 0;
 
   int32_t* vtx_off = nullptr;     // [nv+1]
-  int32_t* vtx_faces = nullptr;   // [3nf], per vertex ascending face index
+  int32_t* vtx_faces = nullptr;   // [3nf], per vertex its corners 3f+j, ascending
   int32_t* face_edges = nullptr;  // [3nf]
   int4* edges = nullptr;          // [ne] (a, b, f_left, f_right)
   float4* face_n = nullptr;       // [nf] unit normal

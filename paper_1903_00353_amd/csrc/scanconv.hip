@@ -28,6 +28,7 @@ struct ScanArgs {
   const int32_t* items;       // edge / vertex polyhedron list (unused for faces)
   const int32_t* brick_index;
   unsigned long long* keys;
+  unsigned long long* counter;  // optional: number of atomicMin issued (diagnostics)
   int64_t nf, ne, n_items;
   double o[3];
   double h, whd, epsd;
@@ -248,8 +249,8 @@ __global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
   Poly q;
   int nc = 0;
   if (item < P.n_items) {
-    if (KIND == KIND_FACE) nc = build_face(P, item, q);
-    else if (KIND == KIND_EDGE) nc = build_edge(P, item, q);
+    if constexpr (KIND == KIND_FACE) nc = build_face(P, item, q);
+    else if constexpr (KIND == KIND_EDGE) nc = build_edge(P, item, q);
     else nc = build_vertex(P, item, q);
   }
   if (nc > 0) {
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
       for (int c = 0; c < 4; c++) s_pl[i * 4 + c][lane] = q.pl[i][c];
 #pragma unroll
     for (int i = 0; i < NG; i++) s_g[i][lane] = q.g[i];
-    if (KIND == KIND_VERT)
+    if constexpr (KIND == KIND_VERT)
 #pragma unroll
       for (int c = 0; c < 4; c++) s_cone[c][lane] = q.cone[c];
     s_anc[0][lane] = q.anc[0];
@@ -275,11 +276,12 @@ __global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
   __syncthreads();
   const long long total = s_start[64];
   const float hf = P.hf, eps = P.eps;
+  unsigned issued = 0;
 
   auto process = [&](int sl, int di, int dj, int dk) {
     f3 p = mk(di * hf, dj * hf, dk * hf);
     float d;
-    if (KIND == KIND_FACE) {
+    if constexpr (KIND == KIND_FACE) {
       f3 A = mk(s_g[0][sl], s_g[1][sl], s_g[2][sl]);
       f3 B = mk(s_g[3][sl], s_g[4][sl], s_g[5][sl]);
       f3 C = mk(s_g[6][sl], s_g[7][sl], s_g[8][sl]);
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
       float w[3];
       closest_triangle(p, A, B, C, qq, w);
       d = norm3(p - qq);
-    } else if (KIND == KIND_EDGE) {
+    } else if constexpr (KIND == KIND_EDGE) {
       f3 A = mk(s_g[0][sl], s_g[1][sl], s_g[2][sl]);
       f3 B = mk(s_g[3][sl], s_g[4][sl], s_g[5][sl]);
       float t;
@@ -302,6 +304,7 @@ __global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
       if (slot >= 0) {
         unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned int)s_id[sl];
         atomicMin(&P.keys[(int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)], key);
+        issued++;
       }
     }
   };
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
         float v = s_pl[4 * i][sl] * p.x + s_pl[4 * i + 1][sl] * p.y + s_pl[4 * i + 2][sl] * p.z + s_pl[4 * i + 3][sl];
         in = in && (v >= -eps);
       }
-      if (KIND == KIND_VERT && in) {
+      if constexpr (KIND == KIND_VERT) if (in) {
         f3 r = p - mk(s_g[0][sl], s_g[1][sl], s_g[2][sl]);
         float rr = dot(r, r);
         float lim = P.whf + eps;
@@ -369,6 +372,11 @@ __global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
     }
   }
   if (lane < qn) process(s_qs[lane], s_qi[lane], s_qj[lane], s_qk[lane]);
+  if (P.counter) {
+    unsigned long long c = issued;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if (lane == 0 && c) atomicAdd(P.counter, c);
+  }
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
@@ -494,7 +502,7 @@ WsLayout ws_layout(const csc_features* f) {
   L.keys = 0;
   L.cnt = au(sizeof(unsigned long long) * (size_t)(nb * BRICK_CELLS + 1));
   L.scan = L.cnt + au(sizeof(int32_t) * (size_t)(nb + 1));
-  L.total = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(nb + 1));
+  L.total = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(nb + 1) + 3 * sizeof(unsigned long long));
   return L;
 }
 }  // namespace
@@ -505,6 +513,69 @@ extern "C" int csc_scan_convert_workspace(const csc_features* f, size_t* bytes, 
   if (max_band_cells) *max_band_cells = f->n_bricks * BRICK_CELLS;
   return CSC_OK;
 }
+
+namespace {
+
+ScanArgs scan_args(const csc_features* f, unsigned long long* keys, unsigned long long* counter) {
+  ScanArgs A;
+  A.V = f->verts;
+  A.T = f->tris;
+  A.fn = f->face_n;
+  A.edges = f->edges;
+  A.ecls = f->edge_cls;
+  A.vinfo = f->vinfo;
+  A.vbits = f->vbits;
+  A.items = nullptr;
+  A.brick_index = f->brick_index;
+  A.keys = keys;
+  A.counter = counter;
+  A.nf = f->nf;
+  A.ne = f->ne;
+  A.n_items = 0;
+  for (int k = 0; k < 3; k++) {
+    A.o[k] = f->grid.origin[k];
+    A.n[k] = f->grid.n[k];
+    A.nb[k] = f->nb[k];
+  }
+  A.h = f->grid.h;
+  A.whd = (double)f->grid.band_cells * f->grid.h;
+  A.epsd = (double)f->opt.eps_rel * f->grid.h;
+  A.hf = (float)f->grid.h;
+  A.whf = (float)A.whd;
+  A.eps = (float)A.epsd;
+  return A;
+}
+
+// key init and the three scan launches; counters (3 slots) may be null
+void run_scans(const csc_features* f, unsigned long long* keys, unsigned long long* counters, hipStream_t s) {
+  const int64_t nk = f->n_bricks * BRICK_CELLS;
+  {
+    StageTimer t(TS_INIT, s);
+    k_fill_u64<<<grid_1d(nk, 256), 256, 0, s>>>(keys, nk, EMPTY_KEY);
+  }
+  ScanArgs A = scan_args(f, keys, counters);
+  {
+    StageTimer t(TS_SCAN_FACE, s);
+    A.n_items = f->nf;
+    k_scan<KIND_FACE><<<grid_1d(f->nf, 64), 64, 0, s>>>(A);
+  }
+  if (f->n_epoly > 0) {
+    StageTimer t(TS_SCAN_EDGE, s);
+    A.items = f->epoly;
+    A.n_items = f->n_epoly;
+    A.counter = counters ? counters + 1 : nullptr;
+    k_scan<KIND_EDGE><<<grid_1d(f->n_epoly, 64), 64, 0, s>>>(A);
+  }
+  if (f->n_vpoly > 0) {
+    StageTimer t(TS_SCAN_VERT, s);
+    A.items = f->vpoly;
+    A.n_items = f->n_vpoly;
+    A.counter = counters ? counters + 2 : nullptr;
+    k_scan<KIND_VERT><<<grid_1d(f->n_vpoly, 64), 64, 0, s>>>(A);
+  }
+}
+
+}  // namespace
 
 extern "C" int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d,
                                 int32_t* feat_d, int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream) {
@@ -518,53 +589,20 @@ extern "C" int csc_scan_convert(const csc_features* f, void* workspace_d, size_t
   int32_t* tmp = (int32_t*)(W + L.scan);
   const int64_t nk = f->n_bricks * BRICK_CELLS;
 
-  if (nk > 0) k_fill_u64<<<grid_1d(nk, 256), 256, 0, s>>>(keys, nk, EMPTY_KEY);
   if (dense_d) {
     int64_t nd = (int64_t)f->grid.n[0] * f->grid.n[1] * f->grid.n[2];
     k_fill_f32<<<grid_1d(nd, 256), 256, 0, s>>>(dense_d, nd, __builtin_inff());
   }
-  ScanArgs A;
-  A.V = f->verts;
-  A.T = f->tris;
-  A.fn = f->face_n;
-  A.edges = f->edges;
-  A.ecls = f->edge_cls;
-  A.vinfo = f->vinfo;
-  A.vbits = f->vbits;
-  A.brick_index = f->brick_index;
-  A.keys = keys;
-  A.nf = f->nf;
-  A.ne = f->ne;
-  for (int k = 0; k < 3; k++) {
-    A.o[k] = f->grid.origin[k];
-    A.n[k] = f->grid.n[k];
-    A.nb[k] = f->nb[k];
+  if (nk > 0) run_scans(f, keys, nullptr, s);
+  hipError_t e;
+  {
+    StageTimer t(TS_COUNT, s);
+    if (nk > 0) k_brick_count<<<(unsigned)f->n_bricks, 512, 0, s>>>(keys, cnt);
+    e = exclusive_scan(cnt, cnt, f->n_bricks, tmp, n_band_d, nullptr, s);
   }
-  A.h = f->grid.h;
-  A.whd = (double)f->grid.band_cells * f->grid.h;
-  A.epsd = (double)f->opt.eps_rel * f->grid.h;
-  A.hf = (float)f->grid.h;
-  A.whf = (float)A.whd;
-  A.eps = (float)A.epsd;
-  if (nk > 0) {
-    A.items = nullptr;
-    A.n_items = f->nf;
-    k_scan<KIND_FACE><<<grid_1d(f->nf, 64), 64, 0, s>>>(A);
-    if (f->n_epoly > 0) {
-      A.items = f->epoly;
-      A.n_items = f->n_epoly;
-      k_scan<KIND_EDGE><<<grid_1d(f->n_epoly, 64), 64, 0, s>>>(A);
-    }
-    if (f->n_vpoly > 0) {
-      A.items = f->vpoly;
-      A.n_items = f->n_vpoly;
-      k_scan<KIND_VERT><<<grid_1d(f->n_vpoly, 64), 64, 0, s>>>(A);
-    }
-    k_brick_count<<<(unsigned)f->n_bricks, 512, 0, s>>>(keys, cnt);
-  }
-  hipError_t e = exclusive_scan(cnt, cnt, f->n_bricks, tmp, n_band_d, nullptr, s);
   if (e != hipSuccess) return fail_hip(e);
   if (nk > 0) {
+    StageTimer t(TS_SIGN, s);
     SignArgs S;
     S.V = f->verts;
     S.T = f->tris;
@@ -591,4 +629,24 @@ extern "C" int csc_scan_convert(const csc_features* f, void* workspace_d, size_t
   }
   e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);
+}
+
+extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_bytes, int64_t counts[3],
+                                      void* stream) {
+  if (!f || !f->valid || !workspace_d || !counts) return CSC_INVALID_ARG;
+  WsLayout L = ws_layout(f);
+  if (ws_bytes < L.total) return CSC_WORKSPACE_TOO_SMALL;
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)workspace_d;
+  unsigned long long* keys = (unsigned long long*)(W + L.keys);
+  unsigned long long* ctr = (unsigned long long*)(W + L.scan);  // reuses the scan scratch
+  hipError_t e = hipMemsetAsync(ctr, 0, 3 * sizeof(unsigned long long), s);
+  if (e != hipSuccess) return fail_hip(e);
+  if (f->n_bricks > 0) run_scans(f, keys, ctr, s);
+  unsigned long long h[3];
+  e = hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e);
+  for (int i = 0; i < 3; i++) counts[i] = (int64_t)h[i];
+  return CSC_OK;
 }

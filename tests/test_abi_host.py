@@ -85,9 +85,18 @@ def test_null_handle_calls():
     nbytes, mx = C.c_size_t(), C.c_int64()
     assert L.csc_scan_convert_workspace(None, C.byref(nbytes), C.byref(mx)) == 1
     assert L.csc_scan_convert(None, None, 0, None, None, None, None, None, None) == 1
-    assert L.csc_sdf_backward(None, None, None, None, 0, None, None, None) == 1
+    assert L.csc_sdf_backward(None, None, None, None, 0, None, None, None, None) == 1
+    assert L.csc_scan_convert_count(None, None, 0, None, None) == 1
     assert L.csc_features_info(None, None) == 1
     L.csc_features_free(None)
+
+
+def test_timing_api_without_device():
+    P.csc_timing_reset()
+    t = P.csc_timing_read()
+    assert list(t) == ["build_features", "init_keys", "scan_faces", "scan_edges", "scan_vertices", "brick_count",
+                       "sign", "backward"]
+    assert all(v == (0.0, 0) for v in t.values())
 
 
 def test_edge_classes_on_a_fold():

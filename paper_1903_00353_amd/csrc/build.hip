@@ -33,73 +33,29 @@ __global__ void k_check_verts(const float* __restrict__ V, int64_t nv, uint32_t*
   if (!isfinite(V[i])) atomicOr(err, ERR_NONFINITE);
 }
 
-constexpr int CC_THREADS = 256;
-constexpr int CC_SLOTS = 1024;  // > 3 * CC_THREADS insertions
-
-// Index range / repeated-corner checks and per-vertex corner counts. A block first
-// counts its corners per vertex in an LDS hash table, then reserves one range per
-// vertex with a single global atomic; each corner gets base + its rank in the block.
-__global__ __launch_bounds__(CC_THREADS) void k_count_corners(const int32_t* __restrict__ T, int64_t nf, int64_t nv,
-                                                             int32_t* cnt, int32_t* slot, uint32_t* err) {
-  __shared__ int s_key[CC_SLOTS], s_cnt[CC_SLOTS], s_base[CC_SLOTS];
-  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS) {
-    s_key[k] = -1;
-    s_cnt[k] = 0;
-  }
-  __syncthreads();
-  const int64_t f = blockIdx.x * (int64_t)CC_THREADS + threadIdx.x;
-  bool ok = false;
-  int32_t v3[3] = {0, 0, 0};
-  int hs[3] = {0, 0, 0}, rank[3] = {0, 0, 0};
-  if (f < nf) {
-    v3[0] = T[3 * f];
-    v3[1] = T[3 * f + 1];
-    v3[2] = T[3 * f + 2];
-    if (v3[0] < 0 || v3[1] < 0 || v3[2] < 0 || v3[0] >= nv || v3[1] >= nv || v3[2] >= nv) atomicOr(err, ERR_INDEX);
-    else if (v3[0] == v3[1] || v3[1] == v3[2] || v3[0] == v3[2]) atomicOr(err, ERR_REPEAT);
-    else ok = true;
-  }
-  if (ok) {
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-      unsigned h = ((unsigned)v3[j] * 2654435761u) >> 22;
-      while (true) {
-        int old = atomicCAS(&s_key[h], -1, v3[j]);
-        if (old == -1 || old == v3[j]) break;
-        h = (h + 1) & (CC_SLOTS - 1);
-      }
-      hs[j] = (int)h;
-      rank[j] = atomicAdd(&s_cnt[h], 1);
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS)
-    if (s_key[k] >= 0) s_base[k] = atomicAdd(&cnt[s_key[k]], s_cnt[k]);
-  __syncthreads();
-  if (ok) {
-#pragma unroll
-    for (int j = 0; j < 3; j++) slot[3 * f + j] = s_base[hs[j]] + rank[j];
-  }
+// index range and repeated-corner checks
+__global__ void k_validate_faces(const int32_t* __restrict__ T, int64_t nf, int64_t nv, uint32_t* err) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int32_t a = T[3 * f], b = T[3 * f + 1], c = T[3 * f + 2];
+  if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) atomicOr(err, ERR_INDEX);
+  else if (a == b || b == c || a == c) atomicOr(err, ERR_REPEAT);
 }
 
-// vertex -> corner table: corner 3f+j stored in the segment of vertex T[3f+j]
-__global__ void k_scatter_corners(const int32_t* __restrict__ T, int64_t nh, const int32_t* __restrict__ off,
-                                  const int32_t* __restrict__ slot, int32_t* vc) {
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= nh) return;
-  vc[off[T[c]] + slot[c]] = (int32_t)c;
+__global__ void k_iota(int32_t* p, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
 }
 
-// deterministic order of each vertex's incident corners (ascending index)
-__global__ void k_sort_segments(const int32_t* __restrict__ off, int32_t* vf, int64_t nv) {
-  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  int32_t s = off[v], e = off[v + 1];
-  for (int32_t i = s + 1; i < e; i++) {
-    int32_t x = vf[i], j = i - 1;
-    while (j >= s && vf[j] > x) { vf[j + 1] = vf[j]; j--; }
-    vf[j + 1] = x;
-  }
+// Segment offsets of the corners sorted by vertex: off[v] = first position whose
+// vertex is >= v (vertices without corners get empty segments), off[nv] = nh.
+__global__ void k_offsets(const uint32_t* __restrict__ key, int64_t nh, int64_t nv, int32_t* off) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nh) return;
+  const int64_t k = key[i], kp = i > 0 ? (int64_t)key[i - 1] : -1;
+  for (int64_t v = kp + 1; v <= k; v++) off[v] = (int32_t)i;
+  if (i == nh - 1)
+    for (int64_t v = k + 1; v <= nv; v++) off[v] = (int32_t)nh;
 }
 
 constexpr int VK_THREADS = 128;
@@ -193,19 +149,53 @@ __global__ void k_edges(const int32_t* __restrict__ T, int64_t nh, int64_t ne, c
   }
 }
 
+// Unit face normal (double precision, stored in single) and the band bricks near
+// the face: every brick within band*h (+ one cell) of its bounding box. A face
+// whose dilated box stays within the 3x3x3 bricks around the brick of its
+// centroid only seeds that brick (k_dilate_bricks covers the rest); larger ones
+// mark every brick of their box directly.
 __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf, float4* fn,
-                            uint32_t* err) {
+                            csc_grid g, int nbx, int nby, int nbz, uint8_t* seed, int32_t* flag, uint32_t* err) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  d3 a = vload_d(V, T[3 * f]), b = vload_d(V, T[3 * f + 1]), c = vload_d(V, T[3 * f + 2]);
-  d3 n = cross(b - a, c - a);
-  double l = len(n);
+  const d3 a = vload_d(V, T[3 * f]), b = vload_d(V, T[3 * f + 1]), c = vload_d(V, T[3 * f + 2]);
+  const d3 n = cross(b - a, c - a);
+  const double l = len(n);
   if (!(l > 0)) {
     atomicOr(err, ERR_DEGENERATE);
     fn[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    fn[f] = make_float4((float)(n.x / l), (float)(n.y / l), (float)(n.z / l), 0.f);
+  }
+  const double r = (double)g.band_cells * g.h + g.h, ih = 1.0 / g.h;
+  const double X[3][3] = {{a.x, b.x, c.x}, {a.y, b.y, c.y}, {a.z, b.z, c.z}};
+  const int nbk[3] = {nbx, nby, nbz};
+  int lo[3], hi[3], cb[3];
+  bool small = true;
+  for (int ax = 0; ax < 3; ax++) {
+    const double x0 = X[ax][0], x1 = X[ax][1], x2 = X[ax][2];
+    const double mn = fmin(x0, fmin(x1, x2)) - r, mx = fmax(x0, fmax(x1, x2)) + r;
+    double lo_c = floor((mn - g.origin[ax]) * ih - 0.5), hi_c = ceil((mx - g.origin[ax]) * ih - 0.5);
+    lo_c = fmax(lo_c, 0.0);
+    hi_c = fmin(hi_c, (double)(g.n[ax] - 1));
+    if (lo_c > hi_c) return;
+    lo[ax] = (int)lo_c / BRICK;
+    hi[ax] = (int)hi_c / BRICK;
+    const double cc = floor(floor(((x0 + x1 + x2) / 3.0 - g.origin[ax]) * ih) / BRICK);  // centroid's brick
+    cb[ax] = (int)fmax(-2.0, fmin(cc, (double)nbk[ax] + 1));
+    small = small && cb[ax] >= 0 && cb[ax] < nbk[ax] && lo[ax] >= cb[ax] - 1 && hi[ax] <= cb[ax] + 1;
+  }
+  if (small) {
+    uint8_t* p = &seed[cb[0] + (int64_t)nbx * (cb[1] + (int64_t)nby * cb[2])];
+    if (*p == 0) *p = 1;
     return;
   }
-  fn[f] = make_float4((float)(n.x / l), (float)(n.y / l), (float)(n.z / l), 0.f);
+  for (int z = lo[2]; z <= hi[2]; z++)
+    for (int y = lo[1]; y <= hi[1]; y++)
+      for (int x = lo[0]; x <= hi[0]; x++) {
+        int32_t* p = &flag[x + (int64_t)nbx * (y + (int64_t)nby * z)];
+        if (*p == 0) *p = 1;
+      }
 }
 
 __device__ inline int32_t third_vertex(const int32_t* T, int64_t f, int32_t a, int32_t b) {
@@ -286,44 +276,6 @@ __global__ void k_vertex_queue(const uint32_t* __restrict__ vbits, int64_t nv, c
   if (b & V_NEG) q[p++] = (int32_t)((v << 1) | 1);
 }
 
-// Bricks within band*h (+ one cell) of each triangle's bounding box. A triangle
-// whose dilated box stays within the 3x3x3 bricks around the brick of its
-// centroid only seeds that brick (the dilation below covers the rest); larger
-// ones mark every brick of their box directly.
-__global__ void k_mark_bricks(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf, csc_grid g,
-                              int nbx, int nby, int nbz, uint8_t* seed, int32_t* flag) {
-  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (f >= nf) return;
-  const double r = (double)g.band_cells * g.h + g.h, ih = 1.0 / g.h;
-  int lo[3], hi[3], cb[3];
-  const int nbk[3] = {nbx, nby, nbz};
-  bool small = true;
-  for (int ax = 0; ax < 3; ax++) {
-    double x0 = V[3 * T[3 * f] + ax], x1 = V[3 * T[3 * f + 1] + ax], x2 = V[3 * T[3 * f + 2] + ax];
-    double mn = fmin(x0, fmin(x1, x2)) - r, mx = fmax(x0, fmax(x1, x2)) + r;
-    double a = floor((mn - g.origin[ax]) * ih - 0.5), b = ceil((mx - g.origin[ax]) * ih - 0.5);
-    a = fmax(a, 0.0);
-    b = fmin(b, (double)(g.n[ax] - 1));
-    if (a > b) return;
-    lo[ax] = (int)a / BRICK;
-    hi[ax] = (int)b / BRICK;
-    double cc = floor(floor(((x0 + x1 + x2) / 3.0 - g.origin[ax]) * ih) / BRICK);  // brick of the centroid's cell
-    cb[ax] = (int)fmax(-2.0, fmin(cc, (double)nbk[ax] + 1));
-    small = small && cb[ax] >= 0 && cb[ax] < nbk[ax] && lo[ax] >= cb[ax] - 1 && hi[ax] <= cb[ax] + 1;
-  }
-  if (small) {
-    uint8_t* p = &seed[cb[0] + (int64_t)nbx * (cb[1] + (int64_t)nby * cb[2])];
-    if (*p == 0) *p = 1;
-    return;
-  }
-  for (int z = lo[2]; z <= hi[2]; z++)
-    for (int y = lo[1]; y <= hi[1]; y++)
-      for (int x = lo[0]; x <= hi[0]; x++) {
-        int32_t* p = &flag[x + (int64_t)nbx * (y + (int64_t)nby * z)];
-        if (*p == 0) *p = 1;
-      }
-}
-
 // flag every brick with a seed among its 27 neighbours
 __global__ void k_dilate_bricks(const uint8_t* __restrict__ seed, int nbx, int nby, int nbz, int32_t* flag) {
   int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -369,7 +321,7 @@ struct Layout {
 };
 
 // arena layout for nv vertices, nf faces, nbt bricks
-Layout layout(int64_t nv, int64_t nf, int64_t nbt) {
+Layout layout(int64_t nv, int64_t nf, int64_t nbt, size_t sort_bytes) {
   int64_t ne = 3 * nf / 2;
   int64_t big = 3 * nf > nbt ? 3 * nf : nbt;
   big = big > nv + 1 ? big : nv + 1;
@@ -392,7 +344,8 @@ Layout layout(int64_t nv, int64_t nf, int64_t nbt) {
       sizeof(int32_t) * (size_t)scan_tmp_ints(big + 1),  // 15 t_scan
       sizeof(int64_t) * ST_COUNT,           // 16 stats
       sizeof(uint32_t) * 4,                 // 17 err
-      0, 0};
+      sort_bytes,                           // 18 radix sort scratch
+      0};
   Layout L;
   size_t o = 0;
   for (int i = 0; i < 20; i++) {
@@ -437,7 +390,14 @@ extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_
     if (!F) return CSC_OUT_OF_MEMORY;
   }
   F->valid = false;
-  Layout L = layout(nv, nf, nbt);
+  int sort_bits = 1;
+  while (sort_bits < 31 && ((int64_t)1 << sort_bits) < nv) sort_bits++;
+  const size_t sort_bytes = sort_pairs_tmp_bytes(3 * nf, sort_bits);
+  if (sort_bytes == 0) {
+    if (fresh) delete F;
+    return fail_hip(hipErrorInvalidValue);
+  }
+  Layout L = layout(nv, nf, nbt, sort_bytes);
   hipError_t he;
   if (F->arena_bytes < L.total) {
     if (F->arena) {
@@ -490,6 +450,8 @@ extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_
   F->t_scan = (int32_t*)(A + L.off[15]);
   F->d_stats = (int64_t*)(A + L.off[16]);
   F->d_err = (uint32_t*)(A + L.off[17]);
+  F->t_sort = (void*)(A + L.off[18]);
+  F->t_sort_bytes = sort_bytes;
 
   const int B = 256;
   const int64_t nh = 3 * nf, ne = F->ne;
@@ -504,22 +466,22 @@ extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_
   } while (0)
 
   StageTimer timer(TS_BUILD, s);
-  // 1. validation and corner counts; the first readback guards every indexed access below
+  // 1. validation; the first readback guards every indexed access below
   CK(hipMemsetAsync(F->d_stats, 0, sizeof(int64_t) * ST_COUNT, s));
   CK(hipMemsetAsync(F->d_err, 0, sizeof(uint32_t), s));
-  k_fill_i32<<<grid_1d(nv + 1, B), B, 0, s>>>(F->t_a, nv + 1, 0);
   k_check_verts<<<grid_1d(3 * nv, B), B, 0, s>>>(verts_d, nv, F->d_err);
-  k_count_corners<<<grid_1d(nf, CC_THREADS), CC_THREADS, 0, s>>>(tris_d, nf, nv, F->t_a, F->t_c, F->d_err);
+  k_validate_faces<<<grid_1d(nf, B), B, 0, s>>>(tris_d, nf, nv, F->d_err);
   CK(hipGetLastError());
   CK(hipMemcpyAsync(F->h_stats + ST_COUNT, F->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   uint32_t err0 = *(uint32_t*)(F->h_stats + ST_COUNT);
   if (err0 & (ERR_INDEX | ERR_REPEAT | ERR_NONFINITE)) return fail(CSC_INVALID_ARG);
 
-  // 2. vertex -> corner table (scan of the counts, scatter into the counted slots, sort)
-  CK(exclusive_scan(F->t_a, F->vtx_off, nv + 1, F->t_scan, nullptr, nullptr, s));
-  k_scatter_corners<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nh, F->vtx_off, F->t_c, F->vtx_faces);
-  k_sort_segments<<<grid_1d(nv, B), B, 0, s>>>(F->vtx_off, F->vtx_faces, nv);
+  // 2. vertex -> corner table: corners 3f+j stably sorted by their vertex T[3f+j]
+  k_iota<<<grid_1d(nh, B), B, 0, s>>>(F->t_a, nh);
+  CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)tris_d, (uint32_t*)F->t_b, F->t_a, F->vtx_faces, nh,
+                sort_bits, s));
+  k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, nv, F->vtx_off);
   // 3. per vertex: twins, pseudonormal, class, cone; then edge numbering
   k_vertex<<<grid_1d(nv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, tris_d, nv, F->vtx_off, F->vtx_faces, o.ruff_mode,
                                                         o.saddle_mode, o.force_both_sides, F->t_a, F->vinfo,
@@ -530,17 +492,16 @@ extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_
   k_fill_i32<<<grid_1d(4 * (ne + 1), B), B, 0, s>>>((int32_t*)F->edges, 4 * (ne + 1), -1);
   CK(exclusive_scan(F->t_b, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
   k_edges<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nh, ne, F->t_a, F->t_b, F->edges, F->face_edges);
-  // 4. face normals and edge classes
-  k_face_geom<<<grid_1d(nf, B), B, 0, s>>>(verts_d, tris_d, nf, F->face_n, F->d_err);
+  // 4. face normals with the band bricks near each face, edge classes
+  k_fill_i32<<<grid_1d(nbt, B), B, 0, s>>>(F->t_b, nbt, 0);
+  k_fill_i32<<<grid_1d((nbt + 3) / 4, B), B, 0, s>>>(F->t_a, (nbt + 3) / 4, 0);
+  k_face_geom<<<grid_1d(nf, B), B, 0, s>>>(verts_d, tris_d, nf, F->face_n, *grid, nb[0], nb[1], nb[2],
+                                           (uint8_t*)F->t_a, F->t_b, F->d_err);
   k_edge_class<<<grid_1d(ne, B), B, 0, s>>>(verts_d, tris_d, F->edges, ne, o.force_both_sides, F->edge_cls, F->t_c);
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
   k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, nv, F->d_stats);
   // 5. band bricks
-  k_fill_i32<<<grid_1d(nbt, B), B, 0, s>>>(F->t_b, nbt, 0);
-  k_fill_i32<<<grid_1d((nbt + 3) / 4, B), B, 0, s>>>(F->t_a, (nbt + 3) / 4, 0);
-  k_mark_bricks<<<grid_1d(nf, B), B, 0, s>>>(verts_d, tris_d, nf, *grid, nb[0], nb[1], nb[2], (uint8_t*)F->t_a,
-                                             F->t_b);
   k_dilate_bricks<<<grid_1d(nbt, B), B, 0, s>>>((const uint8_t*)F->t_a, nb[0], nb[1], nb[2], F->t_b);
   CK(exclusive_scan(F->t_b, F->brick_index, nbt, F->t_scan, &F->d_stats[ST_NBRICKS], nullptr, s));
   k_brick_fix<<<grid_1d(nbt, B), B, 0, s>>>(F->t_b, F->brick_index, F->brick_list, nbt);

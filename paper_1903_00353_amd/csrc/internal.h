@@ -32,6 +32,11 @@ int64_t scan_tmp_ints(int64_t n);
 hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t* total_i64,
                           int32_t* total_i32, hipStream_t s);
 
+// stable radix sort of n (key, value) pairs on the low `bits` key bits
+size_t sort_pairs_tmp_bytes(int64_t n, int bits);
+hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint32_t* keys_out,
+                      const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits, hipStream_t s);
+
 int fail_hip(hipError_t e);  // records the HIP error text, returns CSC_HIP_ERROR
 
 // timed stages (csc_timing_*)
@@ -90,6 +95,8 @@ struct csc_features {
   int32_t* t_b = nullptr;
   int32_t* t_c = nullptr;
   int32_t* t_scan = nullptr;
+  void* t_sort = nullptr;         // radix sort scratch
+  size_t t_sort_bytes = 0;
   int64_t* d_stats = nullptr;     // [ST_COUNT]
   uint32_t* d_err = nullptr;
   int64_t* h_stats = nullptr;     // pinned host mirror [ST_COUNT + 1]

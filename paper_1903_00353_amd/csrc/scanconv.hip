@@ -1,15 +1,19 @@
 // Scan conversion of the characteristic polyhedra (Section 5, Section 9,
 // Section 10) and the sign pass (Section 4.1.3).
 //
-// One wavefront takes 64 polyhedra of one kind (one per lane), builds their
-// planes, bounding boxes and local frames into LDS, then walks the union of
-// their bounding-box cells 64 at a time: every lane tests one cell against its
-// polyhedron (half-space test with slack, Alg. 2; cone/hemisphere discriminant,
-// Eq. 10), the cells inside are compacted into an LDS queue, and each full queue
-// of 64 candidates gets the exact clamped point-feature distance and one packed
-// 64-bit atomicMin of (float bits of |d|, feature id) into the brick store.
-// The paper's per-extrusion thread (Section 9) becomes this load-balanced wave;
-// its float compare-and-swap loop becomes a single order-free integer min.
+// Each polyhedron is walked row by row along the grid axis closest to its main
+// direction (face normal, edge bisector, vertex axis): for every row of its
+// bounding box the cells inside are found at once by intersecting the row with
+// the half-spaces (the half-space test with slack of Alg. 2 solved for the row
+// parameter) and, for vertices, with the ball of radius band*h; cones test their
+// discriminant (Eq. 10) per cell. Each candidate cell gets the exact clamped
+// point-feature distance and one packed 64-bit atomicMin of (float bits of |d|,
+// feature id) into the brick store, the order-free replacement of the paper's
+// float compare-and-swap loop (Section 9).
+// Small polyhedra take one thread each (the paper's per-extrusion scheme); those
+// with more rows go to an overflow list that a second kernel walks with one
+// wavefront per polyhedron, its lanes splitting the rows (the role of the
+// dynamic-parallelism hybrid of Section 9.1).
 #include "geometry.h"
 #include "internal.h"
 
@@ -29,6 +33,8 @@ struct ScanArgs {
   const int32_t* brick_index;
   unsigned long long* keys;
   unsigned long long* counter;  // optional: number of atomicMin issued (diagnostics)
+  int32_t* big_items;           // overflow list of polyhedra with many rows
+  int32_t* big_count;
   int64_t nf, ne, n_items;
   double o[3];
   double h, whd, epsd;
@@ -43,8 +49,20 @@ struct Poly {
   float cone[4];    // vertex: axis, aperture cosine (or -2 for a hemisphere)
   int anc[3];
   int dim[3];
+  int ra, ua, va;   // row axis and the two axes across rows
   int id;
 };
+
+// axis of the largest |component|
+__device__ inline int major_axis(double x, double y, double z) {
+  double ax = fabs(x), ay = fabs(y), az = fabs(z);
+  return ax >= ay ? (ax >= az ? 0 : 2) : (ay >= az ? 1 : 2);
+}
+__device__ inline void set_axes(Poly& q, int ra) {
+  q.ra = ra;
+  q.ua = ra == 0 ? 1 : 0;
+  q.va = ra == 2 ? 1 : 2;
+}
 
 __device__ inline d3 vload_d(const float* V, int64_t i) {
   return mkd((double)V[3 * i], (double)V[3 * i + 1], (double)V[3 * i + 2]);
@@ -109,6 +127,7 @@ __device__ inline int build_face(const ScanArgs& P, int64_t f, Poly& q) {
   q.g[3] = B.x; q.g[4] = B.y; q.g[5] = B.z;
   q.g[6] = C.x; q.g[7] = C.y; q.g[8] = C.z;
   q.id = (int)f;
+  set_axes(q, major_axis(n.x, n.y, n.z));
   return q.dim[0] * q.dim[1] * q.dim[2];
 }
 
@@ -164,6 +183,7 @@ __device__ inline int build_edge(const ScanArgs& P, int64_t item, Poly& q) {
   q.g[0] = A.x; q.g[1] = A.y; q.g[2] = A.z;
   q.g[3] = B.x; q.g[4] = B.y; q.g[5] = B.z;
   q.id = (int)(P.nf + e);
+  set_axes(q, us2 > 1e-12 ? major_axis(us.x, us.y, us.z) : major_axis(ed.x, ed.y, ed.z));
   return q.dim[0] * q.dim[1] * q.dim[2];
 }
 
@@ -205,178 +225,179 @@ __device__ inline int build_vertex(const ScanArgs& P, int64_t item, Poly& q) {
   q.cone[3] = hemi ? -2.f : vi.w;
   q.g[0] = A.x; q.g[1] = A.y; q.g[2] = A.z;
   q.id = (int)(P.nf + P.ne + v);
+  set_axes(q, major_axis(ax.x, ax.y, ax.z));
   return q.dim[0] * q.dim[1] * q.dim[2];
-}
-
-__device__ inline long long wave_incl_scan_ll(long long v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    long long t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
 }
 
 __device__ inline int lanes_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// a / b for a >= 0, b >= 1: float reciprocal estimate, then exact correction
-// (one step suffices while a < 2^24, which covers ordinary polyhedra)
-__device__ inline int idiv(int a, int b) {
-  int qq = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
-  int r = a - qq * b;
-  while (r < 0) { qq--; r += b; }
-  while (r >= b) { qq++; r -= b; }
-  return qq;
-}
+constexpr int SMALL_ROWS = 32;  // polyhedra with more rows go to the wavefront kernel
+
+__device__ inline float pick(const float* v, int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
+
+// Per-plane coefficients along a row: the slack-extended test m . p + off >= -eps at
+// cell (t, du, dv) of the row reads  sl * t + su * du + sv * dv + k >= 0.
+struct Rows {
+  float sl[5], inv[5], su[5], sv[5], k[5];
+  float A[3];       // vertex position (ball test)
+  float R2;         // (band*h + eps)^2
+  int nt;           // cells along the row
+};
 
 template <int KIND>
-__global__ __launch_bounds__(64) void k_scan(ScanArgs P) {
+__device__ inline void setup_rows(const Poly& q, float hf, float eps, float whf, Rows& r) {
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
-  constexpr int NG = KIND == KIND_FACE ? 9 : (KIND == KIND_EDGE ? 6 : 3);
-  __shared__ float s_pl[NPL * 4][64];
-  __shared__ float s_g[NG][64];
-  __shared__ float s_cone[4][64];
-  __shared__ int s_anc[3][64];
-  __shared__ int s_nx[64], s_nxy[64], s_id[64];
-  __shared__ long long s_start[65];
-  __shared__ int s_qs[128], s_qi[128], s_qj[128], s_qk[128];
+#pragma unroll
+  for (int i = 0; i < NPL; i++) {
+    r.sl[i] = pick(q.pl[i], q.ra) * hf;
+    r.inv[i] = fabsf(r.sl[i]) > 1e-20f ? 1.f / r.sl[i] : 0.f;
+    r.su[i] = pick(q.pl[i], q.ua) * hf;
+    r.sv[i] = pick(q.pl[i], q.va) * hf;
+    r.k[i] = q.pl[i][3] + eps;
+  }
+  r.A[0] = pick(q.g, q.ra);
+  r.A[1] = pick(q.g, q.ua);
+  r.A[2] = pick(q.g, q.va);
+  r.R2 = (whf + eps) * (whf + eps);
+  r.nt = q.dim[q.ra];
+}
 
-  const int lane = threadIdx.x;
-  const int64_t item = (int64_t)blockIdx.x * 64 + lane;
-  Poly q;
-  int nc = 0;
-  if (item < P.n_items) {
-    if constexpr (KIND == KIND_FACE) nc = build_face(P, item, q);
-    else if constexpr (KIND == KIND_EDGE) nc = build_edge(P, item, q);
-    else nc = build_vertex(P, item, q);
+// cells [t0, t1] of row (du, dv) that can lie in the polyhedron (conservative)
+template <int KIND>
+__device__ inline bool row_range(const Rows& r, int du, int dv, float hf, int& t0, int& t1) {
+  constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
+  float lo = 0.f, hi = (float)(r.nt - 1);
+#pragma unroll
+  for (int i = 0; i < NPL; i++) {
+    const float v = r.su[i] * du + r.sv[i] * dv + r.k[i];
+    if (r.inv[i] > 0.f) lo = fmaxf(lo, -v * r.inv[i]);
+    else if (r.inv[i] < 0.f) hi = fminf(hi, -v * r.inv[i]);
+    else if (v < 0.f) return false;
   }
-  if (nc > 0) {
-#pragma unroll
-    for (int i = 0; i < NPL; i++)
-#pragma unroll
-      for (int c = 0; c < 4; c++) s_pl[i * 4 + c][lane] = q.pl[i][c];
-#pragma unroll
-    for (int i = 0; i < NG; i++) s_g[i][lane] = q.g[i];
-    if constexpr (KIND == KIND_VERT)
-#pragma unroll
-      for (int c = 0; c < 4; c++) s_cone[c][lane] = q.cone[c];
-    s_anc[0][lane] = q.anc[0];
-    s_anc[1][lane] = q.anc[1];
-    s_anc[2][lane] = q.anc[2];
-    s_nx[lane] = q.dim[0];
-    s_nxy[lane] = q.dim[0] * q.dim[1];
-    s_id[lane] = q.id;
+  if constexpr (KIND == KIND_VERT) {  // the ball |p - v| < band*h (+ slack)
+    const float qu = du * hf - r.A[1], qv = dv * hf - r.A[2];
+    const float disc = r.R2 - qu * qu - qv * qv;
+    if (disc < 0.f) return false;
+    const float w = sqrtf(disc) / hf, c = r.A[0] / hf;
+    lo = fmaxf(lo, c - w);
+    hi = fminf(hi, c + w);
   }
-  long long inc = wave_incl_scan_ll(nc);
-  s_start[lane] = inc - nc;
-  if (lane == 63) s_start[64] = inc;
-  __syncthreads();
-  const long long total = s_start[64];
-  const float hf = P.hf, eps = P.eps;
+  // the bounds carry relative rounding far below 1e-4 cells
+  t0 = max(0, (int)ceilf(lo - 1e-4f));
+  t1 = min(r.nt - 1, (int)floorf(hi + 1e-4f));
+  return t0 <= t1;
+}
+
+// exact distance at the candidate cells of one row, and the packed atomic minimum
+template <int KIND>
+__device__ inline unsigned scan_row(const ScanArgs& P, const Poly& q, const Rows& r, int du, int dv) {
+  int t0, t1;
+  if (!row_range<KIND>(r, du, dv, P.hf, t0, t1)) return 0;
   unsigned issued = 0;
-
-  auto process = [&](int sl, int di, int dj, int dk) {
-    f3 p = mk(di * hf, dj * hf, dk * hf);
+  const float hf = P.hf;
+  for (int t = t0; t <= t1; t++) {
+    const int di = q.ra == 0 ? t : (q.ua == 0 ? du : dv);
+    const int dj = q.ra == 1 ? t : (q.ua == 1 ? du : dv);
+    const int dk = q.ra == 2 ? t : (q.ua == 2 ? du : dv);
+    const f3 p = mk(di * hf, dj * hf, dk * hf);
     float d;
     if constexpr (KIND == KIND_FACE) {
-      f3 A = mk(s_g[0][sl], s_g[1][sl], s_g[2][sl]);
-      f3 B = mk(s_g[3][sl], s_g[4][sl], s_g[5][sl]);
-      f3 C = mk(s_g[6][sl], s_g[7][sl], s_g[8][sl]);
       f3 qq;
       float w[3];
-      closest_triangle(p, A, B, C, qq, w);
+      closest_triangle(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]), mk(q.g[6], q.g[7], q.g[8]), qq, w);
       d = norm3(p - qq);
     } else if constexpr (KIND == KIND_EDGE) {
-      f3 A = mk(s_g[0][sl], s_g[1][sl], s_g[2][sl]);
-      f3 B = mk(s_g[3][sl], s_g[4][sl], s_g[5][sl]);
-      float t;
-      d = norm3(p - closest_segment(p, A, B, t));
+      float tt;
+      d = norm3(p - closest_segment(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]), tt));
     } else {
-      d = norm3(p - mk(s_g[0][sl], s_g[1][sl], s_g[2][sl]));
+      const f3 rr = p - mk(q.g[0], q.g[1], q.g[2]);
+      const float ct = q.cone[3];
+      if (ct > -1.f) {  // cone discriminant with slack
+        const float te = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2])) + P.eps;
+        if (!(te >= 0.f && te * te >= ct * ct * dot(rr, rr))) continue;
+      }
+      d = norm3(rr);
     }
     if (d < P.whf) {
-      int i = s_anc[0][sl] + di, j = s_anc[1][sl] + dj, k = s_anc[2][sl] + dk;
-      int64_t bl = (int64_t)(i >> 3) + (int64_t)P.nb[0] * ((j >> 3) + (int64_t)P.nb[1] * (k >> 3));
-      int32_t slot = P.brick_index[bl];
+      const int i = q.anc[0] + di, j = q.anc[1] + dj, k = q.anc[2] + dk;
+      const int64_t bl = (int64_t)(i >> 3) + (int64_t)P.nb[0] * ((j >> 3) + (int64_t)P.nb[1] * (k >> 3));
+      const int32_t slot = P.brick_index[bl];
       if (slot >= 0) {
-        unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned int)s_id[sl];
+        const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned int)q.id;
         atomicMin(&P.keys[(int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)], key);
         issued++;
       }
     }
-  };
+  }
+  return issued;
+}
 
-  int qn = 0;
-  for (long long base = 0; base < total; base += 64) {
-    const long long g = base + lane;
-    bool in = false;
-    int sl = 0, di = 0, dj = 0, dk = 0;
-    if (g < total) {
-      int lo = 0, hi = 63;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (s_start[mid] <= g) lo = mid;
-        else hi = mid - 1;
-      }
-      sl = lo;
-      int loc = (int)(g - s_start[sl]);
-      int nx = s_nx[sl], nxy = s_nxy[sl];
-      dk = idiv(loc, nxy);
-      int rem = loc - dk * nxy;
-      dj = idiv(rem, nx);
-      di = rem - dj * nx;
-      f3 p = mk(di * hf, dj * hf, dk * hf);
-      in = true;
-#pragma unroll
-      for (int i = 0; i < NPL; i++) {
-        float v = s_pl[4 * i][sl] * p.x + s_pl[4 * i + 1][sl] * p.y + s_pl[4 * i + 2][sl] * p.z + s_pl[4 * i + 3][sl];
-        in = in && (v >= -eps);
-      }
-      if constexpr (KIND == KIND_VERT) if (in) {
-        f3 r = p - mk(s_g[0][sl], s_g[1][sl], s_g[2][sl]);
-        float rr = dot(r, r);
-        float lim = P.whf + eps;
-        in = rr < lim * lim;
-        float ct = s_cone[3][sl];
-        if (in && ct > -1.f) {
-          float te = dot(r, mk(s_cone[0][sl], s_cone[1][sl], s_cone[2][sl])) + eps;
-          in = te >= 0.f && te * te >= ct * ct * rr;
-        }
-      }
-    }
-    unsigned long long m = __ballot(in);
-    int pos = qn + lanes_below(m);
-    if (in) {
-      s_qs[pos] = sl;
-      s_qi[pos] = di;
-      s_qj[pos] = dj;
-      s_qk[pos] = dk;
-    }
-    qn += __popcll(m);
-    __syncthreads();
-    if (qn >= 64) {
-      process(s_qs[lane], s_qi[lane], s_qj[lane], s_qk[lane]);
-      __syncthreads();
-      if (lane < qn - 64) {
-        int a0 = s_qs[64 + lane], a1 = s_qi[64 + lane], a2 = s_qj[64 + lane], a3 = s_qk[64 + lane];
-        s_qs[lane] = a0;
-        s_qi[lane] = a1;
-        s_qj[lane] = a2;
-        s_qk[lane] = a3;
-      }
-      qn -= 64;
-      __syncthreads();
+template <int KIND>
+__device__ inline int build_poly(const ScanArgs& P, int64_t item, Poly& q) {
+  if constexpr (KIND == KIND_FACE) return build_face(P, item, q);
+  else if constexpr (KIND == KIND_EDGE) return build_edge(P, item, q);
+  else return build_vertex(P, item, q);
+}
+
+__device__ inline void add_issued(const ScanArgs& P, unsigned issued) {
+  if (!P.counter) return;
+  unsigned long long c = issued;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(P.counter, c);
+}
+
+// one thread per polyhedron; polyhedra with more than SMALL_ROWS rows are appended
+// to the overflow list (one atomic per wavefront)
+template <int KIND>
+__global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
+  const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  Poly q;
+  int nc = item < P.n_items ? build_poly<KIND>(P, item, q) : 0;
+  const int rows = nc > 0 ? q.dim[q.ua] * q.dim[q.va] : 0;
+  const bool big = rows > SMALL_ROWS;
+  const unsigned long long m = __ballot(big);
+  if (m) {
+    int base = 0;
+    const int leader = __ffsll((long long)m) - 1;
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(P.big_count, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (big) P.big_items[base + lanes_below(m)] = (int32_t)item;
+  }
+  unsigned issued = 0;
+  if (nc > 0 && !big) {
+    Rows r;
+    setup_rows<KIND>(q, P.hf, P.eps, P.whf, r);
+    for (int dv = 0; dv < q.dim[q.va]; dv++)
+      for (int du = 0; du < q.dim[q.ua]; du++) issued += scan_row<KIND>(P, q, r, du, dv);
+  }
+  add_issued(P, issued);
+}
+
+// a wavefront per polyhedron of the overflow list, lanes striding over its rows;
+// every wavefront leaves once the list (final before this launch) is exhausted
+template <int KIND>
+__global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
+  const int lane = threadIdx.x;
+  const int32_t n_big = *P.big_count;
+  unsigned issued = 0;
+  for (int32_t w = blockIdx.x; w < n_big; w += gridDim.x) {
+    Poly q;
+    if (build_poly<KIND>(P, P.big_items[w], q) <= 0) continue;
+    Rows r;
+    setup_rows<KIND>(q, P.hf, P.eps, P.whf, r);
+    const int nu = q.dim[q.ua], rows = nu * q.dim[q.va];
+    for (int row = lane; row < rows; row += 64) {
+      const int dv = row / nu, du = row - dv * nu;
+      issued += scan_row<KIND>(P, q, r, du, dv);
     }
   }
-  if (lane < qn) process(s_qs[lane], s_qi[lane], s_qj[lane], s_qk[lane]);
-  if (P.counter) {
-    unsigned long long c = issued;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
-    if (lane == 0 && c) atomicAdd(P.counter, c);
-  }
+  add_issued(P, issued);
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
@@ -494,7 +515,7 @@ using namespace csc;
 namespace {
 size_t au(size_t x) { return (x + 255) & ~(size_t)255; }
 struct WsLayout {
-  size_t keys, cnt, scan, total;
+  size_t keys, cnt, scan, big, total;
 };
 WsLayout ws_layout(const csc_features* f) {
   WsLayout L;
@@ -502,7 +523,10 @@ WsLayout ws_layout(const csc_features* f) {
   L.keys = 0;
   L.cnt = au(sizeof(unsigned long long) * (size_t)(nb * BRICK_CELLS + 1));
   L.scan = L.cnt + au(sizeof(int32_t) * (size_t)(nb + 1));
-  L.total = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(nb + 1) + 3 * sizeof(unsigned long long));
+  L.big = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(nb + 1) + 3 * sizeof(unsigned long long));
+  int64_t mx = f->nf > f->n_epoly ? f->nf : f->n_epoly;
+  mx = mx > f->n_vpoly ? mx : f->n_vpoly;
+  L.total = L.big + au(sizeof(int32_t) * (size_t)(mx + 2));
   return L;
 }
 }  // namespace
@@ -546,32 +570,41 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, unsigned lon
   return A;
 }
 
-// key init and the three scan launches; counters (3 slots) may be null
-void run_scans(const csc_features* f, unsigned long long* keys, unsigned long long* counters, hipStream_t s) {
+constexpr int BIG_BLOCKS = 2048;
+
+template <int KIND>
+void launch_kind(ScanArgs A, int stage, hipStream_t s) {
+  StageTimer t(stage, s);
+  k_zero_i32<<<1, 64, 0, s>>>(A.big_count, 1);
+  k_scan_small<KIND><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
+  k_scan_big<KIND><<<BIG_BLOCKS, 64, 0, s>>>(A);
+}
+
+// key init and the scan launches of the three kinds; counters (3 slots) may be null.
+// big: overflow list of at least max(F, edge polys, vertex polys) + 1 ints.
+void run_scans(const csc_features* f, unsigned long long* keys, unsigned long long* counters, int32_t* big,
+               hipStream_t s) {
   const int64_t nk = f->n_bricks * BRICK_CELLS;
   {
     StageTimer t(TS_INIT, s);
     k_fill_u64<<<grid_1d(nk, 256), 256, 0, s>>>(keys, nk, EMPTY_KEY);
   }
   ScanArgs A = scan_args(f, keys, counters);
-  {
-    StageTimer t(TS_SCAN_FACE, s);
-    A.n_items = f->nf;
-    k_scan<KIND_FACE><<<grid_1d(f->nf, 64), 64, 0, s>>>(A);
-  }
+  A.big_count = big;
+  A.big_items = big + 1;
+  A.n_items = f->nf;
+  launch_kind<KIND_FACE>(A, TS_SCAN_FACE, s);
   if (f->n_epoly > 0) {
-    StageTimer t(TS_SCAN_EDGE, s);
     A.items = f->epoly;
     A.n_items = f->n_epoly;
     A.counter = counters ? counters + 1 : nullptr;
-    k_scan<KIND_EDGE><<<grid_1d(f->n_epoly, 64), 64, 0, s>>>(A);
+    launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, s);
   }
   if (f->n_vpoly > 0) {
-    StageTimer t(TS_SCAN_VERT, s);
     A.items = f->vpoly;
     A.n_items = f->n_vpoly;
     A.counter = counters ? counters + 2 : nullptr;
-    k_scan<KIND_VERT><<<grid_1d(f->n_vpoly, 64), 64, 0, s>>>(A);
+    launch_kind<KIND_VERT>(A, TS_SCAN_VERT, s);
   }
 }
 
@@ -593,7 +626,7 @@ extern "C" int csc_scan_convert(const csc_features* f, void* workspace_d, size_t
     int64_t nd = (int64_t)f->grid.n[0] * f->grid.n[1] * f->grid.n[2];
     k_fill_f32<<<grid_1d(nd, 256), 256, 0, s>>>(dense_d, nd, __builtin_inff());
   }
-  if (nk > 0) run_scans(f, keys, nullptr, s);
+  if (nk > 0) run_scans(f, keys, nullptr, (int32_t*)(W + L.big), s);
   hipError_t e;
   {
     StageTimer t(TS_COUNT, s);
@@ -642,7 +675,7 @@ extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, 
   unsigned long long* ctr = (unsigned long long*)(W + L.scan);  // reuses the scan scratch
   hipError_t e = hipMemsetAsync(ctr, 0, 3 * sizeof(unsigned long long), s);
   if (e != hipSuccess) return fail_hip(e);
-  if (f->n_bricks > 0) run_scans(f, keys, ctr, s);
+  if (f->n_bricks > 0) run_scans(f, keys, ctr, (int32_t*)(W + L.big), s);
   unsigned long long h[3];
   e = hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

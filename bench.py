@@ -1,13 +1,16 @@
 #!/usr/bin/env python
 """Throughput of the CSC narrow-band SDF path on one MI355X.
 
-One step = the whole hot path over one synthetic mesh already resident in HBM:
-feature build (adjacency, classes, polyhedron lists, bricks), scan conversion of
-every polyhedron with the packed atomicMin, sign pass and band compaction, then
-the adjoint of loss = sum of SDF^2 over the band into the vertex gradient.
-value = band cells / second of that forward+backward step.
+One step = the whole hot path over one batch of synthetic meshes already
+resident in HBM: feature build (validation, adjacency, classes, polyhedron
+lists, bricks), scan conversion of every polyhedron with the packed atomicMin,
+sign pass and band compaction, then the adjoint of loss = sum of SDF^2 over the
+band into the vertex gradient. value = band cells / second of that
+forward+backward step.
 
-Prints one JSON line (rank 0). See --help for the workloads.
+Workloads: the 64-mesh batch (default; the batched step is one captured graph
+replayed, compared with 64 per-mesh plain launches) and single large meshes.
+Prints one JSON line. See --help.
 """
 import argparse
 import hashlib
@@ -22,6 +25,9 @@ sys.path.insert(0, ROOT)
 METRIC = "narrow-band cells/sec (fwd, fwd+bwd), batched vs per-mesh, at 1e-5·h error"
 WORKLOADS = {
     # name: (config number, description)
+    "batch64": (4, "64 meshes (icospheres L2-6, tori 2k-200k triangles, SH-displaced spheres degree <= 8 at 5%), "
+                   "each with its own N^3 grid, N in [64, 256], band 3 cells, fwd+bwd of sum SDF^2; one batched "
+                   "graph replay per step"),
     "sh_sphere9_1024": (5, "displaced sphere: icosphere L9 (5,242,880 triangles), SH degree 16 at 5%, "
                            "1024^3 grid, band 3 cells, fwd+bwd of sum SDF^2, per-mesh"),
     "noisy_torus_512": (3, "noisy torus: 360,000 triangles, tube-normal noise U(+-0.01), 512^3 grid, band 3, fwd+bwd"),
@@ -98,17 +104,218 @@ def cpu_baseline(v, f, grid, budget_s=15.0):
                       f"one-time edge table and normals excluded"}
 
 
+def batch_algorithmic_bytes(stage, nf, nv, n_epoly, n_vpoly, atomics, band_cells, vert_refs, n_bricks):
+    info = {"n_faces": nf, "n_edges": 3 * nf // 2, "n_edge_polyhedra": n_epoly, "n_vertex_polyhedra": n_vpoly,
+            "n_bricks": n_bricks}
+    return algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv)
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_1903_00353_amd as P
+
+    cfg, desc = WORKLOADS["batch64"]
+    name, meshes, grids = meshgen.make_config(cfg)
+    dev = torch.device("cuda:0")
+    B = P.Batch(meshes, grids, device=dev, backward=True, graph_safe=True)
+    info = B.f.info()
+    atomics = P.csc_scan_convert_count(B.f, B.workspace)
+    B.step()
+    torch.cuda.synchronize()
+    B.check()
+    off = B.band_off.cpu().numpy()
+    M = int(off[-1])
+    feat = B.out[1][:M].cpu().numpy()
+    # weighted vertices per band cell from each mesh's own feature numbering
+    vert_refs = 0
+    for m, (v, f) in enumerate(meshes):
+        fe = feat[off[m]:off[m + 1]]
+        F, E = f.shape[0], 3 * f.shape[0] // 2
+        vert_refs += int(3 * (fe < F).sum() + 2 * ((fe >= F) & (fe < F + E)).sum() + (fe >= F + E).sum())
+
+    # batched: one captured graph per step
+    B.capture()
+    for _ in range(args.warmup):
+        B.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.check()
+    ms_graph = (t1 - t0) * 1e3 / args.steps
+
+    # batched eager steps with per-stage events (roofline of the dominant kernel)
+    for _ in range(max(1, args.warmup)):
+        B.step()
+    torch.cuda.synchronize()
+    P.csc_timing_reset()
+    P.csc_timing_enable(True)
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        B.step()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    P.csc_timing_enable(False)
+    stages = P.csc_timing_read()
+    ms_eager = (t3 - t2) * 1e3 / args.steps
+
+    # per-mesh plain launches: 64 x (build, scan, adjoint), handles and buffers reused
+    per = []
+    for m, (v, f) in enumerate(meshes):
+        vt, tt = B.verts[sum(B.nv[:m]):sum(B.nv[:m + 1])], torch.from_numpy(f).to(dev)
+        h = P.csc_build_features(vt, tt, grids[m])
+        nbytes, mx = P.csc_scan_convert_workspace(h)
+        o = (torch.empty(mx, dtype=torch.float32, device=dev), torch.empty(mx, dtype=torch.int32, device=dev),
+             torch.empty(mx, dtype=torch.int32, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+        per.append((vt, tt, grids[m], h, torch.empty(nbytes, dtype=torch.uint8, device=dev), o,
+                    torch.empty(mx, dtype=torch.float32, device=dev), torch.zeros_like(vt)))
+
+    def per_mesh_step():
+        for vt, tt, g, h, ws, o, gsd, gv in per:
+            P.csc_build_features(vt, tt, g, reuse=h)
+            band = P.csc_scan_convert(h, ws, o, sync_count=False)
+            torch.mul(o[0], 2.0, out=gsd)
+            gv.zero_()
+            P.csc_sdf_backward(h, band, gsd, gv, n_band_d=o[3])
+
+    for _ in range(args.warmup):
+        per_mesh_step()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(args.steps):
+        per_mesh_step()
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    ms_per_mesh = (t5 - t4) * 1e3 / args.steps
+    M_per = sum(int(x[5][3].item()) for x in per)
+
+    avg = {k: (ms / c if c else 0.0) for k, (ms, c) in stages.items()}
+    dom = max(SINGLE_KERNEL_STAGES, key=lambda k: avg[k])
+    alg = batch_algorithmic_bytes(dom, int(info["n_faces"]), int(info["n_vertices"]),
+                                  int(info["n_edge_polyhedra"]), int(info["n_vertex_polyhedra"]), atomics, M,
+                                  vert_refs, int(info["n_bricks"]))
+    achieved = alg / (avg[dom] * 1e-3) / 1e9
+    res = {
+        "metric": METRIC,
+        "value": M / (ms_graph * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_graph,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch64: {desc}", "meshes": len(meshes), "faces": int(info["n_faces"]),
+                   "vertices": int(info["n_vertices"]), "grids": [int(g.n[0]) for g in grids], "band_cells": 3.0,
+                   "band_size": M, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("batch64", dom),
+                     "algorithmic_bytes": alg, "avg_ms": avg[dom], "measured_on": "eager batched steps"},
+        "batched_eager": {"value": M / (ms_eager * 1e-3), "ms_per_step": ms_eager},
+        "per_mesh": {"value": M_per / (ms_per_mesh * 1e-3), "ms_per_step": ms_per_mesh, "band_size": M_per},
+        "speedup_batched_vs_per_mesh": ms_per_mesh / ms_graph,
+        "stages_ms": {k: round(x, 4) for k, x in avg.items()},
+        "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2]},
+        "features": info,
+        "kernel_source_sha": kernel_source_sha(),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_batch(meshes, grids, args.cpu_budget)
+    print(json.dumps(res))
+
+
+def cpu_baseline_batch(meshes, grids, budget_s=15.0):
+    """The oracle on the host cores over whole meshes of the batch, in order, until
+    about budget_s seconds of band computation have been spent."""
+    import oracle
+    cells, spent, done, threads = 0, 0.0, 0, 1
+    for (v, f), g in zip(meshes, grids):
+        om = oracle.OracleMesh(v, f)
+        t0 = time.perf_counter()
+        b = om.band(g)
+        spent += time.perf_counter() - t0
+        cells += int(((b["flags"] & oracle.FLAG_IN_BAND) > 0).sum())
+        threads = b["threads"]
+        done += 1
+        if spent >= budget_s:
+            break
+    return {"value": cells / spent, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {done} of {len(meshes)} meshes of the batch, whole grids ({cells} band cells, "
+                      f"{spent:.1f} s); FP64 exact distance with bounding-box cull, pseudonormal sign; "
+                      f"one-time edge tables and normals excluded"}
+
+
+def summarize_counters(args):
+    """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this benchmark and of the
+    plain-copy calibration into bytes per launch of each kernel (profiles/traffic.json)
+    and a short text summary. FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each
+    divided by what the same counter reports per byte of the 1 GiB copy."""
+    import csv
+
+    def per_kernel(path):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = per_kernel(args.fetch_csv), per_kernel(args.write_csv)
+    cf, cw = per_kernel(args.copy_fetch_csv), per_kernel(args.copy_write_csv)
+    copy_name = max(cf, key=lambda k: cf[k] if "copyBuffer" in k else -1)
+    gib_kib = float(1 << 20)  # the calibration copies 1 GiB: 1 GiB read, 1 GiB written
+    fetch_scale, write_scale = cf[copy_name] / gib_kib, cw[copy_name] / gib_kib
+    symbol_of = {"scan_faces": "k_scan_small<0>", "scan_edges": "k_scan_small<1>", "scan_vertices": "k_scan_small<2>",
+                 "sign": "k_sign", "backward": "k_backward", "init_keys": "k_init_keys"}
+    out_path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(out_path)) if os.path.exists(out_path) else {}
+    entry = {}
+    lines = [f"# HBM traffic per launch, workload {args.workload}",
+             f"calibration ({copy_name}, 1 GiB copy): FETCH_SIZE {cf[copy_name]:.0f} KiB -> scale {fetch_scale:.4f}; "
+             f"WRITE_SIZE {cw[copy_name]:.0f} KiB -> scale {write_scale:.4f}",
+             "kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes/launch (scaled)"]
+    for stage, sym in symbol_of.items():
+        names = [k for k in fetch if (sym + "(") in k]
+        if not names:
+            continue
+        k = names[0]
+        b = (fetch[k] / fetch_scale + write.get(k, 0.0) / write_scale) * 1024.0
+        entry[stage] = {"kernel": k, "fetch_kib": fetch[k], "write_kib": write.get(k, 0.0),
+                        "fetch_scale": fetch_scale, "write_scale": write_scale, "bytes_per_launch": b,
+                        "source_sha": kernel_source_sha()}
+        lines.append(f"{k} | {fetch[k]:.0f} | {write.get(k, 0.0):.0f} | {b:.4g}")
+    rec[args.workload] = entry
+    os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sh_sphere9_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batch64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--summarize-counters", action="store_true",
+                    help="write profiles/traffic.json from rocprofv3 counter CSVs (see --*-csv)")
+    ap.add_argument("--fetch-csv")
+    ap.add_argument("--write-csv")
+    ap.add_argument("--copy-fetch-csv")
+    ap.add_argument("--copy-write-csv")
     args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this implementation runs on one GPU; multi-GPU runs are not part of it "
@@ -131,6 +338,8 @@ def main():
     import meshgen
     import paper_1903_00353_amd as P
 
+    if args.workload == "batch64":
+        return bench_batch(args)
     cfg, desc = WORKLOADS[args.workload]
     name, meshes, grids = meshgen.make_config(cfg)
     v, f = meshes[0]

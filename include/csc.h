@@ -96,7 +96,8 @@ typedef struct csc_feature_info {
  * grid: cell geometry and band width. opt: NULL for defaults.
  * out: if *out is a handle from an earlier call, it is rebuilt in place (its
  * device memory is reused when large enough); else a new handle is made.
- * Synchronises `stream` once (to read back error flags and counts).
+ * Synchronises `stream` once at the end (to read back error flags and counts).
+ * The triangles are copied (with validated indices) into the handle.
  * Errors: INVALID_ARG, NONMANIFOLD, INCONSISTENT_ORIENTATION, DEGENERATE_FACE,
  * GRID_TOO_LARGE, OUT_OF_MEMORY, HIP_ERROR, UNSUPPORTED_DEVICE. On error a new
  * handle is not returned (*out unchanged) and a reused handle is left unusable
@@ -105,11 +106,41 @@ typedef struct csc_feature_info {
 int csc_build_features(const float* verts_d, int64_t nv, const int32_t* tris_d, int64_t nf,
                        const csc_grid* grid, const csc_options* opt, void* stream, csc_features** out);
 
-/* Copy the counts of a built handle into *info. */
+/*
+ * Batched build: n_meshes closed surfaces, each with its own grid, in one set of
+ * launches. verts_d: float32 [sum nv][3], the meshes' vertices one after the
+ * other; tris_d: int32 [sum nf][3], each mesh's triangles one after the other,
+ * indexing that mesh's own vertices (0 .. nv[m]-1); nv, nf, grids: host arrays
+ * of n_meshes entries. Feature ids and cell indices in the outputs are those of
+ * each mesh on its own. flags:
+ *   CSC_BUILD_NO_SYNC: queue the device work and return without synchronising;
+ *     *out must be a handle already built (synchronously) for the same sizes,
+ *     grids and options, so that nothing is allocated or copied from the host:
+ *     the call can then be captured into a graph. Errors are read later by
+ *     csc_features_sync.
+ *   CSC_BUILD_GRAPH_SAFE: group corners without the library radix sort (which
+ *     clears memory with memset nodes); required when capturing.
+ * Errors as csc_build_features.
+ */
+#define CSC_BUILD_NO_SYNC 1
+#define CSC_BUILD_GRAPH_SAFE 2
+int csc_build_features_batched(const float* verts_d, const int32_t* tris_d, const int64_t* nv, const int64_t* nf,
+                               const csc_grid* grids, int32_t n_meshes, const csc_options* opt, int32_t flags,
+                               void* stream, csc_features** out);
+
+/* Wait for the work queued on `stream`, read the handle's error flags and counts
+ * back (after a CSC_BUILD_NO_SYNC build, or after a scan to detect a band store
+ * too small for the bricks: CSC_WORKSPACE_TOO_SMALL). */
+int csc_features_sync(csc_features* f, void* stream);
+
+/* Copy the counts of a built and synchronised handle into *info. */
 int csc_features_info(const csc_features* f, csc_feature_info* info);
 
 /* Device workspace (bytes) csc_scan_convert needs, and the largest band size it
- * can return (the length the sdf/feat/cell outputs must have). */
+ * can return (the length the sdf/feat/cell outputs must have). The workspace
+ * holds the band bricks counted by the last synchronised build (all bricks of
+ * the grids if the handle was never synchronised). A larger workspace holds more
+ * bricks; the outputs must then have 512 entries per brick it holds. */
 int csc_scan_convert_workspace(const csc_features* f, size_t* bytes, int64_t* max_band_cells);
 
 /*
@@ -135,6 +166,17 @@ int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, 
                      int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream);
 
 /*
+ * Batched scan conversion (as csc_scan_convert for every mesh of a batched
+ * handle, in one set of launches, with no host synchronisation). The band of
+ * mesh m is entries [band_off_d[m], band_off_d[m+1]) of sdf_d / feat_d / cell_d,
+ * with that mesh's own feature ids and cell indices. band_off_d: device int64
+ * [n_meshes+1]. Bricks beyond the workspace's capacity are dropped and flagged
+ * (csc_features_sync then returns CSC_WORKSPACE_TOO_SMALL).
+ */
+int csc_scan_convert_batched(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d,
+                             int32_t* feat_d, int32_t* cell_d, int64_t* band_off_d, void* stream);
+
+/*
  * Adjoint of the band values with respect to the vertex positions. For each of
  * the band cells c (sdf_d, feat_d, cell_d as written by csc_scan_convert):
  * with q the closest point of the cell centre on feature feat_d[c] and w_k the
@@ -146,11 +188,18 @@ int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, 
  * n_band: number of band cells, or (with n_band_d) an upper bound on it.
  * n_band_d: NULL, or the device int64 written by csc_scan_convert; the count is
  * then read on the device, so no host synchronisation is needed in between.
- * Errors: INVALID_ARG, HIP_ERROR.
+ * Single-mesh handles only. Errors: INVALID_ARG, HIP_ERROR.
  */
 int csc_sdf_backward(const csc_features* f, const float* sdf_d, const int32_t* feat_d, const int32_t* cell_d,
                      int64_t n_band, const int64_t* n_band_d, const float* grad_sdf_d, float* grad_verts_d,
                      void* stream);
+
+/* Batched adjoint: as csc_sdf_backward over the band written by
+ * csc_scan_convert_batched (band_off_d from that call; max_band an upper bound
+ * on the total band size). grad_verts_d: float32 [sum nv][3], accumulated. */
+int csc_sdf_backward_batched(const csc_features* f, const float* sdf_d, const int32_t* feat_d,
+                             const int32_t* cell_d, int64_t max_band, const int64_t* band_off_d,
+                             const float* grad_sdf_d, float* grad_verts_d, void* stream);
 
 /*
  * Diagnostics: run only the key initialisation and the three scan launches and

@@ -53,13 +53,15 @@ class _Band(C.Structure):
                 ("feat", C.POINTER(C.c_int32)), ("flags", C.POINTER(C.c_uint8)), ("threads", C.c_int32)]
 
 
-def _load():
+def _load(path=None):
     global _lib
-    if _lib is not None:
+    if _lib is not None and path is None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = C.CDLL(_LIB)
+    if path is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        path = _LIB
+    lib = C.CDLL(path)
     P = C.c_void_p
     lib.oracle_edges.restype = C.c_int64
     lib.oracle_edges.argtypes = [P, C.c_int64, C.c_int64, P, P]
@@ -82,6 +84,25 @@ def _load():
     lib.oracle_max_threads.restype = C.c_int
     _lib = lib
     return lib
+
+
+class library:
+    """Context manager: run the oracle from another compiled copy (used by the tests
+    that plant a mistake in a copy of the source and check that a pin catches it)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.prev = _lib
+        _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.prev
+        return False
 
 
 def _p(a):

@@ -60,7 +60,10 @@ class csc_feature_info(C.Structure):
 EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspace", "csc_scan_convert",
            "csc_sdf_backward", "csc_features_free", "csc_error_string", "csc_last_hip_error",
            "csc_classify_edge", "csc_classify_vertex", "csc_scan_convert_count", "csc_timing_enable",
-           "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name"]
+           "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name", "csc_build_features_batched",
+           "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched"]
+CSC_BUILD_NO_SYNC = 1
+CSC_BUILD_GRAPH_SAFE = 2
 N_STAGES = 8
 
 _lib = None
@@ -96,6 +99,15 @@ def lib():
     L.csc_timing_read.argtypes = [P, P, C.c_int32]
     L.csc_timing_stage_name.restype = C.c_char_p
     L.csc_timing_stage_name.argtypes = [C.c_int32]
+    L.csc_build_features_batched.restype = C.c_int
+    L.csc_build_features_batched.argtypes = [P, P, P, P, C.POINTER(csc_grid), C.c_int32, C.POINTER(csc_options),
+                                             C.c_int32, P, C.POINTER(C.c_void_p)]
+    L.csc_features_sync.restype = C.c_int
+    L.csc_features_sync.argtypes = [P, P]
+    L.csc_scan_convert_batched.restype = C.c_int
+    L.csc_scan_convert_batched.argtypes = [P, P, C.c_size_t, P, P, P, P, P]
+    L.csc_sdf_backward_batched.restype = C.c_int
+    L.csc_sdf_backward_batched.argtypes = [P, P, P, P, C.c_int64, P, P, P, P]
     L.csc_features_free.restype = None
     L.csc_features_free.argtypes = [P]
     L.csc_error_string.restype = C.c_char_p
@@ -292,6 +304,119 @@ def csc_timing_stage_name(i: int) -> str:
 
 def csc_features_info(f: Features) -> dict:
     return f.info()
+
+
+def csc_features_sync(f: Features, stream=None):
+    _check(lib().csc_features_sync(f.handle, _stream(stream)), "csc_features_sync")
+
+
+def csc_build_features_batched(verts, tris, nv, nf, grids, options=None, flags=0, stream=None,
+                               reuse: Features | None = None) -> Features:
+    """verts: [sum nv, 3] float32, tris: [sum nf, 3] int32 (each mesh's own indices),
+    nv / nf: per-mesh counts, grids: per-mesh grid objects."""
+    _check_mesh(verts, tris)
+    n = len(grids)
+    if len(nv) != n or len(nf) != n or n == 0:
+        raise ValueError("nv, nf and grids must have one entry per mesh")
+    g = (csc_grid * n)(*[make_grid(x) for x in grids])
+    nva = (C.c_int64 * n)(*[int(x) for x in nv])
+    nfa = (C.c_int64 * n)(*[int(x) for x in nf])
+    opt = options if options is not None else make_options()
+    prev = reuse.handle if reuse is not None else None
+    h = C.c_void_p(prev.value if isinstance(prev, C.c_void_p) else prev)
+    code = lib().csc_build_features_batched(_ptr(verts), _ptr(tris), nva, nfa, g, n, C.byref(opt), int(flags),
+                                            _stream(stream), C.byref(h))
+    if code != 0:
+        raise CscError(code, "csc_build_features_batched")
+    if reuse is not None:
+        reuse.handle, reuse.verts, reuse.tris, reuse.grid, reuse.options = h, verts, tris, g, opt
+        return reuse
+    return Features(h, verts, tris, g, opt)
+
+
+def csc_scan_convert_batched(f: Features, workspace, out, band_off, stream=None):
+    sdf, feat, cell = out
+    code = lib().csc_scan_convert_batched(f.handle, _ptr(workspace), workspace.numel(), _ptr(sdf), _ptr(feat),
+                                          _ptr(cell), _ptr(band_off), _stream(stream))
+    _check(code, "csc_scan_convert_batched")
+
+
+def csc_sdf_backward_batched(f: Features, out, band_off, grad_sdf, grad_verts, stream=None):
+    sdf, feat, cell = out
+    code = lib().csc_sdf_backward_batched(f.handle, _ptr(sdf), _ptr(feat), _ptr(cell), int(sdf.numel()),
+                                          _ptr(band_off), _ptr(grad_sdf), _ptr(grad_verts), _stream(stream))
+    _check(code, "csc_sdf_backward_batched")
+
+
+class Batch:
+    """Many meshes, each with its own grid, processed by one set of launches.
+
+    ``meshes``: list of (verts [nv,3] float32, tris [nf,3] int32) arrays or tensors.
+    After ``Batch(...)`` (one synchronised build that sizes every buffer), each
+    ``step()`` runs build + scan conversion (+ adjoint of sum SDF^2) without any
+    host synchronisation or allocation, so it can be captured in a graph
+    (``capture()``) and replayed (``replay()``)."""
+
+    def __init__(self, meshes, grids, options=None, device="cuda", backward=True, graph_safe=True):
+        import torch
+        self.grids = list(grids)
+        self.nv = [int(m[0].shape[0]) for m in meshes]
+        self.nf = [int(m[1].shape[0]) for m in meshes]
+        self.verts = torch.cat([torch.as_tensor(m[0], dtype=torch.float32).reshape(-1, 3) for m in meshes]).to(device)
+        self.tris = torch.cat([torch.as_tensor(m[1], dtype=torch.int32).reshape(-1, 3) for m in meshes]).to(device)
+        self.verts, self.tris = self.verts.contiguous(), self.tris.contiguous()
+        self.options = options
+        self.flags = CSC_BUILD_GRAPH_SAFE if graph_safe else 0
+        self.f = csc_build_features_batched(self.verts, self.tris, self.nv, self.nf, self.grids, options,
+                                            flags=self.flags)
+        nbytes, mx = csc_scan_convert_workspace(self.f)
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        self.out = (torch.empty(max(mx, 1), dtype=torch.float32, device=device),
+                    torch.empty(max(mx, 1), dtype=torch.int32, device=device),
+                    torch.empty(max(mx, 1), dtype=torch.int32, device=device))
+        self.band_off = torch.zeros(len(self.grids) + 1, dtype=torch.int64, device=device)
+        self.backward = backward
+        self.grad_sdf = torch.empty_like(self.out[0])
+        self.grad_verts = torch.zeros_like(self.verts)
+        self.graph = None
+
+    def step(self):
+        """Build, scan conversion and (if enabled) the adjoint of sum SDF^2; queued only."""
+        import torch
+        csc_build_features_batched(self.verts, self.tris, self.nv, self.nf, self.grids, self.options,
+                                   flags=self.flags | CSC_BUILD_NO_SYNC, reuse=self.f)
+        csc_scan_convert_batched(self.f, self.workspace, self.out, self.band_off)
+        if self.backward:
+            torch.mul(self.out[0], 2.0, out=self.grad_sdf)
+            self.grad_verts.zero_()
+            csc_sdf_backward_batched(self.f, self.out, self.band_off, self.grad_sdf, self.grad_verts)
+
+    def capture(self):
+        import torch
+        self.step()  # warm up outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def check(self):
+        """Synchronise and raise if the last build or scan reported an error."""
+        csc_features_sync(self.f)
+
+    def band(self, m):
+        """(sdf, feat, cell) tensors of mesh m (synchronises to read the offsets)."""
+        off = self.band_off.cpu().tolist()
+        a, b = off[m], off[m + 1]
+        return self.out[0][a:b], self.out[1][a:b], self.out[2][a:b]
+
+    def grad(self, m):
+        a = sum(self.nv[:m])
+        return self.grad_verts[a:a + self.nv[m]]
 
 
 def csc_features_free(f: Features):

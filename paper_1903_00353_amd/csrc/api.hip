@@ -60,7 +60,7 @@ extern "C" const char* csc_error_string(int code) {
 extern "C" const char* csc_last_hip_error(void) { return g_last_hip; }
 
 extern "C" int csc_features_info(const csc_features* f, csc_feature_info* info) {
-  if (!f || !f->valid || !info) return CSC_INVALID_ARG;
+  if (!f || !f->synced || !info) return CSC_INVALID_ARG;
   *info = f->info;
   return CSC_OK;
 }

@@ -11,18 +11,18 @@ namespace csc {
 
 struct BwdArgs {
   const float* V;
-  const int32_t* T;
+  const int32_t* T;          // global vertex indices
   const int4* edges;
+  const MeshDesc* md;
   const float* sdf;
-  const int32_t* feat;
-  const int32_t* cell;
+  const int32_t* feat;       // each mesh's own feature ids
+  const int32_t* cell;       // each mesh's own linear cell index
   const float* gsdf;
-  const int64_t* n_dev;  // optional device-side band size
+  const int64_t* band_off;   // [n_meshes+1] band offsets, or null (one mesh)
+  const int64_t* n_dev;      // one mesh: optional device band size
   float* grad;
-  int64_t n, nf, ne, nv;
-  double o[3];
-  double h;
-  int nx, ny;
+  int64_t n;                 // launch bound (and band size if nothing is on the device)
+  int n_meshes;
 };
 
 __device__ inline f3 relb(const float* V, int64_t i, d3 c) {
@@ -34,7 +34,7 @@ constexpr int BW_SLOTS = 1024;  // > 3 * BW_THREADS insertions: probing always e
 
 // One band cell per thread. Each block first sums its cells' contributions per
 // vertex in an LDS hash table (band cells are ordered by brick, so a block's cells
-// share most of their vertices), then adds one value per vertex and axis globally.
+// share many of their vertices), then adds one value per vertex and axis globally.
 __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
   __shared__ int s_key[BW_SLOTS];
   __shared__ float s_acc[3][BW_SLOTS];
@@ -47,42 +47,46 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)BW_THREADS + threadIdx.x;
   int64_t lim = P.n;
-  if (P.n_dev && *P.n_dev < lim) lim = *P.n_dev;
+  if (P.band_off) lim = P.band_off[P.n_meshes] < lim ? P.band_off[P.n_meshes] : lim;
+  else if (P.n_dev && *P.n_dev < lim) lim = *P.n_dev;
   const float gs = i < lim ? P.gsdf[i] : 0.f;
   if (gs != 0.f) {
-    const int32_t lin = P.cell[i], id = P.feat[i];
-    const int ci = lin % P.nx, cj = (lin / P.nx) % P.ny, ck = lin / (P.nx * P.ny);
-    const d3 c = mkd(P.o[0] + (ci + 0.5) * P.h, P.o[1] + (cj + 0.5) * P.h, P.o[2] + (ck + 0.5) * P.h);
+    const int m = P.band_off ? find_segment(P.band_off, P.n_meshes + 1, i) : 0;
+    const MeshDesc& G = P.md[m];
+    const int32_t lin = P.cell[i], lf = P.feat[i];
+    const int ci = lin % G.n[0], cj = (lin / G.n[0]) % G.n[1], ck = lin / (G.n[0] * G.n[1]);
+    const d3 c = mkd(G.origin[0] + (ci + 0.5) * G.h, G.origin[1] + (cj + 0.5) * G.h, G.origin[2] + (ck + 0.5) * G.h);
     const f3 zero = mk(0.f, 0.f, 0.f);
     f3 q;
     float w[3] = {0.f, 0.f, 0.f};
     int32_t vid[3] = {0, 0, 0};
-    int m;
-    if (id < P.nf) {
-      for (int j = 0; j < 3; j++) vid[j] = P.T[3 * (int64_t)id + j];
+    int mcount;
+    if (lf < G.nf) {
+      const int64_t f = (int64_t)G.f_off + lf;
+      for (int j = 0; j < 3; j++) vid[j] = P.T[3 * f + j];
       closest_triangle(zero, relb(P.V, vid[0], c), relb(P.V, vid[1], c), relb(P.V, vid[2], c), q, w);
-      m = 3;
-    } else if (id < P.nf + P.ne) {
-      int4 E = P.edges[id - P.nf];
+      mcount = 3;
+    } else if (lf < G.nf + G.ne) {
+      int4 E = P.edges[(int64_t)G.e_off + (lf - G.nf)];
       vid[0] = E.x;
       vid[1] = E.y;
       float t;
       q = closest_segment(zero, relb(P.V, E.x, c), relb(P.V, E.y, c), t);
       w[0] = 1.f - t;
       w[1] = t;
-      m = 2;
+      mcount = 2;
     } else {
-      vid[0] = (int32_t)(id - P.nf - P.ne);
+      vid[0] = G.v_off + (lf - G.nf - G.ne);
       q = relb(P.V, vid[0], c);
       w[0] = 1.f;
-      m = 1;
+      mcount = 1;
     }
     const float d = norm3(q);
     if (d > 0.f) {
       const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
       // c - q = -q in this frame; g = s (c - q) / |c - q|
       const f3 g = q * (-s / d);
-      for (int k = 0; k < m; k++) {
+      for (int k = 0; k < mcount; k++) {
         const float f = -gs * w[k];
         if (f == 0.f) continue;
         unsigned h = ((unsigned)vid[k] * 2654435761u) >> 22;
@@ -112,33 +116,49 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
 
 using namespace csc;
 
-extern "C" int csc_sdf_backward(const csc_features* f, const float* sdf_d, const int32_t* feat_d,
-                                const int32_t* cell_d, int64_t n_band, const int64_t* n_band_d,
-                                const float* grad_sdf_d, float* grad_verts_d, void* stream) {
-  if (!f || !f->valid || n_band < 0 || !grad_verts_d) return CSC_INVALID_ARG;
-  if (n_band > 0 && (!sdf_d || !feat_d || !cell_d || !grad_sdf_d)) return CSC_INVALID_ARG;
-  if (n_band > f->n_bricks * BRICK_CELLS) return CSC_INVALID_ARG;
-  if (n_band == 0) return CSC_OK;
+namespace {
+
+int backward_impl(const csc_features* f, const float* sdf_d, const int32_t* feat_d, const int32_t* cell_d, int64_t n,
+                  const int64_t* n_dev, const int64_t* band_off, const float* grad_sdf_d, float* grad_verts_d,
+                  hipStream_t s) {
   BwdArgs A;
   A.V = f->verts;
-  A.T = f->tris;
+  A.T = f->tris_g;
   A.edges = f->edges;
+  A.md = f->d_mesh;
   A.sdf = sdf_d;
   A.feat = feat_d;
   A.cell = cell_d;
   A.gsdf = grad_sdf_d;
-  A.n_dev = n_band_d;
+  A.band_off = band_off;
+  A.n_dev = n_dev;
   A.grad = grad_verts_d;
-  A.n = n_band;
-  A.nf = f->nf;
-  A.ne = f->ne;
-  A.nv = f->nv;
-  for (int k = 0; k < 3; k++) A.o[k] = f->grid.origin[k];
-  A.h = f->grid.h;
-  A.nx = f->grid.n[0];
-  A.ny = f->grid.n[1];
-  StageTimer t(TS_BACKWARD, (hipStream_t)stream);
-  k_backward<<<grid_1d(n_band, BW_THREADS), BW_THREADS, 0, (hipStream_t)stream>>>(A);
+  A.n = n;
+  A.n_meshes = f->n_meshes;
+  StageTimer t(TS_BACKWARD, s);
+  k_backward<<<grid_1d(n, BW_THREADS), BW_THREADS, 0, s>>>(A);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);
+}
+
+}  // namespace
+
+extern "C" int csc_sdf_backward(const csc_features* f, const float* sdf_d, const int32_t* feat_d,
+                                const int32_t* cell_d, int64_t n_band, const int64_t* n_band_d,
+                                const float* grad_sdf_d, float* grad_verts_d, void* stream) {
+  if (!f || !f->built || n_band < 0 || !grad_verts_d || f->n_meshes != 1) return CSC_INVALID_ARG;
+  if (n_band > 0 && (!sdf_d || !feat_d || !cell_d || !grad_sdf_d)) return CSC_INVALID_ARG;
+  if (n_band == 0) return CSC_OK;
+  return backward_impl(f, sdf_d, feat_d, cell_d, n_band, n_band_d, nullptr, grad_sdf_d, grad_verts_d,
+                       (hipStream_t)stream);
+}
+
+extern "C" int csc_sdf_backward_batched(const csc_features* f, const float* sdf_d, const int32_t* feat_d,
+                                        const int32_t* cell_d, int64_t max_band, const int64_t* band_off_d,
+                                        const float* grad_sdf_d, float* grad_verts_d, void* stream) {
+  if (!f || !f->built || max_band < 0 || !grad_verts_d || !band_off_d) return CSC_INVALID_ARG;
+  if (max_band > 0 && (!sdf_d || !feat_d || !cell_d || !grad_sdf_d)) return CSC_INVALID_ARG;
+  if (max_band == 0) return CSC_OK;
+  return backward_impl(f, sdf_d, feat_d, cell_d, max_band, nullptr, band_off_d, grad_sdf_d, grad_verts_d,
+                       (hipStream_t)stream);
 }

@@ -1,11 +1,16 @@
-// Feature construction (Section 7, Section 8): adjacency, normals, edge and
-// vertex classes, polyhedron lists and the band bricks.
+// Feature construction (Section 7, Section 8) for a batch of meshes: adjacency,
+// normals, edge and vertex classes, polyhedron lists and the band bricks.
 //
 // Unlike the paper's Morton-code sort of a triangle soup (Section 7.1, 7.2) the
-// input here is already indexed, so twins are found through a vertex -> face
-// table and edges are numbered by a prefix sum over the half-edges that own
-// them (start index < end index), which makes every id deterministic.
+// input here is indexed, so the corners of all triangles are grouped by vertex
+// (stable radix sort, or counting + scatter + per-vertex sort when the build is
+// captured into a graph), twins are matched around each vertex, and edges are
+// numbered by a prefix sum over the half-edges that own them (start index < end
+// index). Every id is deterministic. The whole sequence is device work with no
+// host synchronisation; csc_features_sync reads errors and counts back.
 #include <string.h>
+
+#include <new>
 
 #include "geometry.h"
 #include "internal.h"
@@ -16,9 +21,9 @@ __device__ inline d3 vload_d(const float* V, int64_t i) {
   return mkd((double)V[3 * i], (double)V[3 * i + 1], (double)V[3 * i + 2]);
 }
 __device__ inline f3 vload_f(const float* V, int64_t i) { return mk(V[3 * i], V[3 * i + 1], V[3 * i + 2]); }
+__device__ inline uint32_t* err_word(int64_t* stats) { return (uint32_t*)&stats[ST_ERR]; }
 
-// corner c = 3f + j (32-bit: 3F < 2^31): vertex after / before it in its face, and
-// the half-edge entering it (prev -> corner)
+// corner c = 3f + j (32-bit: 3F < 2^31): the corner after / before it in its face
 __device__ inline int32_t next_corner(int32_t c) { int32_t j = c % 3; return c - j + (j == 2 ? 0 : j + 1); }
 __device__ inline int32_t prev_corner(int32_t c) { int32_t j = c % 3; return c - j + (j == 0 ? 2 : j - 1); }
 
@@ -27,19 +32,42 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_check_verts(const float* __restrict__ V, int64_t nv, uint32_t* err) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= 3 * nv) return;
-  if (!isfinite(V[i])) atomicOr(err, ERR_NONFINITE);
+__global__ void k_zero_i64(int64_t* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-// index range and repeated-corner checks
-__global__ void k_validate_faces(const int32_t* __restrict__ T, int64_t nf, int64_t nv, uint32_t* err) {
+__global__ void k_check_verts(const float* __restrict__ V, int64_t nv, int64_t* stats) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= 3 * nv) return;
+  if (!isfinite(V[i])) atomicOr(err_word(stats), ERR_NONFINITE);
+}
+
+// Per face: its mesh, index range and repeated-corner checks, global indices. A
+// face with a bad index is replaced by three copies of its mesh's first vertex so
+// that every later access stays in bounds (the build then reports the error).
+__global__ void k_globalize(const int32_t* __restrict__ T, int64_t nf, const int32_t* __restrict__ f_off,
+                            const int32_t* __restrict__ v_off, int n_meshes, int32_t* tg, int32_t* face_mesh,
+                            int64_t* stats) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
+  const int m = find_segment(f_off, n_meshes + 1, f);
+  const int32_t nvm = v_off[m + 1] - v_off[m], vo = v_off[m];
   int32_t a = T[3 * f], b = T[3 * f + 1], c = T[3 * f + 2];
-  if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) atomicOr(err, ERR_INDEX);
-  else if (a == b || b == c || a == c) atomicOr(err, ERR_REPEAT);
+  if (a < 0 || b < 0 || c < 0 || a >= nvm || b >= nvm || c >= nvm) {
+    atomicOr(err_word(stats), ERR_INDEX);
+    a = b = c = 0;
+  } else if (a == b || b == c || a == c) {
+    atomicOr(err_word(stats), ERR_REPEAT);
+  }
+  tg[3 * f] = a + vo;
+  tg[3 * f + 1] = b + vo;
+  tg[3 * f + 2] = c + vo;
+  face_mesh[f] = m;
+}
+
+__global__ void k_vert_mesh(int64_t nv, const int32_t* __restrict__ v_off, int n_meshes, int32_t* vert_mesh) {
+  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v < nv) vert_mesh[v] = find_segment(v_off, n_meshes + 1, v);
 }
 
 __global__ void k_iota(int32_t* p, int64_t n) {
@@ -58,6 +86,65 @@ __global__ void k_offsets(const uint32_t* __restrict__ key, int64_t nh, int64_t 
     for (int64_t v = k + 1; v <= nv; v++) off[v] = (int32_t)nh;
 }
 
+constexpr int CC_THREADS = 256;
+constexpr int CC_SLOTS = 1024;  // > 3 * CC_THREADS insertions: probing always ends
+
+// Corner counts per vertex without library sorting (graph-capturable path): a
+// block counts its corners per vertex in an LDS hash table and reserves one range
+// per vertex with a single global atomic; each corner gets base + rank.
+__global__ __launch_bounds__(CC_THREADS) void k_count_corners(const int32_t* __restrict__ tg, int64_t nf, int32_t* cnt,
+                                                             int32_t* slot) {
+  __shared__ int s_key[CC_SLOTS], s_cnt[CC_SLOTS], s_base[CC_SLOTS];
+  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS) {
+    s_key[k] = -1;
+    s_cnt[k] = 0;
+  }
+  __syncthreads();
+  const int64_t f = blockIdx.x * (int64_t)CC_THREADS + threadIdx.x;
+  int hs[3] = {0, 0, 0}, rank[3] = {0, 0, 0};
+  if (f < nf) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      const int32_t v = tg[3 * f + j];
+      unsigned h = ((unsigned)v * 2654435761u) >> 22;
+      while (true) {
+        int old = atomicCAS(&s_key[h], -1, v);
+        if (old == -1 || old == v) break;
+        h = (h + 1) & (CC_SLOTS - 1);
+      }
+      hs[j] = (int)h;
+      rank[j] = atomicAdd(&s_cnt[h], 1);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS)
+    if (s_key[k] >= 0) s_base[k] = atomicAdd(&cnt[s_key[k]], s_cnt[k]);
+  __syncthreads();
+  if (f < nf) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) slot[3 * f + j] = s_base[hs[j]] + rank[j];
+  }
+}
+
+__global__ void k_scatter_corners(const int32_t* __restrict__ tg, int64_t nh, const int32_t* __restrict__ off,
+                                  const int32_t* __restrict__ slot, int32_t* vc) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nh) return;
+  vc[off[tg[c]] + slot[c]] = (int32_t)c;
+}
+
+// deterministic order of each vertex's corners (ascending index)
+__global__ void k_sort_segments(const int32_t* __restrict__ off, int32_t* vc, int64_t nv) {
+  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  int32_t s = off[v], e = off[v + 1];
+  for (int32_t i = s + 1; i < e; i++) {
+    int32_t x = vc[i], j = i - 1;
+    while (j >= s && vc[j] > x) { vc[j + 1] = vc[j]; j--; }
+    vc[j + 1] = x;
+  }
+}
+
 constexpr int VK_THREADS = 128;
 constexpr int VK_MAXD = 16;  // fans up to this degree are staged in LDS
 
@@ -73,7 +160,7 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
                                                       int64_t nv, const int32_t* __restrict__ off,
                                                       const int32_t* __restrict__ vc, int ruff_mode, int saddle_mode,
                                                       int force_both, int32_t* twin, float4* vinfo, uint32_t* vbits,
-                                                      int32_t* count, uint32_t* err) {
+                                                      int32_t* count, int64_t* stats) {
   __shared__ int32_t s_c[VK_MAXD][VK_THREADS], s_n[VK_MAXD][VK_THREADS], s_p[VK_MAXD][VK_THREADS];
   const int t = threadIdx.x;
   const int64_t v = blockIdx.x * (int64_t)VK_THREADS + t;
@@ -105,7 +192,7 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
     if (nmatch != 1) e |= ERR_NONMANIFOLD;
     twin[C_(i)] = nmatch == 1 ? match : -1;
   }
-  if (e) atomicOr(err, e);
+  if (e) atomicOr(err_word(stats), e);
   const d3 pv = vload_d(V, v);
   VertexAccum acc;
   for (int k = 0; k < d; k++) acc.add_face(pv, vload_d(V, N_(k)), vload_d(V, P_(k)));
@@ -132,7 +219,7 @@ __global__ void k_owned(const int32_t* __restrict__ T, int64_t nh, int32_t* flag
 }
 
 // (an open or non-manifold surface can own more or fewer than 3F/2 half-edges: such
-// a build is rejected after the final readback, and nothing is written past ne)
+// a build is rejected, and nothing is written past ne)
 __global__ void k_edges(const int32_t* __restrict__ T, int64_t nh, int64_t ne, const int32_t* __restrict__ twin,
                         const int32_t* __restrict__ eid, int4* edges, int32_t* face_edges) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -154,46 +241,48 @@ __global__ void k_edges(const int32_t* __restrict__ T, int64_t nh, int64_t ne, c
 // whose dilated box stays within the 3x3x3 bricks around the brick of its
 // centroid only seeds that brick (k_dilate_bricks covers the rest); larger ones
 // mark every brick of their box directly.
-__global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf, float4* fn,
-                            csc_grid g, int nbx, int nby, int nbz, uint8_t* seed, int32_t* flag, uint32_t* err) {
+__global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf,
+                            const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float4* fn,
+                            uint8_t* seed, int32_t* flag, int64_t* stats) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
   const d3 a = vload_d(V, T[3 * f]), b = vload_d(V, T[3 * f + 1]), c = vload_d(V, T[3 * f + 2]);
   const d3 n = cross(b - a, c - a);
   const double l = len(n);
   if (!(l > 0)) {
-    atomicOr(err, ERR_DEGENERATE);
+    atomicOr(err_word(stats), ERR_DEGENERATE);
     fn[f] = make_float4(0.f, 0.f, 0.f, 0.f);
   } else {
     fn[f] = make_float4((float)(n.x / l), (float)(n.y / l), (float)(n.z / l), 0.f);
   }
-  const double r = (double)g.band_cells * g.h + g.h, ih = 1.0 / g.h;
+  const MeshDesc& g = md[face_mesh[f]];
+  const double r = g.whd + g.h;
   const double X[3][3] = {{a.x, b.x, c.x}, {a.y, b.y, c.y}, {a.z, b.z, c.z}};
-  const int nbk[3] = {nbx, nby, nbz};
   int lo[3], hi[3], cb[3];
   bool small = true;
   for (int ax = 0; ax < 3; ax++) {
     const double x0 = X[ax][0], x1 = X[ax][1], x2 = X[ax][2];
     const double mn = fmin(x0, fmin(x1, x2)) - r, mx = fmax(x0, fmax(x1, x2)) + r;
-    double lo_c = floor((mn - g.origin[ax]) * ih - 0.5), hi_c = ceil((mx - g.origin[ax]) * ih - 0.5);
+    double lo_c = floor((mn - g.origin[ax]) * g.inv_h - 0.5), hi_c = ceil((mx - g.origin[ax]) * g.inv_h - 0.5);
     lo_c = fmax(lo_c, 0.0);
     hi_c = fmin(hi_c, (double)(g.n[ax] - 1));
-    if (lo_c > hi_c) return;
+    if (!(lo_c <= hi_c)) return;
     lo[ax] = (int)lo_c / BRICK;
     hi[ax] = (int)hi_c / BRICK;
-    const double cc = floor(floor(((x0 + x1 + x2) / 3.0 - g.origin[ax]) * ih) / BRICK);  // centroid's brick
-    cb[ax] = (int)fmax(-2.0, fmin(cc, (double)nbk[ax] + 1));
-    small = small && cb[ax] >= 0 && cb[ax] < nbk[ax] && lo[ax] >= cb[ax] - 1 && hi[ax] <= cb[ax] + 1;
+    const double cc = floor(floor(((x0 + x1 + x2) / 3.0 - g.origin[ax]) * g.inv_h) / BRICK);  // centroid's brick
+    cb[ax] = (int)fmax(-2.0, fmin(cc, (double)g.nb[ax] + 1));
+    small = small && cb[ax] >= 0 && cb[ax] < g.nb[ax] && lo[ax] >= cb[ax] - 1 && hi[ax] <= cb[ax] + 1;
   }
+  const int64_t base = g.brick_base, sx = g.nb[0], sxy = (int64_t)g.nb[0] * g.nb[1];
   if (small) {
-    uint8_t* p = &seed[cb[0] + (int64_t)nbx * (cb[1] + (int64_t)nby * cb[2])];
+    uint8_t* p = &seed[base + cb[0] + sx * cb[1] + sxy * cb[2]];
     if (*p == 0) *p = 1;
     return;
   }
   for (int z = lo[2]; z <= hi[2]; z++)
     for (int y = lo[1]; y <= hi[1]; y++)
       for (int x = lo[0]; x <= hi[0]; x++) {
-        int32_t* p = &flag[x + (int64_t)nbx * (y + (int64_t)nby * z)];
+        int32_t* p = &flag[base + x + sx * y + sxy * z];
         if (*p == 0) *p = 1;
       }
 }
@@ -276,12 +365,17 @@ __global__ void k_vertex_queue(const uint32_t* __restrict__ vbits, int64_t nv, c
   if (b & V_NEG) q[p++] = (int32_t)((v << 1) | 1);
 }
 
-// flag every brick with a seed among its 27 neighbours
-__global__ void k_dilate_bricks(const uint8_t* __restrict__ seed, int nbx, int nby, int nbz, int32_t* flag) {
+// flag every brick with a seed among its 27 neighbours in its own mesh's grid
+__global__ void k_dilate_bricks(const uint8_t* __restrict__ seed, int64_t nbt, const int32_t* __restrict__ brick_base,
+                                const MeshDesc* __restrict__ md, int n_meshes, int32_t* flag) {
   int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= (int64_t)nbx * nby * nbz) return;
+  if (b >= nbt) return;
   if (flag[b]) return;
-  const int x = (int)(b % nbx), y = (int)((b / nbx) % nby), z = (int)(b / ((int64_t)nbx * nby));
+  const int m = find_segment(brick_base, n_meshes + 1, b);
+  const MeshDesc& g = md[m];
+  const int64_t loc = b - g.brick_base;
+  const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
+  const int x = (int)(loc % nbx), y = (int)((loc / nbx) % nby), z = (int)(loc / ((int64_t)nbx * nby));
   for (int dz = -1; dz <= 1; dz++) {
     int zz = z + dz;
     if (zz < 0 || zz >= nbz) continue;
@@ -291,7 +385,7 @@ __global__ void k_dilate_bricks(const uint8_t* __restrict__ seed, int nbx, int n
       for (int dx = -1; dx <= 1; dx++) {
         int xx = x + dx;
         if (xx < 0 || xx >= nbx) continue;
-        if (seed[xx + (int64_t)nbx * (yy + (int64_t)nby * zz)]) {
+        if (seed[g.brick_base + xx + (int64_t)nbx * (yy + (int64_t)nby * zz)]) {
           flag[b] = 1;
           return;
         }
@@ -300,11 +394,32 @@ __global__ void k_dilate_bricks(const uint8_t* __restrict__ seed, int nbx, int n
   }
 }
 
-__global__ void k_brick_fix(const int32_t* __restrict__ flag, int32_t* index, int32_t* list, int64_t n) {
+// slots of the flagged bricks (index = exclusive prefix of the flags), their
+// list and mesh, and the first slot of every mesh
+__global__ void k_brick_fix(const int32_t* __restrict__ flag, int32_t* index, int32_t* list, int32_t* bmesh,
+                            const int32_t* __restrict__ brick_base, int n_meshes, int32_t* first_slot,
+                            const int64_t* __restrict__ stats, int64_t n) {
   int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (b >= n) return;
-  if (flag[b]) list[index[b]] = (int32_t)b;
-  else index[b] = -1;
+  const int m = find_segment(brick_base, n_meshes + 1, b);
+  if (b == brick_base[m]) first_slot[m] = index[b];
+  if (b == n - 1) first_slot[n_meshes] = (int32_t)stats[ST_NBRICKS];
+  if (flag[b]) {
+    list[index[b]] = (int32_t)b;
+    bmesh[index[b]] = m;
+  } else {
+    index[b] = -1;
+  }
+}
+
+int status_from_errors(uint64_t err, int64_t ne_found, int64_t ne_expected) {
+  if (err & (ERR_INDEX | ERR_REPEAT | ERR_NONFINITE)) return CSC_INVALID_ARG;
+  if (err & ERR_OVERFLOW) return CSC_WORKSPACE_TOO_SMALL;
+  if (err & ERR_ORIENT) return CSC_INCONSISTENT_ORIENTATION;
+  if (err & ERR_NONMANIFOLD) return CSC_NONMANIFOLD;
+  if (ne_found != ne_expected) return CSC_NONMANIFOLD;
+  if (err & ERR_DEGENERATE) return CSC_DEGENERATE_FACE;
+  return CSC_OK;
 }
 
 }  // namespace csc
@@ -315,40 +430,48 @@ namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+enum {
+  L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FN, L_ECLS,
+  L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_STATS,
+  L_SORT, L_N
+};
+
 struct Layout {
-  size_t off[20];
+  size_t off[L_N];
   size_t total;
 };
 
-// arena layout for nv vertices, nf faces, nbt bricks
-Layout layout(int64_t nv, int64_t nf, int64_t nbt, size_t sort_bytes) {
-  int64_t ne = 3 * nf / 2;
-  int64_t big = 3 * nf > nbt ? 3 * nf : nbt;
+Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_bytes) {
+  const int64_t ne = 3 * nf / 2;
+  int64_t big = 3 * nf;
+  big = big > nbt ? big : nbt;
   big = big > nv + 1 ? big : nv + 1;
-  size_t sz[20] = {
-      sizeof(int32_t) * (size_t)(nv + 1),   // 0 vtx_off
-      sizeof(int32_t) * (size_t)(3 * nf),   // 1 vtx_faces
-      sizeof(int32_t) * (size_t)(3 * nf),   // 2 face_edges
-      sizeof(int4) * (size_t)(ne + 1),      // 3 edges
-      sizeof(float4) * (size_t)nf,          // 4 face_n
-      (size_t)(ne + 1),                     // 5 edge_cls
-      sizeof(float4) * (size_t)nv,          // 6 vinfo
-      sizeof(uint32_t) * (size_t)nv,        // 7 vbits
-      sizeof(int32_t) * (size_t)(2 * ne + 1),  // 8 epoly
-      sizeof(int32_t) * (size_t)(2 * nv + 1),  // 9 vpoly
-      sizeof(int32_t) * (size_t)nbt,        // 10 brick_index
-      sizeof(int32_t) * (size_t)nbt,        // 11 brick_list
-      sizeof(int32_t) * (size_t)(big + 1),  // 12 t_a
-      sizeof(int32_t) * (size_t)(big + 1),  // 13 t_b
-      sizeof(int32_t) * (size_t)(big + 1),  // 14 t_c
-      sizeof(int32_t) * (size_t)scan_tmp_ints(big + 1),  // 15 t_scan
-      sizeof(int64_t) * ST_COUNT,           // 16 stats
-      sizeof(uint32_t) * 4,                 // 17 err
-      sort_bytes,                           // 18 radix sort scratch
-      0};
+  big = big > ne + 1 ? big : ne + 1;
+  size_t sz[L_N];
+  sz[L_MESH] = sizeof(MeshDesc) * (size_t)n_meshes;
+  sz[L_FOFF] = sz[L_VOFF] = sz[L_BBASE] = sizeof(int32_t) * (size_t)(n_meshes + 1);
+  sz[L_TRIS] = sizeof(int32_t) * (size_t)(3 * nf);
+  sz[L_FMESH] = sizeof(int32_t) * (size_t)nf;
+  sz[L_VMESH] = sizeof(int32_t) * (size_t)nv;
+  sz[L_VTXOFF] = sizeof(int32_t) * (size_t)(nv + 1);
+  sz[L_VTXC] = sizeof(int32_t) * (size_t)(3 * nf);
+  sz[L_FEDGES] = sizeof(int32_t) * (size_t)(3 * nf);
+  sz[L_EDGES] = sizeof(int4) * (size_t)(ne + 1);
+  sz[L_FN] = sizeof(float4) * (size_t)nf;
+  sz[L_ECLS] = (size_t)(ne + 1);
+  sz[L_VINFO] = sizeof(float4) * (size_t)nv;
+  sz[L_VBITS] = sizeof(uint32_t) * (size_t)nv;
+  sz[L_EPOLY] = sizeof(int32_t) * (size_t)(2 * ne + 1);
+  sz[L_VPOLY] = sizeof(int32_t) * (size_t)(2 * nv + 1);
+  sz[L_BINDEX] = sz[L_BLIST] = sz[L_BMESH] = sizeof(int32_t) * (size_t)nbt;
+  sz[L_FIRST] = sizeof(int32_t) * (size_t)(n_meshes + 1);
+  sz[L_TA] = sz[L_TB] = sz[L_TC] = sizeof(int32_t) * (size_t)(big + 1);
+  sz[L_TSCAN] = sizeof(int32_t) * (size_t)scan_tmp_ints(big + 1);
+  sz[L_STATS] = sizeof(int64_t) * ST_COUNT;
+  sz[L_SORT] = sort_bytes;
   Layout L;
   size_t o = 0;
-  for (int i = 0; i < 20; i++) {
+  for (int i = 0; i < L_N; i++) {
     L.off[i] = o;
     o += align_up(sz[i]);
   }
@@ -358,50 +481,97 @@ Layout layout(int64_t nv, int64_t nf, int64_t nbt, size_t sort_bytes) {
 
 bool finite_pos(double x) { return x > 0 && x < 1e300; }
 
+int check_grid(const csc_grid& g) {
+  for (int a = 0; a < 3; a++)
+    if (g.n[a] <= 0 || !isfinite(g.origin[a])) return CSC_INVALID_ARG;
+  if (!finite_pos(g.h) || !(g.band_cells > 0) || !isfinite(g.band_cells)) return CSC_INVALID_ARG;
+  if ((int64_t)g.n[0] * g.n[1] * g.n[2] > INT32_MAX) return CSC_GRID_TOO_LARGE;
+  return CSC_OK;
+}
+
+bool same_config(const csc_features* F, const std::vector<MeshDesc>& m, const csc_options& o) {
+  if ((int)F->mesh.size() != (int)m.size()) return false;
+  if (memcmp(&F->opt, &o, sizeof(o)) != 0) return false;
+  return memcmp(F->mesh.data(), m.data(), sizeof(MeshDesc) * m.size()) == 0;
+}
+
 }  // namespace
 
-extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_t* tris_d, int64_t nf,
-                                  const csc_grid* grid, const csc_options* opt, void* stream, csc_features** out) {
-  if (!verts_d || !tris_d || !grid || !out || nv <= 0 || nf <= 0) return CSC_INVALID_ARG;
-  if (nv > INT32_MAX / 2 || nf > INT32_MAX / 4) return CSC_INVALID_ARG;
-  if (nf % 2 != 0) return CSC_NONMANIFOLD;  // a closed triangle surface has 3F/2 edges
-  for (int a = 0; a < 3; a++) {
-    if (grid->n[a] <= 0 || !isfinite(grid->origin[a])) return CSC_INVALID_ARG;
-  }
-  if (!finite_pos(grid->h) || !(grid->band_cells > 0) || !isfinite(grid->band_cells)) return CSC_INVALID_ARG;
-  if ((int64_t)grid->n[0] * grid->n[1] * grid->n[2] > INT32_MAX) return CSC_GRID_TOO_LARGE;
+// Shared implementation of the single-mesh and batched builds.
+int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, const int64_t* nf,
+               const csc_grid* grids, int32_t n_meshes, const csc_options* opt, int32_t flags, void* stream,
+               csc_features** out) {
+  if (!verts_d || !tris_d || !nv || !nf || !grids || !out || n_meshes <= 0) return CSC_INVALID_ARG;
   csc_options o = {1e-3f, 0, 0, 0};
   if (opt) o = *opt;
   if (!(o.eps_rel >= 0) || !(o.eps_rel < 0.5f) || o.ruff_mode < 0 || o.ruff_mode > 1 || o.saddle_mode < 0 ||
       o.saddle_mode > 2)
     return CSC_INVALID_ARG;
-  int nb[3];
-  for (int a = 0; a < 3; a++) nb[a] = (grid->n[a] + BRICK - 1) / BRICK;
-  int64_t nbt = (int64_t)nb[0] * nb[1] * nb[2];
-  if (nbt > (1 << 24)) return CSC_GRID_TOO_LARGE;
+  std::vector<MeshDesc> mesh((size_t)n_meshes);
+  int64_t tv = 0, tf = 0, te = 0, tb = 0;
+  for (int m = 0; m < n_meshes; m++) {
+    if (nv[m] <= 0 || nf[m] <= 0) return CSC_INVALID_ARG;
+    int gc = check_grid(grids[m]);
+    if (gc != CSC_OK) return gc;
+    if (nf[m] % 2 != 0) return CSC_NONMANIFOLD;  // a closed triangle surface has 3F/2 edges
+    MeshDesc& d = mesh[m];
+    memset(&d, 0, sizeof(d));
+    const csc_grid& g = grids[m];
+    for (int a = 0; a < 3; a++) {
+      d.origin[a] = g.origin[a];
+      d.n[a] = g.n[a];
+      d.nb[a] = (g.n[a] + BRICK - 1) / BRICK;
+    }
+    d.h = g.h;
+    d.inv_h = 1.0 / g.h;
+    d.whd = (double)g.band_cells * g.h;
+    d.epsd = (double)o.eps_rel * g.h;
+    d.hf = (float)g.h;
+    d.whf = (float)d.whd;
+    d.eps = (float)d.epsd;
+    d.band = g.band_cells;
+    d.brick_base = (int32_t)tb;
+    d.v_off = (int32_t)tv;
+    d.f_off = (int32_t)tf;
+    d.e_off = (int32_t)te;
+    d.nv = (int32_t)nv[m];
+    d.nf = (int32_t)nf[m];
+    d.ne = (int32_t)(3 * nf[m] / 2);
+    tb += (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
+    tv += nv[m];
+    tf += nf[m];
+    te += 3 * nf[m] / 2;
+    if (tv > INT32_MAX / 2 || tf > INT32_MAX / 4 || tb > (1 << 26)) return tb > (1 << 26) ? CSC_GRID_TOO_LARGE
+                                                                                          : CSC_INVALID_ARG;
+  }
   int dc = check_device();
   if (dc != CSC_OK) return dc;
 
+  const bool graph_safe = (flags & CSC_BUILD_GRAPH_SAFE) != 0;
+  const bool no_sync = (flags & CSC_BUILD_NO_SYNC) != 0;
   hipStream_t s = (hipStream_t)stream;
   csc_features* F = *out;
-  bool fresh = F == nullptr;
+  const bool fresh = F == nullptr;
   if (fresh) {
     F = new (std::nothrow) csc_features();
     if (!F) return CSC_OUT_OF_MEMORY;
   }
-  F->valid = false;
+  auto fail = [&](int code) {
+    if (fresh) csc_features_free(F);
+    else F->built = F->synced = false;
+    return code;
+  };
   int sort_bits = 1;
-  while (sort_bits < 31 && ((int64_t)1 << sort_bits) < nv) sort_bits++;
-  const size_t sort_bytes = sort_pairs_tmp_bytes(3 * nf, sort_bits);
-  if (sort_bytes == 0) {
-    if (fresh) delete F;
-    return fail_hip(hipErrorInvalidValue);
-  }
-  Layout L = layout(nv, nf, nbt, sort_bytes);
+  while (sort_bits < 31 && ((int64_t)1 << sort_bits) < tv) sort_bits++;
+  size_t sort_bytes = graph_safe ? F->t_sort_bytes : sort_pairs_tmp_bytes(3 * tf, sort_bits);
+  if (!graph_safe && sort_bytes == 0) return fail(fail_hip(hipErrorInvalidValue));
+  Layout L = layout(n_meshes, tv, tf, tb, sort_bytes);
+  const bool config_changed = fresh || !same_config(F, mesh, o) || F->arena_bytes < L.total || F->nv != tv ||
+                              F->nf != tf;
   hipError_t he;
   if (F->arena_bytes < L.total) {
     if (F->arena) {
-      he = hipStreamSynchronize(s);
+      (void)hipStreamSynchronize(s);
       (void)hipFree(F->arena);
       F->arena = nullptr;
       F->arena_bytes = 0;
@@ -409,120 +579,156 @@ extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_
     he = hipMalloc((void**)&F->arena, L.total);
     if (he != hipSuccess) {
       F->arena = nullptr;
-      if (fresh) { if (F->h_stats) (void)hipHostFree(F->h_stats); delete F; }
-      return he == hipErrorOutOfMemory ? CSC_OUT_OF_MEMORY : fail_hip(he);
+      return fail(he == hipErrorOutOfMemory ? CSC_OUT_OF_MEMORY : fail_hip(he));
     }
     F->arena_bytes = L.total;
   }
   if (!F->h_stats) {
-    he = hipHostMalloc((void**)&F->h_stats, sizeof(int64_t) * (ST_COUNT + 2), hipHostMallocDefault);
+    he = hipHostMalloc((void**)&F->h_stats, sizeof(int64_t) * ST_COUNT, hipHostMallocDefault);
     if (he != hipSuccess) {
       F->h_stats = nullptr;
-      if (fresh) { (void)hipFree(F->arena); delete F; }
-      return fail_hip(he);
+      return fail(fail_hip(he));
     }
   }
   char* A = F->arena;
+  F->n_meshes = n_meshes;
   F->verts = verts_d;
-  F->tris = tris_d;
-  F->nv = nv;
-  F->nf = nf;
-  F->ne = 3 * nf / 2;
-  F->grid = *grid;
+  F->nv = tv;
+  F->nf = tf;
+  F->ne = te;
+  F->nbt = tb;
   F->opt = o;
-  for (int a = 0; a < 3; a++) F->nb[a] = nb[a];
-  F->nbricks_total = nbt;
-  F->vtx_off = (int32_t*)(A + L.off[0]);
-  F->vtx_faces = (int32_t*)(A + L.off[1]);
-  F->face_edges = (int32_t*)(A + L.off[2]);
-  F->edges = (int4*)(A + L.off[3]);
-  F->face_n = (float4*)(A + L.off[4]);
-  F->edge_cls = (uint8_t*)(A + L.off[5]);
-  F->vinfo = (float4*)(A + L.off[6]);
-  F->vbits = (uint32_t*)(A + L.off[7]);
-  F->epoly = (int32_t*)(A + L.off[8]);
-  F->vpoly = (int32_t*)(A + L.off[9]);
-  F->brick_index = (int32_t*)(A + L.off[10]);
-  F->brick_list = (int32_t*)(A + L.off[11]);
-  F->t_a = (int32_t*)(A + L.off[12]);
-  F->t_b = (int32_t*)(A + L.off[13]);
-  F->t_c = (int32_t*)(A + L.off[14]);
-  F->t_scan = (int32_t*)(A + L.off[15]);
-  F->d_stats = (int64_t*)(A + L.off[16]);
-  F->d_err = (uint32_t*)(A + L.off[17]);
-  F->t_sort = (void*)(A + L.off[18]);
-  F->t_sort_bytes = sort_bytes;
+  F->sort_bits = sort_bits;
+  F->d_mesh = (MeshDesc*)(A + L.off[L_MESH]);
+  F->f_off = (int32_t*)(A + L.off[L_FOFF]);
+  F->v_off = (int32_t*)(A + L.off[L_VOFF]);
+  F->brick_base = (int32_t*)(A + L.off[L_BBASE]);
+  F->tris_g = (int32_t*)(A + L.off[L_TRIS]);
+  F->face_mesh = (int32_t*)(A + L.off[L_FMESH]);
+  F->vert_mesh = (int32_t*)(A + L.off[L_VMESH]);
+  F->vtx_off = (int32_t*)(A + L.off[L_VTXOFF]);
+  F->vtx_corners = (int32_t*)(A + L.off[L_VTXC]);
+  F->face_edges = (int32_t*)(A + L.off[L_FEDGES]);
+  F->edges = (int4*)(A + L.off[L_EDGES]);
+  F->face_n = (float4*)(A + L.off[L_FN]);
+  F->edge_cls = (uint8_t*)(A + L.off[L_ECLS]);
+  F->vinfo = (float4*)(A + L.off[L_VINFO]);
+  F->vbits = (uint32_t*)(A + L.off[L_VBITS]);
+  F->epoly = (int32_t*)(A + L.off[L_EPOLY]);
+  F->vpoly = (int32_t*)(A + L.off[L_VPOLY]);
+  F->brick_index = (int32_t*)(A + L.off[L_BINDEX]);
+  F->brick_list = (int32_t*)(A + L.off[L_BLIST]);
+  F->brick_mesh = (int32_t*)(A + L.off[L_BMESH]);
+  F->first_slot = (int32_t*)(A + L.off[L_FIRST]);
+  F->t_a = (int32_t*)(A + L.off[L_TA]);
+  F->t_b = (int32_t*)(A + L.off[L_TB]);
+  F->t_c = (int32_t*)(A + L.off[L_TC]);
+  F->t_scan = (int32_t*)(A + L.off[L_TSCAN]);
+  F->d_stats = (int64_t*)(A + L.off[L_STATS]);
+  F->t_sort = graph_safe ? F->t_sort : (void*)(A + L.off[L_SORT]);
+  if (!graph_safe) F->t_sort_bytes = sort_bytes;
+  F->built = F->synced = false;
 
-  const int B = 256;
-  const int64_t nh = 3 * nf, ne = F->ne;
-  auto fail = [&](int code) {
-    if (fresh) csc_features_free(F);
-    return code;
-  };
-#define CK(x)                                   \
-  do {                                          \
-    hipError_t e_ = (x);                        \
+#define CK(x)                                        \
+  do {                                               \
+    hipError_t e_ = (x);                             \
     if (e_ != hipSuccess) return fail(fail_hip(e_)); \
   } while (0)
 
-  StageTimer timer(TS_BUILD, s);
-  // 1. validation; the first readback guards every indexed access below
-  CK(hipMemsetAsync(F->d_stats, 0, sizeof(int64_t) * ST_COUNT, s));
-  CK(hipMemsetAsync(F->d_err, 0, sizeof(uint32_t), s));
-  k_check_verts<<<grid_1d(3 * nv, B), B, 0, s>>>(verts_d, nv, F->d_err);
-  k_validate_faces<<<grid_1d(nf, B), B, 0, s>>>(tris_d, nf, nv, F->d_err);
-  CK(hipGetLastError());
-  CK(hipMemcpyAsync(F->h_stats + ST_COUNT, F->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  CK(hipStreamSynchronize(s));
-  uint32_t err0 = *(uint32_t*)(F->h_stats + ST_COUNT);
-  if (err0 & (ERR_INDEX | ERR_REPEAT | ERR_NONFINITE)) return fail(CSC_INVALID_ARG);
+  if (config_changed) {
+    // descriptors and offset tables change only with the configuration (never
+    // inside a captured replay of the same batch)
+    std::vector<int32_t> tabs(3 * (size_t)(n_meshes + 1));
+    for (int m = 0; m <= n_meshes; m++) {
+      tabs[m] = m < n_meshes ? mesh[m].f_off : (int32_t)tf;
+      tabs[(n_meshes + 1) + m] = m < n_meshes ? mesh[m].v_off : (int32_t)tv;
+      tabs[2 * (n_meshes + 1) + m] = m < n_meshes ? mesh[m].brick_base : (int32_t)tb;
+    }
+    CK(hipMemcpy(F->d_mesh, mesh.data(), sizeof(MeshDesc) * n_meshes, hipMemcpyHostToDevice));
+    CK(hipMemcpy(F->f_off, tabs.data(), sizeof(int32_t) * (n_meshes + 1), hipMemcpyHostToDevice));
+    CK(hipMemcpy(F->v_off, tabs.data() + (n_meshes + 1), sizeof(int32_t) * (n_meshes + 1), hipMemcpyHostToDevice));
+    CK(hipMemcpy(F->brick_base, tabs.data() + 2 * (n_meshes + 1), sizeof(int32_t) * (n_meshes + 1),
+                 hipMemcpyHostToDevice));
+    F->mesh = mesh;
+  }
 
-  // 2. vertex -> corner table: corners 3f+j stably sorted by their vertex T[3f+j]
-  k_iota<<<grid_1d(nh, B), B, 0, s>>>(F->t_a, nh);
-  CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)tris_d, (uint32_t*)F->t_b, F->t_a, F->vtx_faces, nh,
-                sort_bits, s));
-  k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, nv, F->vtx_off);
+  StageTimer timer(TS_BUILD, s);
+  const int B = 256;
+  const int64_t nh = 3 * tf, ne = te;
+  // 1. inputs: finite coordinates, per-mesh index ranges, global indices
+  k_zero_i64<<<1, 64, 0, s>>>(F->d_stats, ST_COUNT);
+  k_check_verts<<<grid_1d(3 * tv, B), B, 0, s>>>(verts_d, tv, F->d_stats);
+  k_globalize<<<grid_1d(tf, B), B, 0, s>>>(tris_d, tf, F->f_off, F->v_off, n_meshes, F->tris_g, F->face_mesh,
+                                            F->d_stats);
+  k_vert_mesh<<<grid_1d(tv, B), B, 0, s>>>(tv, F->v_off, n_meshes, F->vert_mesh);
+  const int32_t* T = F->tris_g;
+  // 2. vertex -> corner table
+  if (graph_safe) {
+    k_fill_i32<<<grid_1d(tv + 1, B), B, 0, s>>>(F->t_a, tv + 1, 0);
+    k_count_corners<<<grid_1d(tf, CC_THREADS), CC_THREADS, 0, s>>>(T, tf, F->t_a, F->t_c);
+    CK(exclusive_scan(F->t_a, F->vtx_off, tv + 1, F->t_scan, nullptr, nullptr, s));
+    k_scatter_corners<<<grid_1d(nh, B), B, 0, s>>>(T, nh, F->vtx_off, F->t_c, F->vtx_corners);
+    k_sort_segments<<<grid_1d(tv, B), B, 0, s>>>(F->vtx_off, F->vtx_corners, tv);
+  } else {
+    k_iota<<<grid_1d(nh, B), B, 0, s>>>(F->t_a, nh);
+    CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, F->t_a, F->vtx_corners, nh,
+                  sort_bits, s));
+    k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, tv, F->vtx_off);
+  }
   // 3. per vertex: twins, pseudonormal, class, cone; then edge numbering
-  k_vertex<<<grid_1d(nv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, tris_d, nv, F->vtx_off, F->vtx_faces, o.ruff_mode,
+  k_vertex<<<grid_1d(tv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, T, tv, F->vtx_off, F->vtx_corners, o.ruff_mode,
                                                         o.saddle_mode, o.force_both_sides, F->t_a, F->vinfo,
-                                                        F->vbits, F->t_c, F->d_err);
-  CK(exclusive_scan(F->t_c, F->t_c, nv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
-  k_vertex_queue<<<grid_1d(nv, B), B, 0, s>>>(F->vbits, nv, F->t_c, F->vpoly);
-  k_owned<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nh, F->t_b);
+                                                        F->vbits, F->t_c, F->d_stats);
+  CK(exclusive_scan(F->t_c, F->t_c, tv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
+  k_vertex_queue<<<grid_1d(tv, B), B, 0, s>>>(F->vbits, tv, F->t_c, F->vpoly);
+  k_owned<<<grid_1d(nh, B), B, 0, s>>>(T, nh, F->t_b);
   k_fill_i32<<<grid_1d(4 * (ne + 1), B), B, 0, s>>>((int32_t*)F->edges, 4 * (ne + 1), -1);
   CK(exclusive_scan(F->t_b, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
-  k_edges<<<grid_1d(nh, B), B, 0, s>>>(tris_d, nh, ne, F->t_a, F->t_b, F->edges, F->face_edges);
-  // 4. face normals with the band bricks near each face, edge classes
-  k_fill_i32<<<grid_1d(nbt, B), B, 0, s>>>(F->t_b, nbt, 0);
-  k_fill_i32<<<grid_1d((nbt + 3) / 4, B), B, 0, s>>>(F->t_a, (nbt + 3) / 4, 0);
-  k_face_geom<<<grid_1d(nf, B), B, 0, s>>>(verts_d, tris_d, nf, F->face_n, *grid, nb[0], nb[1], nb[2],
-                                           (uint8_t*)F->t_a, F->t_b, F->d_err);
-  k_edge_class<<<grid_1d(ne, B), B, 0, s>>>(verts_d, tris_d, F->edges, ne, o.force_both_sides, F->edge_cls, F->t_c);
+  k_edges<<<grid_1d(nh, B), B, 0, s>>>(T, nh, ne, F->t_a, F->t_b, F->edges, F->face_edges);
+  // 4. face normals with the band bricks near each face; edge classes
+  k_fill_i32<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, tb, 0);
+  k_fill_i32<<<grid_1d((tb + 3) / 4, B), B, 0, s>>>(F->t_a, (tb + 3) / 4, 0);
+  k_face_geom<<<grid_1d(tf, B), B, 0, s>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, (uint8_t*)F->t_a,
+                                            F->t_b, F->d_stats);
+  k_edge_class<<<grid_1d(ne, B), B, 0, s>>>(verts_d, T, F->edges, ne, o.force_both_sides, F->edge_cls, F->t_c);
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
-  k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, nv, F->d_stats);
+  k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, tv, F->d_stats);
   // 5. band bricks
-  k_dilate_bricks<<<grid_1d(nbt, B), B, 0, s>>>((const uint8_t*)F->t_a, nb[0], nb[1], nb[2], F->t_b);
-  CK(exclusive_scan(F->t_b, F->brick_index, nbt, F->t_scan, &F->d_stats[ST_NBRICKS], nullptr, s));
-  k_brick_fix<<<grid_1d(nbt, B), B, 0, s>>>(F->t_b, F->brick_index, F->brick_list, nbt);
+  k_dilate_bricks<<<grid_1d(tb, B), B, 0, s>>>((const uint8_t*)F->t_a, tb, F->brick_base, F->d_mesh, n_meshes,
+                                               F->t_b);
+  CK(exclusive_scan(F->t_b, F->brick_index, tb, F->t_scan, &F->d_stats[ST_NBRICKS], nullptr, s));
+  k_brick_fix<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, F->brick_index, F->brick_list, F->brick_mesh, F->brick_base,
+                                           n_meshes, F->first_slot, F->d_stats, tb);
   CK(hipGetLastError());
-  CK(hipMemcpyAsync(F->h_stats, F->d_stats, sizeof(int64_t) * ST_COUNT, hipMemcpyDeviceToHost, s));
-  CK(hipMemcpyAsync(F->h_stats + ST_COUNT, F->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  CK(hipStreamSynchronize(s));
 #undef CK
-  uint32_t err = *(uint32_t*)(F->h_stats + ST_COUNT);
+  F->built = true;
+  if (no_sync) return CSC_OK;
+  int rc = csc_features_sync(F, stream);
+  if (rc != CSC_OK) return fail(rc);
+  *out = F;
+  return CSC_OK;
+}
+
+extern "C" int csc_features_sync(csc_features* F, void* stream) {
+  if (!F || !F->built || !F->h_stats) return CSC_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t he = hipMemcpyAsync(F->h_stats, F->d_stats, sizeof(int64_t) * ST_COUNT, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return fail_hip(he);
   const int64_t* st = F->h_stats;
-  if (err & ERR_ORIENT) return fail(CSC_INCONSISTENT_ORIENTATION);
-  if (err & ERR_NONMANIFOLD) return fail(CSC_NONMANIFOLD);
-  if (st[ST_NE] != ne) return fail(CSC_NONMANIFOLD);
-  if (err & ERR_DEGENERATE) return fail(CSC_DEGENERATE_FACE);
+  int rc = status_from_errors((uint64_t)(uint32_t)st[ST_ERR], st[ST_NE], F->ne);
+  if (rc != CSC_OK) {
+    F->synced = false;
+    return rc;
+  }
   F->n_epoly = st[ST_NEPOLY];
   F->n_vpoly = st[ST_NVPOLY];
   F->n_bricks = st[ST_NBRICKS];
   csc_feature_info& I = F->info;
-  I.n_vertices = nv;
-  I.n_faces = nf;
-  I.n_edges = ne;
+  I.n_vertices = F->nv;
+  I.n_faces = F->nf;
+  I.n_edges = F->ne;
   I.n_edge_polyhedra = F->n_epoly;
   I.n_vertex_polyhedra = F->n_vpoly;
   I.edges_convex = st[ST_E_CONVEX];
@@ -536,7 +742,20 @@ extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_
   I.vertices_ruff = st[ST_V_RUFF];
   I.n_bricks = F->n_bricks;
   I.max_band_cells = F->n_bricks * BRICK_CELLS;
-  F->valid = true;
-  *out = F;
+  F->synced = true;
   return CSC_OK;
+}
+
+extern "C" int csc_build_features(const float* verts_d, int64_t nv, const int32_t* tris_d, int64_t nf,
+                                  const csc_grid* grid, const csc_options* opt, void* stream, csc_features** out) {
+  if (!grid) return CSC_INVALID_ARG;
+  return build_impl(verts_d, tris_d, &nv, &nf, grid, 1, opt, 0, stream, out);
+}
+
+extern "C" int csc_build_features_batched(const float* verts_d, const int32_t* tris_d, const int64_t* nv,
+                                          const int64_t* nf, const csc_grid* grids, int32_t n_meshes,
+                                          const csc_options* opt, int32_t flags, void* stream, csc_features** out) {
+  if (flags & ~(CSC_BUILD_NO_SYNC | CSC_BUILD_GRAPH_SAFE)) return CSC_INVALID_ARG;
+  if ((flags & CSC_BUILD_NO_SYNC) && (!out || !*out)) return CSC_INVALID_ARG;
+  return build_impl(verts_d, tris_d, nv, nf, grids, n_meshes, opt, flags, stream, out);
 }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/csc.h"
 
 namespace csc {
@@ -11,23 +13,36 @@ constexpr int BRICK = 8;          // band store brick edge (cells)
 constexpr int BRICK_CELLS = 512;  // BRICK^3
 constexpr unsigned long long EMPTY_KEY = ~0ull;
 
-// device error bits gathered during the build
+// device error bits gathered during a build or scan
 enum : uint32_t {
   ERR_INDEX = 1u, ERR_REPEAT = 2u, ERR_NONFINITE = 4u, ERR_NONMANIFOLD = 8u, ERR_ORIENT = 16u,
-  ERR_DEGENERATE = 32u, ERR_EDGECOUNT = 64u
+  ERR_DEGENERATE = 32u, ERR_OVERFLOW = 64u
 };
 
-// device statistics slots
+// device counters and statistics (int64 slots)
 enum {
   ST_NE = 0, ST_NEPOLY, ST_NVPOLY, ST_NBRICKS,
   ST_E_CONVEX, ST_E_CONCAVE, ST_E_FLAT, ST_E_UNKNOWN,
   ST_V_CONVEX, ST_V_CONCAVE, ST_V_FLAT, ST_V_SADDLE, ST_V_RUFF,
-  ST_COUNT = 16
+  ST_ERR, ST_COUNT = 16
+};
+
+// One mesh of a batch: its grid, band and slice of the concatenated arrays.
+struct MeshDesc {
+  double origin[3];
+  double h, inv_h, whd, epsd;
+  float hf, whf, eps, band;
+  int32_t n[3];
+  int32_t nb[3];
+  int32_t brick_base;           // first brick of this mesh in the batch's brick space
+  int32_t v_off, f_off, e_off;  // first vertex / face / edge of this mesh
+  int32_t nv, nf, ne;
+  int32_t pad;
 };
 
 // Exclusive prefix sum of in[0..n) into out (may alias in). If total_i64 is not
 // null the sum is stored there; if total_i32 is not null, also there. tmp must
-// hold scan_tmp_ints(n) ints.
+// hold scan_tmp_ints(n) ints. Kernels only (safe inside a captured graph).
 int64_t scan_tmp_ints(int64_t n);
 hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t* total_i64,
                           int32_t* total_i32, hipStream_t s);
@@ -38,11 +53,13 @@ hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint
                       const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits, hipStream_t s);
 
 int fail_hip(hipError_t e);  // records the HIP error text, returns CSC_HIP_ERROR
+int check_device();          // CSC_OK or CSC_UNSUPPORTED_DEVICE / CSC_HIP_ERROR
 
 // timed stages (csc_timing_*)
 enum { TS_BUILD = 0, TS_INIT, TS_SCAN_FACE, TS_SCAN_EDGE, TS_SCAN_VERT, TS_COUNT, TS_SIGN, TS_BACKWARD, N_STAGES };
 
-// Records a pair of events around its scope on stream s when timing is enabled.
+// Records a pair of events around its scope on stream s when timing is enabled
+// and the stream is not being captured into a graph.
 class StageTimer {
  public:
   StageTimer(int stage, hipStream_t s);
@@ -57,51 +74,76 @@ class StageTimer {
   void* b_ = nullptr;
   bool active_ = false;
 };
-int check_device();          // CSC_OK or CSC_UNSUPPORTED_DEVICE / CSC_HIP_ERROR
 
 inline unsigned grid_1d(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// largest m with table[m] <= x over table[0..n] (ascending, table[0] = 0 <= x)
+template <typename T>
+__host__ __device__ inline int find_segment(const T* table, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)table[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 }  // namespace csc
 
-// The handle. Device arrays live in one arena allocation.
+// The handle: a batch of one or more meshes. Device arrays live in one arena.
 struct csc_features {
-  const float* verts = nullptr;
-  const int32_t* tris = nullptr;
-  int64_t nv = 0, nf = 0, ne = 0;
-  csc_grid grid{};
+  int32_t n_meshes = 0;
+  std::vector<csc::MeshDesc> mesh;  // host copy of the descriptors
+  const float* verts = nullptr;     // caller's vertices, all meshes concatenated
+  int64_t nv = 0, nf = 0, ne = 0;   // totals over the batch
+  int64_t nbt = 0;                  // bricks of all grids
   csc_options opt{};
-  int32_t nb[3] = {0, 0, 0};   // bricks per axis
-  int64_t nbricks_total = 0;   // nb[0]*nb[1]*nb[2]
+  int sort_bits = 1;
 
   char* arena = nullptr;
   size_t arena_bytes = 0;
 
-  int32_t* vtx_off = nullptr;     // [nv+1]
-  int32_t* vtx_faces = nullptr;   // [3nf], per vertex its corners 3f+j, ascending
-  int32_t* face_edges = nullptr;  // [3nf]
-  int4* edges = nullptr;          // [ne] (a, b, f_left, f_right)
-  float4* face_n = nullptr;       // [nf] unit normal
-  uint8_t* edge_cls = nullptr;    // [ne] class | side bits << 2
-  float4* vinfo = nullptr;        // [nv] unit pseudonormal, cone aperture cosine
-  uint32_t* vbits = nullptr;      // [nv] class bits
-  int32_t* epoly = nullptr;       // [<= 2ne] (e << 1) | inward
-  int32_t* vpoly = nullptr;       // [<= 2nv] (v << 1) | inward
-  int32_t* brick_index = nullptr; // [nbricks_total] -> slot or -1
-  int32_t* brick_list = nullptr;  // [nbricks_total] slot -> brick
-  int32_t* t_a = nullptr;         // temporaries
+  csc::MeshDesc* d_mesh = nullptr;  // [n_meshes]
+  int32_t* f_off = nullptr;         // [n_meshes+1] first face of each mesh
+  int32_t* v_off = nullptr;         // [n_meshes+1] first vertex
+  int32_t* brick_base = nullptr;    // [n_meshes+1] first brick
+  int32_t* tris_g = nullptr;        // [nf][3] global vertex indices (sanitised)
+  int32_t* face_mesh = nullptr;     // [nf]
+  int32_t* vert_mesh = nullptr;     // [nv]
+  int32_t* vtx_off = nullptr;       // [nv+1]
+  int32_t* vtx_corners = nullptr;   // [3nf] per vertex its corners 3f+j, ascending
+  int32_t* face_edges = nullptr;    // [3nf]
+  int4* edges = nullptr;            // [ne] (a, b, f_left, f_right), global indices
+  float4* face_n = nullptr;         // [nf] unit normal
+  uint8_t* edge_cls = nullptr;      // [ne] class | side bits << 2
+  float4* vinfo = nullptr;          // [nv] unit pseudonormal, cone aperture cosine
+  uint32_t* vbits = nullptr;        // [nv] class bits
+  int32_t* epoly = nullptr;         // [<= 2ne] (e << 1) | inward
+  int32_t* vpoly = nullptr;         // [<= 2nv] (v << 1) | inward
+  int32_t* brick_index = nullptr;   // [nbt] -> slot or -1
+  int32_t* brick_list = nullptr;    // [nbt] slot -> brick
+  int32_t* brick_mesh = nullptr;    // [nbt] slot -> mesh
+  int32_t* first_slot = nullptr;    // [n_meshes+1] first slot of each mesh's bricks
+  int32_t* t_a = nullptr;           // temporaries
   int32_t* t_b = nullptr;
   int32_t* t_c = nullptr;
   int32_t* t_scan = nullptr;
-  void* t_sort = nullptr;         // radix sort scratch
+  void* t_sort = nullptr;           // radix sort scratch
   size_t t_sort_bytes = 0;
-  int64_t* d_stats = nullptr;     // [ST_COUNT]
-  uint32_t* d_err = nullptr;
-  int64_t* h_stats = nullptr;     // pinned host mirror [ST_COUNT + 1]
+  int64_t* d_stats = nullptr;       // [ST_COUNT] counters; ST_ERR holds the error bits
+  int64_t* h_stats = nullptr;       // pinned host mirror [ST_COUNT]
 
+  bool built = false;               // device work queued for the current inputs
+  bool synced = false;              // counts below read back since the last build
   int64_t n_epoly = 0, n_vpoly = 0, n_bricks = 0;
   csc_feature_info info{};
-  bool valid = false;
 };
+
+namespace csc {
+// status of a device-side error word
+int status_from_errors(uint64_t err, int64_t ne_found, int64_t ne_expected);
+}  // namespace csc

@@ -1,5 +1,5 @@
 // Scan conversion of the characteristic polyhedra (Section 5, Section 9,
-// Section 10) and the sign pass (Section 4.1.3).
+// Section 10) and the sign pass (Section 4.1.3), for a batch of meshes.
 //
 // Each polyhedron is walked row by row along the grid axis closest to its main
 // direction (face normal, edge bisector, vertex axis): for every row of its
@@ -13,7 +13,8 @@
 // Small polyhedra take one thread each (the paper's per-extrusion scheme); those
 // with more rows go to an overflow list that a second kernel walks with one
 // wavefront per polyhedron, its lanes splitting the rows (the role of the
-// dynamic-parallelism hybrid of Section 9.1).
+// dynamic-parallelism hybrid of Section 9.1). Item counts are read on the
+// device, so the whole sequence runs without host synchronisation.
 #include "geometry.h"
 #include "internal.h"
 
@@ -23,24 +24,25 @@ enum { KIND_FACE = 0, KIND_EDGE = 1, KIND_VERT = 2 };
 
 struct ScanArgs {
   const float* V;
-  const int32_t* T;
+  const int32_t* T;            // global vertex indices
   const float4* fn;
   const int4* edges;
   const uint8_t* ecls;
   const float4* vinfo;
   const uint32_t* vbits;
-  const int32_t* items;       // edge / vertex polyhedron list (unused for faces)
+  const int32_t* items;        // edge / vertex polyhedron list (unused for faces)
+  const int64_t* n_items_d;    // device count of items (null: n_items)
+  const int32_t* face_mesh;
+  const int32_t* vert_mesh;
+  const MeshDesc* md;
   const int32_t* brick_index;
   unsigned long long* keys;
   unsigned long long* counter;  // optional: number of atomicMin issued (diagnostics)
   int32_t* big_items;           // overflow list of polyhedra with many rows
   int32_t* big_count;
-  int64_t nf, ne, n_items;
-  double o[3];
-  double h, whd, epsd;
-  int n[3];
-  int nb[3];
-  float hf, whf, eps;
+  int64_t* stats;               // error word (brick capacity overflow)
+  int64_t cap;                  // bricks the key store holds
+  int64_t nf, ne, n_items;      // totals; n_items = launch bound
 };
 
 struct Poly {
@@ -50,8 +52,18 @@ struct Poly {
   int anc[3];
   int dim[3];
   int ra, ua, va;   // row axis and the two axes across rows
-  int id;
+  int id;           // global feature id
+  int mesh;
 };
+
+__device__ inline d3 vload_d(const float* V, int64_t i) {
+  return mkd((double)V[3 * i], (double)V[3 * i + 1], (double)V[3 * i + 2]);
+}
+
+__device__ inline f3 unit_f(d3 v) {
+  double l = len(v);
+  return l > 0 ? tof(v * (1.0 / l)) : mk(0.f, 0.f, 0.f);
+}
 
 // axis of the largest |component|
 __device__ inline int major_axis(double x, double y, double z) {
@@ -64,22 +76,13 @@ __device__ inline void set_axes(Poly& q, int ra) {
   q.va = ra == 2 ? 1 : 2;
 }
 
-__device__ inline d3 vload_d(const float* V, int64_t i) {
-  return mkd((double)V[3 * i], (double)V[3 * i + 1], (double)V[3 * i + 2]);
-}
-
-__device__ inline f3 unit_f(d3 v) {
-  double l = len(v);
-  return l > 0 ? tof(v * (1.0 / l)) : mk(0.f, 0.f, 0.f);
-}
-
 // bounding box [lo, hi] (world) -> anchor and dimensions in cells; false if empty
-__device__ inline bool box_cells(const ScanArgs& P, const double lo[3], const double hi[3], Poly& q) {
+__device__ inline bool box_cells(const MeshDesc& G, const double lo[3], const double hi[3], Poly& q) {
   const double marg = 1e-4;
   for (int k = 0; k < 3; k++) {
-    double a = ceil((lo[k] - P.o[k]) / P.h - 0.5 - marg), b = floor((hi[k] - P.o[k]) / P.h - 0.5 + marg);
+    double a = ceil((lo[k] - G.origin[k]) * G.inv_h - 0.5 - marg), b = floor((hi[k] - G.origin[k]) * G.inv_h - 0.5 + marg);
     if (a < 0) a = 0;
-    if (b > P.n[k] - 1) b = P.n[k] - 1;
+    if (b > G.n[k] - 1) b = G.n[k] - 1;
     if (!(a <= b)) return false;
     q.anc[k] = (int)a;
     q.dim[k] = (int)(b - a) + 1;
@@ -87,8 +90,9 @@ __device__ inline bool box_cells(const ScanArgs& P, const double lo[3], const do
   return true;
 }
 
-__device__ inline d3 anchor_centre(const ScanArgs& P, const Poly& q) {
-  return mkd(P.o[0] + (q.anc[0] + 0.5) * P.h, P.o[1] + (q.anc[1] + 0.5) * P.h, P.o[2] + (q.anc[2] + 0.5) * P.h);
+__device__ inline d3 anchor_centre(const MeshDesc& G, const Poly& q) {
+  return mkd(G.origin[0] + (q.anc[0] + 0.5) * G.h, G.origin[1] + (q.anc[1] + 0.5) * G.h,
+             G.origin[2] + (q.anc[2] + 0.5) * G.h);
 }
 
 __device__ inline void set_plane(Poly& q, int i, f3 m, f3 through) {
@@ -100,19 +104,19 @@ __device__ inline void set_plane(Poly& q, int i, f3 m, f3 through) {
 
 // Face prism (Section 8.1): three inward side planes through the edges and the two
 // caps |n . (x - a)| <= band*h (both the outward and inward prism at once).
-__device__ inline int build_face(const ScanArgs& P, int64_t f, Poly& q) {
+__device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f, Poly& q) {
   d3 a = vload_d(P.V, P.T[3 * f]), b = vload_d(P.V, P.T[3 * f + 1]), c = vload_d(P.V, P.T[3 * f + 2]);
   float4 nn = P.fn[f];
   d3 n = mkd(nn.x, nn.y, nn.z);
   double lo[3], hi[3];
   const double A3[3] = {a.x, a.y, a.z}, B3[3] = {b.x, b.y, b.z}, C3[3] = {c.x, c.y, c.z}, N3[3] = {n.x, n.y, n.z};
   for (int k = 0; k < 3; k++) {
-    double r = P.whd * fabs(N3[k]) + P.epsd;
+    double r = G.whd * fabs(N3[k]) + G.epsd;
     lo[k] = fmin(A3[k], fmin(B3[k], C3[k])) - r;
     hi[k] = fmax(A3[k], fmax(B3[k], C3[k])) + r;
   }
-  if (!box_cells(P, lo, hi, q)) return 0;
-  d3 c0 = anchor_centre(P, q);
+  if (!box_cells(G, lo, hi, q)) return 0;
+  d3 c0 = anchor_centre(G, q);
   f3 A = tof(a - c0), B = tof(b - c0), C = tof(c - c0), nf = mk(nn.x, nn.y, nn.z);
   const f3 W[3] = {A, B, C};
   for (int j = 0; j < 3; j++) {
@@ -121,8 +125,8 @@ __device__ inline int build_face(const ScanArgs& P, int64_t f, Poly& q) {
     set_plane(q, j, m * (1.f / l), W[j]);
   }
   float na = dot(nf, A);
-  q.pl[3][0] = -nf.x; q.pl[3][1] = -nf.y; q.pl[3][2] = -nf.z; q.pl[3][3] = na + P.whf;
-  q.pl[4][0] = nf.x;  q.pl[4][1] = nf.y;  q.pl[4][2] = nf.z;  q.pl[4][3] = P.whf - na;
+  q.pl[3][0] = -nf.x; q.pl[3][1] = -nf.y; q.pl[3][2] = -nf.z; q.pl[3][3] = na + G.whf;
+  q.pl[4][0] = nf.x;  q.pl[4][1] = nf.y;  q.pl[4][2] = nf.z;  q.pl[4][3] = G.whf - na;
   q.g[0] = A.x; q.g[1] = A.y; q.g[2] = A.z;
   q.g[3] = B.x; q.g[4] = B.y; q.g[5] = B.z;
   q.g[6] = C.x; q.g[7] = C.y; q.g[8] = C.z;
@@ -135,8 +139,7 @@ __device__ inline int build_face(const ScanArgs& P, int64_t f, Poly& q) {
 // (outward side) or their negatives (inward side), between the end caps, cut by
 // the base plane through the edge with the summed normal (Section 8.2); the far
 // side is the band distance itself (cells with |d| >= band*h are dropped).
-__device__ inline int build_edge(const ScanArgs& P, int64_t item, Poly& q) {
-  int32_t ent = P.items[item];
+__device__ inline int build_edge(const ScanArgs& P, const MeshDesc& G, int32_t ent, Poly& q) {
   int64_t e = ent >> 1;
   double sg = (ent & 1) ? -1.0 : 1.0;
   int4 E = P.edges[e];
@@ -155,23 +158,23 @@ __device__ inline int build_edge(const ScanArgs& P, int64_t item, Poly& q) {
   const double A3[3] = {a.x, a.y, a.z}, B3[3] = {b.x, b.y, b.z};
   double lo[3], hi[3];
   for (int k = 0; k < 3; k++) {
-    double x1 = P.whd * U1[k], x2 = P.whd * U2[k];
+    double x1 = G.whd * U1[k], x2 = G.whd * U2[k];
     double alo = fmin(0.0, fmin(x1, x2)), ahi = fmax(0.0, fmax(x1, x2));
     if (us2 > 1e-12) {  // the arc lies inside the quadrilateral through the tangent intersection
-      double t = P.whd * 2.0 * US[k] / us2;
+      double t = G.whd * 2.0 * US[k] / us2;
       alo = fmin(alo, t);
       ahi = fmax(ahi, t);
     } else {
-      alo = -P.whd;
-      ahi = P.whd;
+      alo = -G.whd;
+      ahi = G.whd;
     }
-    alo = fmax(alo, -P.whd);
-    ahi = fmin(ahi, P.whd);
-    lo[k] = fmin(A3[k], B3[k]) + alo - P.epsd;
-    hi[k] = fmax(A3[k], B3[k]) + ahi + P.epsd;
+    alo = fmax(alo, -G.whd);
+    ahi = fmin(ahi, G.whd);
+    lo[k] = fmin(A3[k], B3[k]) + alo - G.epsd;
+    hi[k] = fmax(A3[k], B3[k]) + ahi + G.epsd;
   }
-  if (!box_cells(P, lo, hi, q)) return 0;
-  d3 c0 = anchor_centre(P, q);
+  if (!box_cells(G, lo, hi, q)) return 0;
+  d3 c0 = anchor_centre(G, q);
   f3 A = tof(a - c0), B = tof(b - c0);
   set_plane(q, 0, unit_f(cross(ed, n1) * (sg * kap)), A);
   set_plane(q, 1, unit_f(cross(n2, ed) * (sg * kap)), A);
@@ -190,8 +193,7 @@ __device__ inline int build_edge(const ScanArgs& P, int64_t item, Poly& q) {
 // Vertex cone (Section 4.2, Section 8.3) about the (possibly reflected)
 // pseudonormal with the most diverging positive-pointing normal on its side, or a
 // hemisphere (Section 4.1.3); box = cone box intersected with the sphere box.
-__device__ inline int build_vertex(const ScanArgs& P, int64_t item, Poly& q) {
-  int32_t ent = P.items[item];
+__device__ inline int build_vertex(const ScanArgs& P, const MeshDesc& G, int32_t ent, Poly& q) {
   int64_t v = ent >> 1;
   double sg = (ent & 1) ? -1.0 : 1.0;
   float4 vi = P.vinfo[v];
@@ -208,17 +210,17 @@ __device__ inline int build_vertex(const ScanArgs& P, int64_t item, Poly& q) {
     double s = sqrt(fmax(0.0, 1.0 - AX[k] * AX[k]));
     double l, u;
     if (hemi) {
-      l = AX[k] > 0 ? -P.whd * s : -P.whd;
-      u = AX[k] < 0 ? P.whd * s : P.whd;
+      l = AX[k] > 0 ? -G.whd * s : -G.whd;
+      u = AX[k] < 0 ? G.whd * s : G.whd;
     } else {
-      l = fmax(-P.whd, fmin(0.0, P.whd * (AX[k] - tn * s)));
-      u = fmin(P.whd, fmax(0.0, P.whd * (AX[k] + tn * s)));
+      l = fmax(-G.whd, fmin(0.0, G.whd * (AX[k] - tn * s)));
+      u = fmin(G.whd, fmax(0.0, G.whd * (AX[k] + tn * s)));
     }
-    lo[k] = P3[k] + l - P.epsd;
-    hi[k] = P3[k] + u + P.epsd;
+    lo[k] = P3[k] + l - G.epsd;
+    hi[k] = P3[k] + u + G.epsd;
   }
-  if (!box_cells(P, lo, hi, q)) return 0;
-  d3 c0 = anchor_centre(P, q);
+  if (!box_cells(G, lo, hi, q)) return 0;
+  d3 c0 = anchor_centre(G, q);
   f3 A = tof(p - c0), axf = tof(ax);
   set_plane(q, 0, axf, A);
   q.cone[0] = axf.x; q.cone[1] = axf.y; q.cone[2] = axf.z;
@@ -227,6 +229,22 @@ __device__ inline int build_vertex(const ScanArgs& P, int64_t item, Poly& q) {
   q.id = (int)(P.nf + P.ne + v);
   set_axes(q, major_axis(ax.x, ax.y, ax.z));
   return q.dim[0] * q.dim[1] * q.dim[2];
+}
+
+template <int KIND>
+__device__ inline int build_poly(const ScanArgs& P, int64_t item, Poly& q) {
+  if constexpr (KIND == KIND_FACE) {
+    q.mesh = P.face_mesh[item];
+    return build_face(P, P.md[q.mesh], item, q);
+  } else if constexpr (KIND == KIND_EDGE) {
+    const int32_t ent = P.items[item];
+    q.mesh = P.face_mesh[P.edges[ent >> 1].z];
+    return build_edge(P, P.md[q.mesh], ent, q);
+  } else {
+    const int32_t ent = P.items[item];
+    q.mesh = P.vert_mesh[ent >> 1];
+    return build_vertex(P, P.md[q.mesh], ent, q);
+  }
 }
 
 __device__ inline int lanes_below(unsigned long long m) {
@@ -247,20 +265,20 @@ struct Rows {
 };
 
 template <int KIND>
-__device__ inline void setup_rows(const Poly& q, float hf, float eps, float whf, Rows& r) {
+__device__ inline void setup_rows(const Poly& q, const MeshDesc& G, Rows& r) {
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
 #pragma unroll
   for (int i = 0; i < NPL; i++) {
-    r.sl[i] = pick(q.pl[i], q.ra) * hf;
+    r.sl[i] = pick(q.pl[i], q.ra) * G.hf;
     r.inv[i] = fabsf(r.sl[i]) > 1e-20f ? 1.f / r.sl[i] : 0.f;
-    r.su[i] = pick(q.pl[i], q.ua) * hf;
-    r.sv[i] = pick(q.pl[i], q.va) * hf;
-    r.k[i] = q.pl[i][3] + eps;
+    r.su[i] = pick(q.pl[i], q.ua) * G.hf;
+    r.sv[i] = pick(q.pl[i], q.va) * G.hf;
+    r.k[i] = q.pl[i][3] + G.eps;
   }
   r.A[0] = pick(q.g, q.ra);
   r.A[1] = pick(q.g, q.ua);
   r.A[2] = pick(q.g, q.va);
-  r.R2 = (whf + eps) * (whf + eps);
+  r.R2 = (G.whf + G.eps) * (G.whf + G.eps);
   r.nt = q.dim[q.ra];
 }
 
@@ -292,11 +310,12 @@ __device__ inline bool row_range(const Rows& r, int du, int dv, float hf, int& t
 
 // exact distance at the candidate cells of one row, and the packed atomic minimum
 template <int KIND>
-__device__ inline unsigned scan_row(const ScanArgs& P, const Poly& q, const Rows& r, int du, int dv) {
+__device__ inline unsigned scan_row(const ScanArgs& P, const MeshDesc& G, const Poly& q, const Rows& r, int du,
+                                    int dv) {
   int t0, t1;
-  if (!row_range<KIND>(r, du, dv, P.hf, t0, t1)) return 0;
+  if (!row_range<KIND>(r, du, dv, G.hf, t0, t1)) return 0;
   unsigned issued = 0;
-  const float hf = P.hf;
+  const float hf = G.hf;
   for (int t = t0; t <= t1; t++) {
     const int di = q.ra == 0 ? t : (q.ua == 0 ? du : dv);
     const int dj = q.ra == 1 ? t : (q.ua == 1 ? du : dv);
@@ -315,30 +334,25 @@ __device__ inline unsigned scan_row(const ScanArgs& P, const Poly& q, const Rows
       const f3 rr = p - mk(q.g[0], q.g[1], q.g[2]);
       const float ct = q.cone[3];
       if (ct > -1.f) {  // cone discriminant with slack
-        const float te = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2])) + P.eps;
+        const float te = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2])) + G.eps;
         if (!(te >= 0.f && te * te >= ct * ct * dot(rr, rr))) continue;
       }
       d = norm3(rr);
     }
-    if (d < P.whf) {
+    if (d < G.whf) {
       const int i = q.anc[0] + di, j = q.anc[1] + dj, k = q.anc[2] + dk;
-      const int64_t bl = (int64_t)(i >> 3) + (int64_t)P.nb[0] * ((j >> 3) + (int64_t)P.nb[1] * (k >> 3));
+      const int64_t bl = (int64_t)G.brick_base + (i >> 3) + (int64_t)G.nb[0] * ((j >> 3) + (int64_t)G.nb[1] * (k >> 3));
       const int32_t slot = P.brick_index[bl];
-      if (slot >= 0) {
+      if (slot >= 0 && slot < P.cap) {
         const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned int)q.id;
         atomicMin(&P.keys[(int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)], key);
         issued++;
+      } else if (slot >= P.cap) {
+        atomicOr((uint32_t*)&P.stats[ST_ERR], ERR_OVERFLOW);
       }
     }
   }
   return issued;
-}
-
-template <int KIND>
-__device__ inline int build_poly(const ScanArgs& P, int64_t item, Poly& q) {
-  if constexpr (KIND == KIND_FACE) return build_face(P, item, q);
-  else if constexpr (KIND == KIND_EDGE) return build_edge(P, item, q);
-  else return build_vertex(P, item, q);
 }
 
 __device__ inline void add_issued(const ScanArgs& P, unsigned issued) {
@@ -348,13 +362,17 @@ __device__ inline void add_issued(const ScanArgs& P, unsigned issued) {
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(P.counter, c);
 }
 
+__device__ inline int64_t item_count(const ScanArgs& P) {
+  return P.n_items_d ? (*P.n_items_d < P.n_items ? *P.n_items_d : P.n_items) : P.n_items;
+}
+
 // one thread per polyhedron; polyhedra with more than SMALL_ROWS rows are appended
 // to the overflow list (one atomic per wavefront)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   Poly q;
-  int nc = item < P.n_items ? build_poly<KIND>(P, item, q) : 0;
+  const int nc = item < item_count(P) ? build_poly<KIND>(P, item, q) : 0;
   const int rows = nc > 0 ? q.dim[q.ua] * q.dim[q.va] : 0;
   const bool big = rows > SMALL_ROWS;
   const unsigned long long m = __ballot(big);
@@ -367,10 +385,11 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   }
   unsigned issued = 0;
   if (nc > 0 && !big) {
+    const MeshDesc& G = P.md[q.mesh];
     Rows r;
-    setup_rows<KIND>(q, P.hf, P.eps, P.whf, r);
+    setup_rows<KIND>(q, G, r);
     for (int dv = 0; dv < q.dim[q.va]; dv++)
-      for (int du = 0; du < q.dim[q.ua]; du++) issued += scan_row<KIND>(P, q, r, du, dv);
+      for (int du = 0; du < q.dim[q.ua]; du++) issued += scan_row<KIND>(P, G, q, r, du, dv);
   }
   add_issued(P, issued);
 }
@@ -385,12 +404,13 @@ __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
   for (int32_t w = blockIdx.x; w < n_big; w += gridDim.x) {
     Poly q;
     if (build_poly<KIND>(P, P.big_items[w], q) <= 0) continue;
+    const MeshDesc& G = P.md[q.mesh];
     Rows r;
-    setup_rows<KIND>(q, P.hf, P.eps, P.whf, r);
+    setup_rows<KIND>(q, G, r);
     const int nu = q.dim[q.ua], rows = nu * q.dim[q.va];
     for (int row = lane; row < rows; row += 64) {
       const int dv = row / nu, du = row - dv * nu;
-      issued += scan_row<KIND>(P, q, r, du, dv);
+      issued += scan_row<KIND>(P, G, q, r, du, dv);
     }
   }
   add_issued(P, issued);
@@ -400,27 +420,49 @@ __global__ void k_zero_i32(int32_t* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// every key of the allocated bricks (device count, capped) set to empty
+__global__ void k_init_keys(unsigned long long* keys, const int64_t* __restrict__ stats, int64_t cap) {
+  const int64_t nb = stats[ST_NBRICKS] < cap ? stats[ST_NBRICKS] : cap;
+  const int64_t n = nb * BRICK_CELLS;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    keys[i] = EMPTY_KEY;
 }
 
 __global__ void k_fill_f32(float* p, int64_t n, float v) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
-// number of set keys per brick
-__global__ __launch_bounds__(512) void k_brick_count(const unsigned long long* __restrict__ keys, int32_t* cnt) {
+// number of set keys per brick slot (0 for slots past the allocated bricks)
+__global__ __launch_bounds__(512) void k_brick_count(const unsigned long long* __restrict__ keys,
+                                                     const int64_t* __restrict__ stats, int64_t cap, int32_t* cnt) {
   __shared__ int ws[8];
-  unsigned long long k = keys[(int64_t)blockIdx.x * BRICK_CELLS + threadIdx.x];
-  unsigned long long m = __ballot(k != EMPTY_KEY);
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = __popcll(m);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int t = 0;
-    for (int w = 0; w < 8; w++) t += ws[w];
-    cnt[blockIdx.x] = t;
+  const int64_t nb = stats[ST_NBRICKS] < cap ? stats[ST_NBRICKS] : cap;
+  for (int64_t s = blockIdx.x; s < cap; s += gridDim.x) {
+    const bool live = s < nb;
+    const unsigned long long k = live ? keys[s * BRICK_CELLS + threadIdx.x] : EMPTY_KEY;
+    const unsigned long long m = __ballot(k != EMPTY_KEY);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int w = 0; w < 8; w++) t += ws[w];
+      cnt[s] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// band offsets of every mesh from the per-brick offsets
+__global__ void k_band_offsets(const int32_t* __restrict__ first_slot, const int32_t* __restrict__ boff, int n_meshes,
+                               int64_t cap, int64_t* band_off) {
+  for (int m = threadIdx.x; m <= n_meshes; m += blockDim.x) {
+    int64_t s = first_slot[m];
+    band_off[m] = boff[s < cap ? s : cap];
   }
 }
 
@@ -432,17 +474,17 @@ struct SignArgs {
   const int32_t* face_edges;
   const float4* vinfo;
   const int32_t* brick_list;
+  const int32_t* brick_mesh;
+  const MeshDesc* md;
   const unsigned long long* keys;
   const int32_t* boff;
+  const int64_t* stats;
   float* sdf;
   int32_t* feat;
   int32_t* cell;
   float* dense;
+  int64_t cap;
   int64_t nf, ne;
-  double o[3];
-  double h;
-  int n[3];
-  int nb[3];
 };
 
 __device__ inline f3 rel(const float* V, int64_t i, d3 c) { return tof(vload_d(V, i) - c); }
@@ -450,62 +492,65 @@ __device__ inline f3 xyz(float4 a) { return mk(a.x, a.y, a.z); }
 
 // Sign of a band cell from the pseudonormal of the lowest-dimensional feature
 // holding its closest point (face normal; edge: sum of the two face normals;
-// vertex: angle-weighted pseudonormal), Section 4.1.3 and Eq. 8.
+// vertex: angle-weighted pseudonormal), Section 4.1.3 and Eq. 8. Writes the band
+// list with each mesh's own feature ids and cell indices.
 __global__ __launch_bounds__(512) void k_sign(SignArgs P) {
-  __shared__ int ws[9];
+  __shared__ int ws[8];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t slot = blockIdx.x;
-  unsigned long long key = P.keys[slot * BRICK_CELLS + t];
-  bool valid = key != EMPTY_KEY;
-  unsigned long long m = __ballot(valid);
-  if (lane == 0) ws[w] = __popcll(m);
-  __syncthreads();
-  if (t == 0) {
-    int acc = 0;
-    for (int i = 0; i < 8; i++) {
-      int c = ws[i];
-      ws[i] = acc;
-      acc += c;
+  const int64_t nb = P.stats[ST_NBRICKS] < P.cap ? P.stats[ST_NBRICKS] : P.cap;
+  for (int64_t slot = blockIdx.x; slot < nb; slot += gridDim.x) {
+    const unsigned long long key = P.keys[slot * BRICK_CELLS + t];
+    const bool valid = key != EMPTY_KEY;
+    const unsigned long long m = __ballot(valid);
+    if (lane == 0) ws[w] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int i = 0; i < w; i++) before += ws[i];
+    __syncthreads();
+    if (!valid) continue;
+    const int64_t out = P.boff[slot] + before + lanes_below(m);
+    const MeshDesc& G = P.md[P.brick_mesh[slot]];
+    const int32_t b = P.brick_list[slot] - G.brick_base;
+    const int bx = b % G.nb[0], by = (b / G.nb[0]) % G.nb[1], bz = b / (G.nb[0] * G.nb[1]);
+    const int i = bx * 8 + (t & 7), j = by * 8 + ((t >> 3) & 7), k = bz * 8 + (t >> 6);
+    const float d = __uint_as_float((uint32_t)(key >> 32));
+    const int32_t id = (int32_t)(key & 0xffffffffu);
+    const d3 c = mkd(G.origin[0] + (i + 0.5) * G.h, G.origin[1] + (j + 0.5) * G.h, G.origin[2] + (k + 0.5) * G.h);
+    f3 qq, N;
+    int32_t local;
+    if (id < P.nf) {
+      const int64_t f = id;
+      float wt[3];
+      int r = closest_triangle(mk(0.f, 0.f, 0.f), rel(P.V, P.T[3 * f], c), rel(P.V, P.T[3 * f + 1], c),
+                               rel(P.V, P.T[3 * f + 2], c), qq, wt);
+      if (r == 0) N = xyz(P.fn[f]);
+      else if (r <= 3) {
+        int4 E = P.edges[P.face_edges[3 * f + r - 1]];
+        N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
+      } else N = xyz(P.vinfo[P.T[3 * f + r - 4]]);
+      local = id - G.f_off;
+    } else if (id < P.nf + P.ne) {
+      const int64_t e = id - P.nf;
+      int4 E = P.edges[e];
+      float tt;
+      qq = closest_segment(mk(0.f, 0.f, 0.f), rel(P.V, E.x, c), rel(P.V, E.y, c), tt);
+      if (tt <= 0.f) N = xyz(P.vinfo[E.x]);
+      else if (tt >= 1.f) N = xyz(P.vinfo[E.y]);
+      else N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
+      local = G.nf + (int32_t)(e - G.e_off);
+    } else {
+      const int64_t v = id - P.nf - P.ne;
+      qq = rel(P.V, v, c);
+      N = xyz(P.vinfo[v]);
+      local = G.nf + G.ne + (int32_t)(v - G.v_off);
     }
+    const float s = dot(mk(-qq.x, -qq.y, -qq.z), N) >= 0.f ? 1.f : -1.f;
+    const int32_t lin = i + G.n[0] * (j + G.n[1] * k);
+    P.sdf[out] = s * d;
+    P.feat[out] = local;
+    P.cell[out] = lin;
+    if (P.dense) P.dense[lin] = s * d;
   }
-  __syncthreads();
-  if (!valid) return;
-  const int64_t out = P.boff[slot] + ws[w] + lanes_below(m);
-  const int32_t b = P.brick_list[slot];
-  const int bx = b % P.nb[0], by = (b / P.nb[0]) % P.nb[1], bz = b / (P.nb[0] * P.nb[1]);
-  const int i = bx * 8 + (t & 7), j = by * 8 + ((t >> 3) & 7), k = bz * 8 + (t >> 6);
-  const float d = __uint_as_float((uint32_t)(key >> 32));
-  const int32_t id = (int32_t)(key & 0xffffffffu);
-  const d3 c = mkd(P.o[0] + (i + 0.5) * P.h, P.o[1] + (j + 0.5) * P.h, P.o[2] + (k + 0.5) * P.h);
-  f3 qq, N;
-  if (id < P.nf) {
-    const int64_t f = id;
-    float wt[3];
-    int r = closest_triangle(mk(0.f, 0.f, 0.f), rel(P.V, P.T[3 * f], c), rel(P.V, P.T[3 * f + 1], c),
-                             rel(P.V, P.T[3 * f + 2], c), qq, wt);
-    if (r == 0) N = xyz(P.fn[f]);
-    else if (r <= 3) {
-      int4 E = P.edges[P.face_edges[3 * f + r - 1]];
-      N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
-    } else N = xyz(P.vinfo[P.T[3 * f + r - 4]]);
-  } else if (id < P.nf + P.ne) {
-    int4 E = P.edges[id - P.nf];
-    float tt;
-    qq = closest_segment(mk(0.f, 0.f, 0.f), rel(P.V, E.x, c), rel(P.V, E.y, c), tt);
-    if (tt <= 0.f) N = xyz(P.vinfo[E.x]);
-    else if (tt >= 1.f) N = xyz(P.vinfo[E.y]);
-    else N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
-  } else {
-    const int64_t v = id - P.nf - P.ne;
-    qq = rel(P.V, v, c);
-    N = xyz(P.vinfo[v]);
-  }
-  const float s = dot(mk(-qq.x, -qq.y, -qq.z), N) >= 0.f ? 1.f : -1.f;
-  const int32_t lin = i + P.n[0] * (j + P.n[1] * k);
-  P.sdf[out] = s * d;
-  P.feat[out] = id;
-  P.cell[out] = lin;
-  if (P.dense) P.dense[lin] = s * d;
 }
 
 }  // namespace csc
@@ -514,170 +559,193 @@ using namespace csc;
 
 namespace {
 size_t au(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr int PERSIST_BLOCKS = 2048;
+
 struct WsLayout {
-  size_t keys, cnt, scan, big, total;
+  size_t keys, cnt, scan, big, boff, ctr, total;
+  int64_t cap;
 };
-WsLayout ws_layout(const csc_features* f) {
+
+int64_t capacity(const csc_features* f) { return f->synced ? f->n_bricks : f->nbt; }
+
+WsLayout ws_layout(const csc_features* f, int64_t cap) {
   WsLayout L;
-  int64_t nb = f->n_bricks;
+  L.cap = cap;
   L.keys = 0;
-  L.cnt = au(sizeof(unsigned long long) * (size_t)(nb * BRICK_CELLS + 1));
-  L.scan = L.cnt + au(sizeof(int32_t) * (size_t)(nb + 1));
-  L.big = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(nb + 1) + 3 * sizeof(unsigned long long));
-  int64_t mx = f->nf > f->n_epoly ? f->nf : f->n_epoly;
-  mx = mx > f->n_vpoly ? mx : f->n_vpoly;
-  L.total = L.big + au(sizeof(int32_t) * (size_t)(mx + 2));
+  L.cnt = au(sizeof(unsigned long long) * (size_t)(cap * BRICK_CELLS + 1));
+  L.scan = L.cnt + au(sizeof(int32_t) * (size_t)(cap + 1));
+  L.big = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(cap + 1));
+  int64_t mx = f->nf > 2 * f->ne ? f->nf : 2 * f->ne;
+  mx = mx > 2 * f->nv ? mx : 2 * f->nv;
+  L.boff = L.big + au(sizeof(int32_t) * (size_t)(mx + 2));
+  L.ctr = L.boff + au(sizeof(int64_t) * (size_t)(f->n_meshes + 1));
+  L.total = L.ctr + au(4 * sizeof(unsigned long long));
   return L;
 }
-}  // namespace
 
-extern "C" int csc_scan_convert_workspace(const csc_features* f, size_t* bytes, int64_t* max_band_cells) {
-  if (!f || !f->valid || !bytes) return CSC_INVALID_ARG;
-  *bytes = ws_layout(f).total;
-  if (max_band_cells) *max_band_cells = f->n_bricks * BRICK_CELLS;
-  return CSC_OK;
+// cap from the workspace size: the largest brick count whose layout fits
+bool cap_from_bytes(const csc_features* f, size_t bytes, WsLayout& L) {
+  int64_t hi = f->nbt, lo = 0;
+  if (ws_layout(f, 0).total > bytes) return false;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) / 2;
+    if (ws_layout(f, mid).total <= bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  L = ws_layout(f, lo);
+  return true;
 }
 
-namespace {
-
-ScanArgs scan_args(const csc_features* f, unsigned long long* keys, unsigned long long* counter) {
+ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap) {
   ScanArgs A;
   A.V = f->verts;
-  A.T = f->tris;
+  A.T = f->tris_g;
   A.fn = f->face_n;
   A.edges = f->edges;
   A.ecls = f->edge_cls;
   A.vinfo = f->vinfo;
   A.vbits = f->vbits;
   A.items = nullptr;
+  A.n_items_d = nullptr;
+  A.face_mesh = f->face_mesh;
+  A.vert_mesh = f->vert_mesh;
+  A.md = f->d_mesh;
   A.brick_index = f->brick_index;
   A.keys = keys;
-  A.counter = counter;
+  A.counter = nullptr;
+  A.big_items = nullptr;
+  A.big_count = nullptr;
+  A.stats = f->d_stats;
+  A.cap = cap;
   A.nf = f->nf;
   A.ne = f->ne;
   A.n_items = 0;
-  for (int k = 0; k < 3; k++) {
-    A.o[k] = f->grid.origin[k];
-    A.n[k] = f->grid.n[k];
-    A.nb[k] = f->nb[k];
-  }
-  A.h = f->grid.h;
-  A.whd = (double)f->grid.band_cells * f->grid.h;
-  A.epsd = (double)f->opt.eps_rel * f->grid.h;
-  A.hf = (float)f->grid.h;
-  A.whf = (float)A.whd;
-  A.eps = (float)A.epsd;
   return A;
 }
-
-constexpr int BIG_BLOCKS = 2048;
 
 template <int KIND>
 void launch_kind(ScanArgs A, int stage, hipStream_t s) {
   StageTimer t(stage, s);
   k_zero_i32<<<1, 64, 0, s>>>(A.big_count, 1);
   k_scan_small<KIND><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
-  k_scan_big<KIND><<<BIG_BLOCKS, 64, 0, s>>>(A);
+  k_scan_big<KIND><<<PERSIST_BLOCKS, 64, 0, s>>>(A);
 }
 
-// key init and the scan launches of the three kinds; counters (3 slots) may be null.
-// big: overflow list of at least max(F, edge polys, vertex polys) + 1 ints.
-void run_scans(const csc_features* f, unsigned long long* keys, unsigned long long* counters, int32_t* big,
-               hipStream_t s) {
-  const int64_t nk = f->n_bricks * BRICK_CELLS;
+// key initialisation and the scan launches of the three kinds; counters
+// (3 slots) may be null; big: overflow list (count, then items)
+void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, unsigned long long* counters,
+               int32_t* big, hipStream_t s) {
   {
     StageTimer t(TS_INIT, s);
-    k_fill_u64<<<grid_1d(nk, 256), 256, 0, s>>>(keys, nk, EMPTY_KEY);
+    k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap);
   }
-  ScanArgs A = scan_args(f, keys, counters);
+  ScanArgs A = scan_args(f, keys, cap);
   A.big_count = big;
   A.big_items = big + 1;
+  A.counter = counters;
   A.n_items = f->nf;
   launch_kind<KIND_FACE>(A, TS_SCAN_FACE, s);
-  if (f->n_epoly > 0) {
-    A.items = f->epoly;
-    A.n_items = f->n_epoly;
-    A.counter = counters ? counters + 1 : nullptr;
-    launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, s);
-  }
-  if (f->n_vpoly > 0) {
-    A.items = f->vpoly;
-    A.n_items = f->n_vpoly;
-    A.counter = counters ? counters + 2 : nullptr;
-    launch_kind<KIND_VERT>(A, TS_SCAN_VERT, s);
-  }
+  A.items = f->epoly;
+  A.n_items = 2 * f->ne;
+  A.n_items_d = &f->d_stats[ST_NEPOLY];
+  A.counter = counters ? counters + 1 : nullptr;
+  launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, s);
+  A.items = f->vpoly;
+  A.n_items = 2 * f->nv;
+  A.n_items_d = &f->d_stats[ST_NVPOLY];
+  A.counter = counters ? counters + 2 : nullptr;
+  launch_kind<KIND_VERT>(A, TS_SCAN_VERT, s);
 }
 
-}  // namespace
-
-extern "C" int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d,
-                                int32_t* feat_d, int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream) {
-  if (!f || !f->valid || !workspace_d || !sdf_d || !feat_d || !cell_d || !n_band_d) return CSC_INVALID_ARG;
-  WsLayout L = ws_layout(f);
-  if (ws_bytes < L.total) return CSC_WORKSPACE_TOO_SMALL;
-  hipStream_t s = (hipStream_t)stream;
+int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d, int32_t* feat_d,
+                      int32_t* cell_d, int64_t* n_band_d, int64_t* band_off_d, float* dense_d, hipStream_t s) {
+  WsLayout L;
+  if (!cap_from_bytes(f, ws_bytes, L)) return CSC_WORKSPACE_TOO_SMALL;
+  const int64_t cap = L.cap;
   char* W = (char*)workspace_d;
   unsigned long long* keys = (unsigned long long*)(W + L.keys);
   int32_t* cnt = (int32_t*)(W + L.cnt);
   int32_t* tmp = (int32_t*)(W + L.scan);
-  const int64_t nk = f->n_bricks * BRICK_CELLS;
-
+  int64_t* boff64 = band_off_d ? band_off_d : (int64_t*)(W + L.boff);
   if (dense_d) {
-    int64_t nd = (int64_t)f->grid.n[0] * f->grid.n[1] * f->grid.n[2];
-    k_fill_f32<<<grid_1d(nd, 256), 256, 0, s>>>(dense_d, nd, __builtin_inff());
+    const MeshDesc& G = f->mesh[0];
+    int64_t nd = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    k_fill_f32<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(dense_d, nd, __builtin_inff());
   }
-  if (nk > 0) run_scans(f, keys, nullptr, (int32_t*)(W + L.big), s);
+  run_scans(f, keys, cap, nullptr, (int32_t*)(W + L.big), s);
   hipError_t e;
   {
     StageTimer t(TS_COUNT, s);
-    if (nk > 0) k_brick_count<<<(unsigned)f->n_bricks, 512, 0, s>>>(keys, cnt);
-    e = exclusive_scan(cnt, cnt, f->n_bricks, tmp, n_band_d, nullptr, s);
+    if (cap > 0) k_brick_count<<<PERSIST_BLOCKS, 512, 0, s>>>(keys, f->d_stats, cap, cnt);
+    e = exclusive_scan(cnt, cnt, cap, tmp, n_band_d, cnt + cap, s);
+    k_band_offsets<<<1, 64, 0, s>>>(f->first_slot, cnt, f->n_meshes, cap, boff64);
   }
   if (e != hipSuccess) return fail_hip(e);
-  if (nk > 0) {
+  if (cap > 0) {
     StageTimer t(TS_SIGN, s);
     SignArgs S;
     S.V = f->verts;
-    S.T = f->tris;
+    S.T = f->tris_g;
     S.fn = f->face_n;
     S.edges = f->edges;
     S.face_edges = f->face_edges;
     S.vinfo = f->vinfo;
     S.brick_list = f->brick_list;
+    S.brick_mesh = f->brick_mesh;
+    S.md = f->d_mesh;
     S.keys = keys;
     S.boff = cnt;
+    S.stats = f->d_stats;
     S.sdf = sdf_d;
     S.feat = feat_d;
     S.cell = cell_d;
     S.dense = dense_d;
+    S.cap = cap;
     S.nf = f->nf;
     S.ne = f->ne;
-    for (int k = 0; k < 3; k++) {
-      S.o[k] = f->grid.origin[k];
-      S.n[k] = f->grid.n[k];
-      S.nb[k] = f->nb[k];
-    }
-    S.h = f->grid.h;
-    k_sign<<<(unsigned)f->n_bricks, 512, 0, s>>>(S);
+    k_sign<<<PERSIST_BLOCKS, 512, 0, s>>>(S);
   }
   e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);
 }
 
+}  // namespace
+
+extern "C" int csc_scan_convert_workspace(const csc_features* f, size_t* bytes, int64_t* max_band_cells) {
+  if (!f || !f->built || !bytes) return CSC_INVALID_ARG;
+  const int64_t cap = capacity(f);
+  *bytes = ws_layout(f, cap).total;
+  if (max_band_cells) *max_band_cells = cap * BRICK_CELLS;
+  return CSC_OK;
+}
+
+extern "C" int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d,
+                                int32_t* feat_d, int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream) {
+  if (!f || !f->built || !workspace_d || !sdf_d || !feat_d || !cell_d || !n_band_d) return CSC_INVALID_ARG;
+  if (dense_d && f->n_meshes != 1) return CSC_INVALID_ARG;
+  return scan_convert_impl(f, workspace_d, ws_bytes, sdf_d, feat_d, cell_d, n_band_d, nullptr, dense_d,
+                           (hipStream_t)stream);
+}
+
+extern "C" int csc_scan_convert_batched(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d,
+                                        int32_t* feat_d, int32_t* cell_d, int64_t* band_off_d, void* stream) {
+  if (!f || !f->built || !workspace_d || !sdf_d || !feat_d || !cell_d || !band_off_d) return CSC_INVALID_ARG;
+  return scan_convert_impl(f, workspace_d, ws_bytes, sdf_d, feat_d, cell_d, nullptr, band_off_d, nullptr,
+                           (hipStream_t)stream);
+}
+
 extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_bytes, int64_t counts[3],
                                       void* stream) {
-  if (!f || !f->valid || !workspace_d || !counts) return CSC_INVALID_ARG;
-  WsLayout L = ws_layout(f);
-  if (ws_bytes < L.total) return CSC_WORKSPACE_TOO_SMALL;
+  if (!f || !f->built || !workspace_d || !counts) return CSC_INVALID_ARG;
+  WsLayout L;
+  if (!cap_from_bytes(f, ws_bytes, L)) return CSC_WORKSPACE_TOO_SMALL;
   hipStream_t s = (hipStream_t)stream;
   char* W = (char*)workspace_d;
-  unsigned long long* keys = (unsigned long long*)(W + L.keys);
-  unsigned long long* ctr = (unsigned long long*)(W + L.scan);  // reuses the scan scratch
-  hipError_t e = hipMemsetAsync(ctr, 0, 3 * sizeof(unsigned long long), s);
-  if (e != hipSuccess) return fail_hip(e);
-  if (f->n_bricks > 0) run_scans(f, keys, ctr, (int32_t*)(W + L.big), s);
+  unsigned long long* ctr = (unsigned long long*)(W + L.ctr);
+  k_zero_u64<<<1, 64, 0, s>>>(ctr, 3);
+  run_scans(f, (unsigned long long*)(W + L.keys), L.cap, ctr, (int32_t*)(W + L.big), s);
   unsigned long long h[3];
-  e = hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail_hip(e);
   for (int i = 0; i < 3; i++) counts[i] = (int64_t)h[i];

@@ -36,6 +36,8 @@ namespace csc {
 StageTimer::StageTimer(int stage, hipStream_t s) : stage_(stage), s_(s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (hipEventCreate((hipEvent_t*)&a_) != hipSuccess) return;
   if (hipEventCreate((hipEvent_t*)&b_) != hipSuccess) {
     (void)hipEventDestroy((hipEvent_t)a_);

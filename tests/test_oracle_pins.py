@@ -263,3 +263,26 @@ def test_feature_distance_of_canonical_feature_is_d(configs):
     assert np.max(np.abs(fd - b["d"])) <= 1e-15
     kinds = np.bincount(np.digitize(b["feat"], [om.F, om.F + om.E]), minlength=3)
     assert np.all(kinds > 0)  # faces, edges and vertices all occur as closest features
+
+
+def test_feature_distance_every_region():
+    """Distance to each single face and edge (every closest-point region of every
+    triangle, all orientations) against the independent NumPy formulation, over a
+    whole grid around an irregular tetrahedron."""
+    v = (np.array([[0.31, 0.28, 0.35], [0.71, 0.33, 0.30], [0.42, 0.74, 0.38], [0.47, 0.45, 0.77]]) ).astype(np.float32)
+    f = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], np.int32)
+    om = oracle.OracleMesh(v, f)
+    g = Grid.unit(24, 3)
+    cells = np.arange(g.ncells)
+    P = oracle.cell_centres(g, cells)
+    for t in range(4):
+        d = om.feature_dist(g, cells, np.full(cells.size, t, np.int32))
+        ref = oracle.allpairs_distance(v, f[t:t + 1], P)
+        assert np.max(np.abs(d - ref)) <= 1e-12, t
+    V = v.astype(np.float64)
+    for e in range(om.E):
+        a, b = V[om.edges[e, 0]], V[om.edges[e, 1]]
+        d = om.feature_dist(g, cells, np.full(cells.size, om.F + e, np.int32))
+        tt = np.clip((P - a) @ (b - a) / ((b - a) @ (b - a)), 0, 1)
+        ref = np.linalg.norm(P - (a + tt[:, None] * (b - a)), axis=1)
+        assert np.max(np.abs(d - ref)) <= 1e-12, e

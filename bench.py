@@ -34,9 +34,12 @@ WORKLOADS = {
     "icosphere5_jitter_256": (2, "jittered icosphere L5: 20,480 triangles, 256^3 grid, band 4, fwd+bwd"),
 }
 PEAK_HBM_GBS = 8000.0
-SINGLE_KERNEL_STAGES = ["init_keys", "scan_faces", "scan_edges", "scan_vertices", "sign", "backward"]
-KERNEL_SYMBOL = {"init_keys": "k_fill_u64", "scan_faces": "k_scan<0>", "scan_edges": "k_scan<1>",
-                 "scan_vertices": "k_scan<2>", "sign": "k_sign", "backward": "k_backward"}
+# stages timed around exactly one kernel launch, and that kernel
+KERNEL_SYMBOL = {"init_keys": "k_init_keys", "scan_faces": "k_scan_small<0>", "scan_edges": "k_scan_small<1>",
+                 "scan_vertices": "k_scan_small<2>", "scan_faces_big": "k_scan_big<0>",
+                 "scan_edges_big": "k_scan_big<1>", "scan_vertices_big": "k_scan_big<2>", "sign": "k_sign",
+                 "backward": "k_backward"}
+SINGLE_KERNEL_STAGES = list(KERNEL_SYMBOL)
 
 
 def kernel_source_sha() -> str:
@@ -62,7 +65,9 @@ def load_traffic(workload: str, kernel: str):
 
 
 def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
-    """Bytes the method itself must move per launch of each single-kernel stage."""
+    """Bytes the method itself must move per launch of each single-kernel stage.
+    atomics: packed atomicMin counts [faces, edges, vertices] of the
+    one-thread-per-polyhedron launches, then of the overflow launches."""
     F, E = info["n_faces"], info["n_edges"]
     if stage == "init_keys":
         return 8 * info["n_bricks"] * 512
@@ -72,6 +77,8 @@ def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
         return 16 * info["n_edge_polyhedra"] + 12 * nv + 12 * F + 8 * atomics[1]
     if stage == "scan_vertices":
         return 16 * info["n_vertex_polyhedra"] + 12 * nv + 8 * atomics[2]
+    if stage.endswith("_big"):  # overflow launches: their atomics (geometry counted above)
+        return 8 * atomics[3 + ["scan_faces_big", "scan_edges_big", "scan_vertices_big"].index(stage)]
     if stage == "sign":         # one key read and (sdf, id, cell) written per band cell
         return 20 * band_cells
     if stage == "backward":     # (sdf, id, cell, dL/dSDF) read, 3 floats added per weighted vertex
@@ -121,6 +128,8 @@ def bench_batch(args):
     name, meshes, grids = meshgen.make_config(cfg)
     dev = torch.device("cuda:0")
     B = P.Batch(meshes, grids, device=dev, backward=True, graph_safe=True)
+    from paper_1903_00353_amd import autotune
+    schedule, _ = autotune.tune_batch(B)
     info = B.f.info()
     atomics = P.csc_scan_convert_count(B.f, B.workspace)
     B.step()
@@ -168,7 +177,7 @@ def bench_batch(args):
     per = []
     for m, (v, f) in enumerate(meshes):
         vt, tt = B.verts[sum(B.nv[:m]):sum(B.nv[:m + 1])], torch.from_numpy(f).to(dev)
-        h = P.csc_build_features(vt, tt, grids[m])
+        h = P.csc_build_features(vt, tt, grids[m], B.options)
         nbytes, mx = P.csc_scan_convert_workspace(h)
         o = (torch.empty(mx, dtype=torch.float32, device=dev), torch.empty(mx, dtype=torch.int32, device=dev),
              torch.empty(mx, dtype=torch.int32, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
@@ -222,8 +231,10 @@ def bench_batch(args):
         "batched_eager": {"value": M / (ms_eager * 1e-3), "ms_per_step": ms_eager},
         "per_mesh": {"value": M_per / (ms_per_mesh * 1e-3), "ms_per_step": ms_per_mesh, "band_size": M_per},
         "speedup_batched_vs_per_mesh": ms_per_mesh / ms_graph,
+        "schedule": {"small_rows": list(schedule)},
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
-        "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2]},
+        "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
+                    "edges_big": atomics[4], "vertices_big": atomics[5]},
         "features": info,
         "kernel_source_sha": kernel_source_sha(),
     }
@@ -271,8 +282,7 @@ def summarize_counters(args):
     copy_name = max(cf, key=lambda k: cf[k] if "copyBuffer" in k else -1)
     gib_kib = float(1 << 20)  # the calibration copies 1 GiB: 1 GiB read, 1 GiB written
     fetch_scale, write_scale = cf[copy_name] / gib_kib, cw[copy_name] / gib_kib
-    symbol_of = {"scan_faces": "k_scan_small<0>", "scan_edges": "k_scan_small<1>", "scan_vertices": "k_scan_small<2>",
-                 "sign": "k_sign", "backward": "k_backward", "init_keys": "k_init_keys"}
+    symbol_of = KERNEL_SYMBOL
     out_path = os.path.join(ROOT, "profiles", "traffic.json")
     rec = json.load(open(out_path)) if os.path.exists(out_path) else {}
     entry = {}
@@ -347,7 +357,10 @@ def main():
     dev = torch.device("cuda:0")
     verts = torch.from_numpy(v).to(dev)
     tris = torch.from_numpy(f).to(dev)
-    feats = P.csc_build_features(verts, tris, g)
+    from paper_1903_00353_amd import autotune
+    schedule, _ = autotune.tune_single(verts, tris, g)
+    opts = P.make_options(small_rows=schedule)
+    feats = P.csc_build_features(verts, tris, g, opts)
     info = feats.info()
     nbytes, mx = P.csc_scan_convert_workspace(feats)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -357,7 +370,7 @@ def main():
     gv = torch.zeros_like(verts)
 
     def forward():
-        P.csc_build_features(verts, tris, g, reuse=feats)
+        P.csc_build_features(verts, tris, g, opts, reuse=feats)
         return P.csc_scan_convert(feats, ws, out, sync_count=False)
 
     def step():
@@ -424,7 +437,9 @@ def main():
                      "algorithmic_bytes": alg, "avg_ms": avg[dom]},
         "fwd": {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd},
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
-        "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2]},
+        "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
+                    "edges_big": atomics[4], "vertices_big": atomics[5]},
+        "schedule": {"small_rows": list(schedule)},
         "features": info,
         "kernel_source_sha": kernel_source_sha(),
     }

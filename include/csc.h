@@ -69,6 +69,9 @@ typedef struct csc_options {
   int32_t saddle_mode;      /* saddle vertices (Section 3.2): 0 cone and its reflection (default),
                                1 hemispheres on both sides, 2 no extrusion (ablation only) */
   int32_t force_both_sides; /* 1: extrude every non-flat edge and every vertex on both sides */
+  int32_t small_rows[3];    /* schedule (faces, edges, vertices): polyhedra with more rows than this
+                               are walked by a wavefront each instead of a single thread; 0 = 32.
+                               Only the speed depends on it (see the autotuner in the binding). */
 } csc_options;
 
 typedef struct csc_features csc_features; /* opaque, library-owned, device resident */
@@ -202,18 +205,22 @@ int csc_sdf_backward_batched(const csc_features* f, const float* sdf_d, const in
                              const float* grad_sdf_d, float* grad_verts_d, void* stream);
 
 /*
- * Diagnostics: run only the key initialisation and the three scan launches and
- * return the number of packed atomicMin operations each issued (counts[0] faces,
- * counts[1] edges, counts[2] vertices). Synchronises `stream`. The band store in
+ * Diagnostics: run only the key initialisation and the scan launches and return
+ * the number of packed atomicMin operations each issued: counts[0..2] by the
+ * one-thread-per-polyhedron launch for faces, edges and vertices, counts[3..5] by
+ * the overflow launch of the same kinds. Synchronises `stream`. The band store in
  * the workspace is left as after a scan, but no band list is written.
  */
-int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_bytes, int64_t counts[3],
+int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_bytes, int64_t counts[6],
                            void* stream);
 
 /*
  * Per-stage timing with HIP events recorded on the stream of each call (stages:
  * 0 build_features, 1 init_keys, 2 scan_faces, 3 scan_edges, 4 scan_vertices,
- * 5 brick_count, 6 sign, 7 backward). While enabled, every call records a pair
+ * 5 brick_count, 6 sign, 7 backward, 8 scan_faces_big, 9 scan_edges_big,
+ * 10 scan_vertices_big; stages 2-4 time the one-thread-per-polyhedron launch of
+ * each kind and 8-10 the wave-per-polyhedron launch over its overflow list,
+ * every other stage one launch or the whole build). While enabled, every call records a pair
  * of events around each stage; csc_timing_read waits for the recorded events and
  * returns the accumulated milliseconds and call counts of the first n stages.
  * Process-wide; not meant for concurrent callers.

@@ -43,7 +43,7 @@ class csc_grid(C.Structure):
 
 class csc_options(C.Structure):
     _fields_ = [("eps_rel", C.c_float), ("ruff_mode", C.c_int32), ("saddle_mode", C.c_int32),
-                ("force_both_sides", C.c_int32)]
+                ("force_both_sides", C.c_int32), ("small_rows", C.c_int32 * 3)]
 
 
 class csc_feature_info(C.Structure):
@@ -64,7 +64,7 @@ EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspac
            "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched"]
 CSC_BUILD_NO_SYNC = 1
 CSC_BUILD_GRAPH_SAFE = 2
-N_STAGES = 8
+N_STAGES = 11
 
 _lib = None
 
@@ -142,8 +142,11 @@ def make_grid(grid) -> csc_grid:
     return g
 
 
-def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0) -> csc_options:
-    return csc_options(float(eps_rel), int(ruff_mode), int(saddle_mode), int(force_both_sides))
+def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0, small_rows=(0, 0, 0)) -> csc_options:
+    o = csc_options(float(eps_rel), int(ruff_mode), int(saddle_mode), int(force_both_sides))
+    for k in range(3):
+        o.small_rows[k] = int(small_rows[k])
+    return o
 
 
 def _ptr(t):
@@ -271,12 +274,13 @@ def csc_sdf_backward(f: Features, band: Band, grad_sdf, grad_verts=None, stream=
 
 
 def csc_scan_convert_count(f: Features, workspace=None, stream=None):
-    """Atomics issued by the face, edge and vertex scans (diagnostic; synchronises)."""
+    """Atomics issued by the scans (diagnostic; synchronises): [faces, edges, vertices]
+    of the one-thread-per-polyhedron launches, then the same of the overflow launches."""
     import torch
     nbytes, _ = csc_scan_convert_workspace(f)
     if workspace is None:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f.verts.device)
-    counts = (C.c_int64 * 3)()
+    counts = (C.c_int64 * 6)()
     _check(lib().csc_scan_convert_count(f.handle, _ptr(workspace), workspace.numel(), counts, _stream(stream)),
            "csc_scan_convert_count")
     return [int(x) for x in counts]

@@ -502,11 +502,15 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                const csc_grid* grids, int32_t n_meshes, const csc_options* opt, int32_t flags, void* stream,
                csc_features** out) {
   if (!verts_d || !tris_d || !nv || !nf || !grids || !out || n_meshes <= 0) return CSC_INVALID_ARG;
-  csc_options o = {1e-3f, 0, 0, 0};
+  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}};
   if (opt) o = *opt;
   if (!(o.eps_rel >= 0) || !(o.eps_rel < 0.5f) || o.ruff_mode < 0 || o.ruff_mode > 1 || o.saddle_mode < 0 ||
       o.saddle_mode > 2)
     return CSC_INVALID_ARG;
+  for (int k = 0; k < 3; k++) {
+    if (o.small_rows[k] < 0) return CSC_INVALID_ARG;
+    if (o.small_rows[k] == 0) o.small_rows[k] = 32;
+  }
   std::vector<MeshDesc> mesh((size_t)n_meshes);
   int64_t tv = 0, tf = 0, te = 0, tb = 0;
   for (int m = 0; m < n_meshes; m++) {
@@ -541,8 +545,9 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
     tv += nv[m];
     tf += nf[m];
     te += 3 * nf[m] / 2;
-    if (tv > INT32_MAX / 2 || tf > INT32_MAX / 4 || tb > (1 << 26)) return tb > (1 << 26) ? CSC_GRID_TOO_LARGE
-                                                                                          : CSC_INVALID_ARG;
+    // feature ids (faces + edges + vertices) must fit in 30 bits of the packed key
+    if (tf + te + tv >= (1 << 30)) return CSC_INVALID_ARG;
+    if (tb > (1 << 26)) return CSC_GRID_TOO_LARGE;
   }
   int dc = check_device();
   if (dc != CSC_OK) return dc;

@@ -43,15 +43,30 @@ struct ScanArgs {
   int64_t* stats;               // error word (brick capacity overflow)
   int64_t cap;                  // bricks the key store holds
   int64_t nf, ne, n_items;      // totals; n_items = launch bound
+  int32_t small_rows;           // more rows: one wavefront per polyhedron
+};
+
+// Packed key of a candidate: float bits of |d| in the high word; the low word
+// holds the global feature id in bits 0-29 and, in bits 30-31, the sign when
+// this polyhedron alone decides it (0 outside, 1 inside) or 2 when the sign pass
+// must decide it (a face whose closest point lies on its boundary). The minimum
+// keeps the smallest (|d| bits, sign code, id).
+constexpr uint32_t SIGN_POS = 0u, SIGN_NEG = 1u, SIGN_OPEN = 2u;
+constexpr uint32_t ID_MASK = 0x3fffffffu;
+
+struct I3 {
+  int x, y, z;
 };
 
 struct Poly {
   float pl[5][4];   // inside: m . p + off >= -eps  (p relative to the anchor cell centre)
   float g[9];       // feature points relative to the anchor cell centre
-  float cone[4];    // vertex: axis, aperture cosine (or -2 for a hemisphere)
-  int anc[3];
-  int dim[3];
+  float cone[4];    // vertex: axis, aperture cosine (or -2 for a hemisphere); face: unit normal
+  float side;       // +1 outward polyhedron, -1 inward (edges and vertices)
+  I3 anc;           // anchor cell (lowest corner of the box)
+  I3 dim;           // box extent in cells
   int ra, ua, va;   // row axis and the two axes across rows
+  int nt, nu, nv;   // cells along ra, ua, va (resolved once: no runtime-indexed arrays)
   int id;           // global feature id
   int mesh;
 };
@@ -74,25 +89,35 @@ __device__ inline void set_axes(Poly& q, int ra) {
   q.ra = ra;
   q.ua = ra == 0 ? 1 : 0;
   q.va = ra == 2 ? 1 : 2;
+  // arithmetic blends: a select over record fields would be turned into a load
+  // from a selected address, which keeps the whole record in scratch memory
+  q.nt = q.dim.x * (ra == 0) + q.dim.y * (ra == 1) + q.dim.z * (ra == 2);
+  q.nu = q.dim.y * (ra == 0) + q.dim.x * (ra != 0);
+  q.nv = q.dim.y * (ra == 2) + q.dim.z * (ra != 2);
+}
+
+// one axis of a box: first cell and number of cells whose centres lie in [lo, hi]
+__device__ inline bool axis_cells(double lo, double hi, double o, double ih, int n, int& a0, int& cnt) {
+  const double marg = 1e-4;
+  double a = ceil((lo - o) * ih - 0.5 - marg), b = floor((hi - o) * ih - 0.5 + marg);
+  if (a < 0) a = 0;
+  if (b > n - 1) b = n - 1;
+  if (!(a <= b)) return false;
+  a0 = (int)a;
+  cnt = (int)(b - a) + 1;
+  return true;
 }
 
 // bounding box [lo, hi] (world) -> anchor and dimensions in cells; false if empty
 __device__ inline bool box_cells(const MeshDesc& G, const double lo[3], const double hi[3], Poly& q) {
-  const double marg = 1e-4;
-  for (int k = 0; k < 3; k++) {
-    double a = ceil((lo[k] - G.origin[k]) * G.inv_h - 0.5 - marg), b = floor((hi[k] - G.origin[k]) * G.inv_h - 0.5 + marg);
-    if (a < 0) a = 0;
-    if (b > G.n[k] - 1) b = G.n[k] - 1;
-    if (!(a <= b)) return false;
-    q.anc[k] = (int)a;
-    q.dim[k] = (int)(b - a) + 1;
-  }
-  return true;
+  return axis_cells(lo[0], hi[0], G.origin[0], G.inv_h, G.n[0], q.anc.x, q.dim.x) &&
+         axis_cells(lo[1], hi[1], G.origin[1], G.inv_h, G.n[1], q.anc.y, q.dim.y) &&
+         axis_cells(lo[2], hi[2], G.origin[2], G.inv_h, G.n[2], q.anc.z, q.dim.z);
 }
 
 __device__ inline d3 anchor_centre(const MeshDesc& G, const Poly& q) {
-  return mkd(G.origin[0] + (q.anc[0] + 0.5) * G.h, G.origin[1] + (q.anc[1] + 0.5) * G.h,
-             G.origin[2] + (q.anc[2] + 0.5) * G.h);
+  return mkd(G.origin[0] + (q.anc.x + 0.5) * G.h, G.origin[1] + (q.anc.y + 0.5) * G.h,
+             G.origin[2] + (q.anc.z + 0.5) * G.h);
 }
 
 __device__ inline void set_plane(Poly& q, int i, f3 m, f3 through) {
@@ -130,9 +155,11 @@ __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f
   q.g[0] = A.x; q.g[1] = A.y; q.g[2] = A.z;
   q.g[3] = B.x; q.g[4] = B.y; q.g[5] = B.z;
   q.g[6] = C.x; q.g[7] = C.y; q.g[8] = C.z;
+  q.cone[0] = nf.x; q.cone[1] = nf.y; q.cone[2] = nf.z;
+  q.side = 1.f;
   q.id = (int)f;
   set_axes(q, major_axis(n.x, n.y, n.z));
-  return q.dim[0] * q.dim[1] * q.dim[2];
+  return q.dim.x * q.dim.y * q.dim.z;
 }
 
 // Edge wedge (Section 8.2): the dihedral region spanned by the two face normals
@@ -185,9 +212,10 @@ __device__ inline int build_edge(const ScanArgs& P, const MeshDesc& G, int32_t e
   else { q.pl[4][0] = 0; q.pl[4][1] = 0; q.pl[4][2] = 0; q.pl[4][3] = 0; }
   q.g[0] = A.x; q.g[1] = A.y; q.g[2] = A.z;
   q.g[3] = B.x; q.g[4] = B.y; q.g[5] = B.z;
+  q.side = (float)sg;
   q.id = (int)(P.nf + e);
   set_axes(q, us2 > 1e-12 ? major_axis(us.x, us.y, us.z) : major_axis(ed.x, ed.y, ed.z));
-  return q.dim[0] * q.dim[1] * q.dim[2];
+  return q.dim.x * q.dim.y * q.dim.z;
 }
 
 // Vertex cone (Section 4.2, Section 8.3) about the (possibly reflected)
@@ -226,9 +254,10 @@ __device__ inline int build_vertex(const ScanArgs& P, const MeshDesc& G, int32_t
   q.cone[0] = axf.x; q.cone[1] = axf.y; q.cone[2] = axf.z;
   q.cone[3] = hemi ? -2.f : vi.w;
   q.g[0] = A.x; q.g[1] = A.y; q.g[2] = A.z;
+  q.side = (float)sg;
   q.id = (int)(P.nf + P.ne + v);
   set_axes(q, major_axis(ax.x, ax.y, ax.z));
-  return q.dim[0] * q.dim[1] * q.dim[2];
+  return q.dim.x * q.dim.y * q.dim.z;
 }
 
 template <int KIND>
@@ -251,9 +280,11 @@ __device__ inline int lanes_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-constexpr int SMALL_ROWS = 32;  // polyhedra with more rows go to the wavefront kernel
-
-__device__ inline float pick(const float* v, int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
+// component a of (x, y, z) by value (taking an array's address would force the
+// polyhedron record out of registers)
+__device__ inline float pick3(float x, float y, float z, int a) {
+  return x * (float)(a == 0) + y * (float)(a == 1) + z * (float)(a == 2);
+}
 
 // Per-plane coefficients along a row: the slack-extended test m . p + off >= -eps at
 // cell (t, du, dv) of the row reads  sl * t + su * du + sv * dv + k >= 0.
@@ -269,17 +300,17 @@ __device__ inline void setup_rows(const Poly& q, const MeshDesc& G, Rows& r) {
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
 #pragma unroll
   for (int i = 0; i < NPL; i++) {
-    r.sl[i] = pick(q.pl[i], q.ra) * G.hf;
+    r.sl[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.ra) * G.hf;
     r.inv[i] = fabsf(r.sl[i]) > 1e-20f ? 1.f / r.sl[i] : 0.f;
-    r.su[i] = pick(q.pl[i], q.ua) * G.hf;
-    r.sv[i] = pick(q.pl[i], q.va) * G.hf;
+    r.su[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.ua) * G.hf;
+    r.sv[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.va) * G.hf;
     r.k[i] = q.pl[i][3] + G.eps;
   }
-  r.A[0] = pick(q.g, q.ra);
-  r.A[1] = pick(q.g, q.ua);
-  r.A[2] = pick(q.g, q.va);
+  r.A[0] = pick3(q.g[0], q.g[1], q.g[2], q.ra);
+  r.A[1] = pick3(q.g[0], q.g[1], q.g[2], q.ua);
+  r.A[2] = pick3(q.g[0], q.g[1], q.g[2], q.va);
   r.R2 = (G.whf + G.eps) * (G.whf + G.eps);
-  r.nt = q.dim[q.ra];
+  r.nt = q.nt;
 }
 
 // cells [t0, t1] of row (du, dv) that can lie in the polyhedron (conservative)
@@ -322,29 +353,43 @@ __device__ inline unsigned scan_row(const ScanArgs& P, const MeshDesc& G, const 
     const int dk = q.ra == 2 ? t : (q.ua == 2 ? du : dv);
     const f3 p = mk(di * hf, dj * hf, dk * hf);
     float d;
+    uint32_t code;
     if constexpr (KIND == KIND_FACE) {
       f3 qq;
       float w[3];
-      closest_triangle(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]), mk(q.g[6], q.g[7], q.g[8]), qq, w);
+      const int region = closest_triangle(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]),
+                                          mk(q.g[6], q.g[7], q.g[8]), qq, w);
       d = norm3(p - qq);
+      // interior closest point: the face normal is the pseudonormal
+      code = region != 0 ? SIGN_OPEN
+                         : (dot(p - qq, mk(q.cone[0], q.cone[1], q.cone[2])) >= 0.f ? SIGN_POS : SIGN_NEG);
     } else if constexpr (KIND == KIND_EDGE) {
       float tt;
-      d = norm3(p - closest_segment(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]), tt));
+      const f3 qq = closest_segment(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]), tt);
+      d = norm3(p - qq);
+      // interior of the edge: pseudonormal n1 + n2 = side * (base plane normal) * |n1 + n2|
+      const f3 bis = mk(q.pl[4][0], q.pl[4][1], q.pl[4][2]);
+      const bool ok = tt > 0.f && tt < 1.f && dot(bis, bis) > 0.f;
+      code = !ok ? SIGN_OPEN : (dot(p - qq, bis) * q.side >= 0.f ? SIGN_POS : SIGN_NEG);
     } else {
       const f3 rr = p - mk(q.g[0], q.g[1], q.g[2]);
       const float ct = q.cone[3];
+      const float ta = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2]));
       if (ct > -1.f) {  // cone discriminant with slack
-        const float te = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2])) + G.eps;
+        const float te = ta + G.eps;
         if (!(te >= 0.f && te * te >= ct * ct * dot(rr, rr))) continue;
       }
       d = norm3(rr);
+      // the vertex itself: its angle-weighted pseudonormal (axis = side * N)
+      code = ta * q.side >= 0.f ? SIGN_POS : SIGN_NEG;
     }
     if (d < G.whf) {
-      const int i = q.anc[0] + di, j = q.anc[1] + dj, k = q.anc[2] + dk;
+      const int i = q.anc.x + di, j = q.anc.y + dj, k = q.anc.z + dk;
       const int64_t bl = (int64_t)G.brick_base + (i >> 3) + (int64_t)G.nb[0] * ((j >> 3) + (int64_t)G.nb[1] * (k >> 3));
       const int32_t slot = P.brick_index[bl];
       if (slot >= 0 && slot < P.cap) {
-        const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned int)q.id;
+        const unsigned long long key =
+            ((unsigned long long)__float_as_uint(d) << 32) | (code << 30) | (uint32_t)q.id;
         atomicMin(&P.keys[(int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)], key);
         issued++;
       } else if (slot >= P.cap) {
@@ -355,26 +400,27 @@ __device__ inline unsigned scan_row(const ScanArgs& P, const MeshDesc& G, const 
   return issued;
 }
 
-__device__ inline void add_issued(const ScanArgs& P, unsigned issued) {
+// counter[0] counts the one-thread-per-polyhedron launch, counter[3] the overflow launch
+__device__ inline void add_issued(const ScanArgs& P, unsigned issued, int slot) {
   if (!P.counter) return;
   unsigned long long c = issued;
   for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(P.counter, c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(P.counter + slot, c);
 }
 
 __device__ inline int64_t item_count(const ScanArgs& P) {
   return P.n_items_d ? (*P.n_items_d < P.n_items ? *P.n_items_d : P.n_items) : P.n_items;
 }
 
-// one thread per polyhedron; polyhedra with more than SMALL_ROWS rows are appended
+// one thread per polyhedron; polyhedra with more than small_rows rows are appended
 // to the overflow list (one atomic per wavefront)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   Poly q;
   const int nc = item < item_count(P) ? build_poly<KIND>(P, item, q) : 0;
-  const int rows = nc > 0 ? q.dim[q.ua] * q.dim[q.va] : 0;
-  const bool big = rows > SMALL_ROWS;
+  const int rows = nc > 0 ? q.nu * q.nv : 0;
+  const bool big = rows > P.small_rows;
   const unsigned long long m = __ballot(big);
   if (m) {
     int base = 0;
@@ -388,10 +434,10 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
     const MeshDesc& G = P.md[q.mesh];
     Rows r;
     setup_rows<KIND>(q, G, r);
-    for (int dv = 0; dv < q.dim[q.va]; dv++)
-      for (int du = 0; du < q.dim[q.ua]; du++) issued += scan_row<KIND>(P, G, q, r, du, dv);
+    for (int dv = 0; dv < q.nv; dv++)
+      for (int du = 0; du < q.nu; du++) issued += scan_row<KIND>(P, G, q, r, du, dv);
   }
-  add_issued(P, issued);
+  add_issued(P, issued, 0);
 }
 
 // a wavefront per polyhedron of the overflow list, lanes striding over its rows;
@@ -407,13 +453,13 @@ __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
     const MeshDesc& G = P.md[q.mesh];
     Rows r;
     setup_rows<KIND>(q, G, r);
-    const int nu = q.dim[q.ua], rows = nu * q.dim[q.va];
+    const int nu = q.nu, rows = nu * q.nv;
     for (int row = lane; row < rows; row += 64) {
       const int dv = row / nu, du = row - dv * nu;
       issued += scan_row<KIND>(P, G, q, r, du, dv);
     }
   }
-  add_issued(P, issued);
+  add_issued(P, issued, 3);
 }
 
 __global__ void k_zero_i32(int32_t* p, int n) {
@@ -514,11 +560,16 @@ __global__ __launch_bounds__(512) void k_sign(SignArgs P) {
     const int bx = b % G.nb[0], by = (b / G.nb[0]) % G.nb[1], bz = b / (G.nb[0] * G.nb[1]);
     const int i = bx * 8 + (t & 7), j = by * 8 + ((t >> 3) & 7), k = bz * 8 + (t >> 6);
     const float d = __uint_as_float((uint32_t)(key >> 32));
-    const int32_t id = (int32_t)(key & 0xffffffffu);
+    const uint32_t code = ((uint32_t)key) >> 30;
+    const int32_t id = (int32_t)((uint32_t)key & ID_MASK);
     const d3 c = mkd(G.origin[0] + (i + 0.5) * G.h, G.origin[1] + (j + 0.5) * G.h, G.origin[2] + (k + 0.5) * G.h);
-    f3 qq, N;
+    f3 qq = mk(0.f, 0.f, 0.f), N = mk(0.f, 0.f, 0.f);
     int32_t local;
-    if (id < P.nf) {
+    if (code != SIGN_OPEN) {  // decided by the winning polyhedron
+      local = id < P.nf ? id - G.f_off
+                        : (id < P.nf + P.ne ? G.nf + (int32_t)(id - P.nf - G.e_off)
+                                            : G.nf + G.ne + (int32_t)(id - P.nf - P.ne - G.v_off));
+    } else if (id < P.nf) {
       const int64_t f = id;
       float wt[3];
       int r = closest_triangle(mk(0.f, 0.f, 0.f), rel(P.V, P.T[3 * f], c), rel(P.V, P.T[3 * f + 1], c),
@@ -544,7 +595,8 @@ __global__ __launch_bounds__(512) void k_sign(SignArgs P) {
       N = xyz(P.vinfo[v]);
       local = G.nf + G.ne + (int32_t)(v - G.v_off);
     }
-    const float s = dot(mk(-qq.x, -qq.y, -qq.z), N) >= 0.f ? 1.f : -1.f;
+    const float s = code == SIGN_POS ? 1.f
+                  : (code == SIGN_NEG ? -1.f : (dot(mk(-qq.x, -qq.y, -qq.z), N) >= 0.f ? 1.f : -1.f));
     const int32_t lin = i + G.n[0] * (j + G.n[1] * k);
     P.sdf[out] = s * d;
     P.feat[out] = local;
@@ -579,7 +631,7 @@ WsLayout ws_layout(const csc_features* f, int64_t cap) {
   mx = mx > 2 * f->nv ? mx : 2 * f->nv;
   L.boff = L.big + au(sizeof(int32_t) * (size_t)(mx + 2));
   L.ctr = L.boff + au(sizeof(int64_t) * (size_t)(f->n_meshes + 1));
-  L.total = L.ctr + au(4 * sizeof(unsigned long long));
+  L.total = L.ctr + au(8 * sizeof(unsigned long long));
   return L;
 }
 
@@ -620,14 +672,18 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.nf = f->nf;
   A.ne = f->ne;
   A.n_items = 0;
+  A.small_rows = 32;
   return A;
 }
 
 template <int KIND>
-void launch_kind(ScanArgs A, int stage, hipStream_t s) {
-  StageTimer t(stage, s);
+void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s) {
   k_zero_i32<<<1, 64, 0, s>>>(A.big_count, 1);
-  k_scan_small<KIND><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
+  {
+    StageTimer t(stage, s);
+    k_scan_small<KIND><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
+  }
+  StageTimer t(stage_big, s);
   k_scan_big<KIND><<<PERSIST_BLOCKS, 64, 0, s>>>(A);
 }
 
@@ -644,17 +700,20 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.big_items = big + 1;
   A.counter = counters;
   A.n_items = f->nf;
-  launch_kind<KIND_FACE>(A, TS_SCAN_FACE, s);
+  A.small_rows = f->opt.small_rows[0];
+  launch_kind<KIND_FACE>(A, TS_SCAN_FACE, TS_SCAN_FACE_BIG, s);
+  A.small_rows = f->opt.small_rows[1];
   A.items = f->epoly;
   A.n_items = 2 * f->ne;
   A.n_items_d = &f->d_stats[ST_NEPOLY];
   A.counter = counters ? counters + 1 : nullptr;
-  launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, s);
+  launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, TS_SCAN_EDGE_BIG, s);
+  A.small_rows = f->opt.small_rows[2];
   A.items = f->vpoly;
   A.n_items = 2 * f->nv;
   A.n_items_d = &f->d_stats[ST_NVPOLY];
   A.counter = counters ? counters + 2 : nullptr;
-  launch_kind<KIND_VERT>(A, TS_SCAN_VERT, s);
+  launch_kind<KIND_VERT>(A, TS_SCAN_VERT, TS_SCAN_VERT_BIG, s);
 }
 
 int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d, int32_t* feat_d,
@@ -734,7 +793,7 @@ extern "C" int csc_scan_convert_batched(const csc_features* f, void* workspace_d
                            (hipStream_t)stream);
 }
 
-extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_bytes, int64_t counts[3],
+extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_bytes, int64_t counts[6],
                                       void* stream) {
   if (!f || !f->built || !workspace_d || !counts) return CSC_INVALID_ARG;
   WsLayout L;
@@ -742,12 +801,12 @@ extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, 
   hipStream_t s = (hipStream_t)stream;
   char* W = (char*)workspace_d;
   unsigned long long* ctr = (unsigned long long*)(W + L.ctr);
-  k_zero_u64<<<1, 64, 0, s>>>(ctr, 3);
+  k_zero_u64<<<1, 64, 0, s>>>(ctr, 6);
   run_scans(f, (unsigned long long*)(W + L.keys), L.cap, ctr, (int32_t*)(W + L.big), s);
-  unsigned long long h[3];
+  unsigned long long h[6];
   hipError_t e = hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail_hip(e);
-  for (int i = 0; i < 3; i++) counts[i] = (int64_t)h[i];
+  for (int i = 0; i < 6; i++) counts[i] = (int64_t)h[i];
   return CSC_OK;
 }

@@ -14,8 +14,9 @@ bool g_on = false;
 std::vector<Rec> g_pending;
 double g_ms[csc::N_STAGES];
 int64_t g_calls[csc::N_STAGES];
-const char* g_names[csc::N_STAGES] = {"build_features", "init_keys",  "scan_faces", "scan_edges",
-                                      "scan_vertices",  "brick_count", "sign",      "backward"};
+const char* g_names[csc::N_STAGES] = {"build_features", "init_keys",      "scan_faces",     "scan_edges",
+                                      "scan_vertices",  "brick_count",    "sign",           "backward",
+                                      "scan_faces_big", "scan_edges_big", "scan_vertices_big"};
 
 void drain_locked() {
   for (Rec& r : g_pending) {

@@ -95,7 +95,7 @@ def test_timing_api_without_device():
     P.csc_timing_reset()
     t = P.csc_timing_read()
     assert list(t) == ["build_features", "init_keys", "scan_faces", "scan_edges", "scan_vertices", "brick_count",
-                       "sign", "backward"]
+                       "sign", "backward", "scan_faces_big", "scan_edges_big", "scan_vertices_big"]
     assert all(v == (0.0, 0) for v in t.values())
 
 
@@ -197,3 +197,33 @@ def test_ruff_vertex_gets_hemisphere():
     assert abs(ct - min(nn @ N for nn in normals if nn @ N > 0)) < 1e-12
     bits1, _, _ = P.csc_classify_vertex(np.zeros(3), _fan(np.zeros(3), ring), P.make_options(ruff_mode=1))
     assert bits1 & 256 and not bits1 & 4
+
+
+@pytest.mark.parametrize("case", ["n0", "null_sizes", "odd_faces_mesh1", "bad_grid_mesh2", "zero_verts", "flags"])
+def test_batched_host_argument_checks(case):
+    L = P.lib()
+    fake = C.c_void_p(0x1000)  # never dereferenced: every case fails its host check first
+    n = 3
+    grids = (P.csc_grid * n)(*[_grid() for _ in range(n)])
+    nv = (C.c_int64 * n)(8, 8, 8)
+    nf = (C.c_int64 * n)(12, 12, 12)
+    opt = P.make_options()
+    out = C.c_void_p(None)
+    flags = 0
+    nn = n
+    nva, nfa = nv, nf
+    if case == "n0":
+        nn = 0
+    elif case == "null_sizes":
+        nva = None
+    elif case == "odd_faces_mesh1":
+        nf[1] = 13
+    elif case == "bad_grid_mesh2":
+        grids[2].h = -1.0
+    elif case == "zero_verts":
+        nv[0] = 0
+    elif case == "flags":
+        flags = 1  # NO_SYNC without an existing handle
+    code = L.csc_build_features_batched(fake, fake, nva, nfa, grids, nn, C.byref(opt), flags, None, C.byref(out))
+    assert code == {"odd_faces_mesh1": 2}.get(case, 1)
+    assert out.value is None

@@ -98,3 +98,27 @@ def test_batch_rejects_bad_mesh():
     with pytest.raises(P.CscError) as ei:
         P.Batch(meshes, grids)
     assert ei.value.code == 1
+
+
+def test_schedule_does_not_change_results():
+    """The wavefront/thread threshold only changes the speed: every schedule gives the
+    same band bit for bit; the autotuner picks one of its candidates per kind."""
+    meshes, grids = small_batch(6)
+    ref = None
+    for rows in ((1 << 30,) * 3, (0, 0, 0), (4, 8, 2), (1, 1, 1)):
+        B = P.Batch(meshes, grids, options=P.make_options(small_rows=rows), backward=False)
+        B.step()
+        B.check()
+        cur = [batch_band(B, m) for m in range(len(meshes))]
+        if ref is None:
+            ref = cur
+        for a, b in zip(ref, cur):
+            assert all(np.array_equal(x, y) for x, y in zip(a, b)), rows
+    from paper_1903_00353_amd import autotune
+    B = P.Batch(meshes, grids, backward=True)
+    best, timings = autotune.tune_batch(B, use_cache=False, reps=1)
+    assert len(best) == 3 and all(b in autotune.CANDIDATES for b in best)
+    B.step()
+    B.check()
+    for a, b in zip(ref, [batch_band(B, m) for m in range(len(meshes))]):
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))

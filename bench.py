@@ -111,6 +111,52 @@ def cpu_baseline(v, f, grid, budget_s=15.0):
                       f"one-time edge table and normals excluded"}
 
 
+def timed_steps(fn, steps):
+    """Run fn `steps` times between two device synchronisations. Returns the mean
+    wall-clock ms per step over the bracket and the per-step ms from HIP events
+    recorded between the steps on the current stream (median, minimum)."""
+    import statistics
+
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i].record()
+        fn()
+    ev[steps].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return (t1 - t0) * 1e3 / steps, statistics.median(per), min(per)
+
+
+def stage_averages(fn, steps):
+    """Mean ms per launch of every library stage over `steps` eager calls of fn
+    (the library's own HIP events on the stream each kernel is launched on)."""
+    import torch
+
+    import paper_1903_00353_amd as P
+    torch.cuda.synchronize()
+    P.csc_timing_reset()
+    P.csc_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.csc_timing_enable(False)
+    stages = P.csc_timing_read()
+    return {k: (ms / c if c else 0.0) for k, (ms, c) in stages.items()}, (t1 - t0) * 1e3 / steps
+
+
+def parse_rows(text):
+    rows = tuple(int(x) for x in text.split(","))
+    if len(rows) != 3 or min(rows) < 1:
+        raise SystemExit("--small-rows takes three positive integers: faces,edges,vertices")
+    return rows
+
+
 def batch_algorithmic_bytes(stage, nf, nv, n_epoly, n_vpoly, atomics, band_cells, vert_refs, n_bricks):
     info = {"n_faces": nf, "n_edges": 3 * nf // 2, "n_edge_polyhedra": n_epoly, "n_vertex_polyhedra": n_vpoly,
             "n_bricks": n_bricks}
@@ -118,7 +164,6 @@ def batch_algorithmic_bytes(stage, nf, nv, n_epoly, n_vpoly, atomics, band_cells
 
 
 def bench_batch(args):
-    import numpy as np
     import torch
 
     import meshgen
@@ -129,8 +174,15 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     B = P.Batch(meshes, grids, device=dev, backward=True, graph_safe=True)
     from paper_1903_00353_amd import autotune
-    schedule, _ = autotune.tune_batch(B)
+    if args.small_rows:
+        schedule = parse_rows(args.small_rows)
+        B.options = P.make_options(small_rows=schedule)
+        B.f = P.csc_build_features_batched(B.verts, B.tris, B.nv, B.nf, B.grids, B.options, flags=B.flags,
+                                           reuse=B.f)
+    else:
+        schedule, _ = autotune.tune_batch(B)
     info = B.f.info()
+    # untimed diagnostics: atomics per scan launch, band size, weighted vertices per band cell
     atomics = P.csc_scan_convert_count(B.f, B.workspace)
     B.step()
     torch.cuda.synchronize()
@@ -138,72 +190,26 @@ def bench_batch(args):
     off = B.band_off.cpu().numpy()
     M = int(off[-1])
     feat = B.out[1][:M].cpu().numpy()
-    # weighted vertices per band cell from each mesh's own feature numbering
     vert_refs = 0
     for m, (v, f) in enumerate(meshes):
         fe = feat[off[m]:off[m + 1]]
         F, E = f.shape[0], 3 * f.shape[0] // 2
         vert_refs += int(3 * (fe < F).sum() + 2 * ((fe >= F) & (fe < F + E)).sum() + (fe >= F + E).sum())
 
-    # batched: one captured graph per step
-    B.capture()
+    # the timed step: one replay of the captured batched graph (build, scan, sign, 2*SDF, adjoint)
+    run = B.step
+    if not args.no_graph:
+        B.capture()
+        run = B.replay
     for _ in range(args.warmup):
-        B.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        B.replay()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+        run()
+    ms_graph, med_graph, min_graph = timed_steps(run, args.steps)
     B.check()
-    ms_graph = (t1 - t0) * 1e3 / args.steps
 
-    # batched eager steps with per-stage events (roofline of the dominant kernel)
+    # the same step launched eagerly, with the library's per-stage events (roofline)
     for _ in range(max(1, args.warmup)):
         B.step()
-    torch.cuda.synchronize()
-    P.csc_timing_reset()
-    P.csc_timing_enable(True)
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        B.step()
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    P.csc_timing_enable(False)
-    stages = P.csc_timing_read()
-    ms_eager = (t3 - t2) * 1e3 / args.steps
-
-    # per-mesh plain launches: 64 x (build, scan, adjoint), handles and buffers reused
-    per = []
-    for m, (v, f) in enumerate(meshes):
-        vt, tt = B.verts[sum(B.nv[:m]):sum(B.nv[:m + 1])], torch.from_numpy(f).to(dev)
-        h = P.csc_build_features(vt, tt, grids[m], B.options)
-        nbytes, mx = P.csc_scan_convert_workspace(h)
-        o = (torch.empty(mx, dtype=torch.float32, device=dev), torch.empty(mx, dtype=torch.int32, device=dev),
-             torch.empty(mx, dtype=torch.int32, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
-        per.append((vt, tt, grids[m], h, torch.empty(nbytes, dtype=torch.uint8, device=dev), o,
-                    torch.empty(mx, dtype=torch.float32, device=dev), torch.zeros_like(vt)))
-
-    def per_mesh_step():
-        for vt, tt, g, h, ws, o, gsd, gv in per:
-            P.csc_build_features(vt, tt, g, reuse=h)
-            band = P.csc_scan_convert(h, ws, o, sync_count=False)
-            torch.mul(o[0], 2.0, out=gsd)
-            gv.zero_()
-            P.csc_sdf_backward(h, band, gsd, gv, n_band_d=o[3])
-
-    for _ in range(args.warmup):
-        per_mesh_step()
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    for _ in range(args.steps):
-        per_mesh_step()
-    torch.cuda.synchronize()
-    t5 = time.perf_counter()
-    ms_per_mesh = (t5 - t4) * 1e3 / args.steps
-    M_per = sum(int(x[5][3].item()) for x in per)
-
-    avg = {k: (ms / c if c else 0.0) for k, (ms, c) in stages.items()}
+    avg, ms_eager = stage_averages(B.step, args.steps)
     dom = max(SINGLE_KERNEL_STAGES, key=lambda k: avg[k])
     alg = batch_algorithmic_bytes(dom, int(info["n_faces"]), int(info["n_vertices"]),
                                   int(info["n_edge_polyhedra"]), int(info["n_vertex_polyhedra"]), atomics, M,
@@ -228,9 +234,8 @@ def bench_batch(args):
         "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("batch64", dom),
                      "algorithmic_bytes": alg, "avg_ms": avg[dom], "measured_on": "eager batched steps"},
+        "step_ms": {"median": med_graph, "min": min_graph, "launch": "eager" if args.no_graph else "graph replay"},
         "batched_eager": {"value": M / (ms_eager * 1e-3), "ms_per_step": ms_eager},
-        "per_mesh": {"value": M_per / (ms_per_mesh * 1e-3), "ms_per_step": ms_per_mesh, "band_size": M_per},
-        "speedup_batched_vs_per_mesh": ms_per_mesh / ms_graph,
         "schedule": {"small_rows": list(schedule)},
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
         "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
@@ -238,30 +243,72 @@ def bench_batch(args):
         "features": info,
         "kernel_source_sha": kernel_source_sha(),
     }
+    if args.timed_only:
+        print(json.dumps(res))
+        return
+
+    # forward only (build, scan, sign), batched eager
+    B.backward = False
+    B.step()
+    ms_fwd, med_fwd, min_fwd = timed_steps(B.step, args.steps)
+    B.backward = True
+    B.check()
+    res["fwd"] = {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd, "median": med_fwd, "min": min_fwd,
+                  "launch": "eager"}
+
+    # per-mesh plain launches: 64 x (build, scan, adjoint), handles and buffers reused
+    per = []
+    for m, (v, f) in enumerate(meshes):
+        vt, tt = B.verts[sum(B.nv[:m]):sum(B.nv[:m + 1])], torch.from_numpy(f).to(dev)
+        h = P.csc_build_features(vt, tt, grids[m], B.options)
+        nbytes, mx = P.csc_scan_convert_workspace(h)
+        o = (torch.empty(mx, dtype=torch.float32, device=dev), torch.empty(mx, dtype=torch.int32, device=dev),
+             torch.empty(mx, dtype=torch.int32, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+        per.append((vt, tt, grids[m], h, torch.empty(nbytes, dtype=torch.uint8, device=dev), o,
+                    torch.empty(mx, dtype=torch.float32, device=dev), torch.zeros_like(vt)))
+
+    def per_mesh_step():
+        for vt, tt, g, h, ws, o, gsd, gv in per:
+            P.csc_build_features(vt, tt, g, reuse=h)
+            band = P.csc_scan_convert(h, ws, o, sync_count=False)
+            torch.mul(o[0], 2.0, out=gsd)
+            gv.zero_()
+            P.csc_sdf_backward(h, band, gsd, gv, n_band_d=o[3])
+
+    for _ in range(args.warmup):
+        per_mesh_step()
+    ms_per_mesh, med_pm, min_pm = timed_steps(per_mesh_step, args.steps)
+    M_per = sum(int(x[5][3].item()) for x in per)
+    res["per_mesh"] = {"value": M_per / (ms_per_mesh * 1e-3), "ms_per_step": ms_per_mesh, "median": med_pm,
+                       "min": min_pm, "band_size": M_per}
+    res["speedup_batched_vs_per_mesh"] = ms_per_mesh / ms_graph
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_batch(meshes, grids, args.cpu_budget)
     print(json.dumps(res))
 
 
 def cpu_baseline_batch(meshes, grids, budget_s=15.0):
-    """The oracle on the host cores over whole meshes of the batch, in order, until
-    about budget_s seconds of band computation have been spent."""
+    """The oracle on the host cores over whole meshes of the batch, in order
+    (repeating the batch if it ends first), until about budget_s seconds of band
+    computation have been spent."""
     import oracle
     cells, spent, done, threads = 0, 0.0, 0, 1
-    for (v, f), g in zip(meshes, grids):
-        om = oracle.OracleMesh(v, f)
+    oms = {}
+    while spent < budget_s and done < 64 * len(meshes):
+        m = done % len(meshes)
+        if m not in oms:
+            oms[m] = oracle.OracleMesh(*meshes[m])
         t0 = time.perf_counter()
-        b = om.band(g)
+        b = oms[m].band(grids[m])
         spent += time.perf_counter() - t0
         cells += int(((b["flags"] & oracle.FLAG_IN_BAND) > 0).sum())
         threads = b["threads"]
         done += 1
-        if spent >= budget_s:
-            break
+    passes = done / len(meshes)
     return {"value": cells / spent, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"the first {done} of {len(meshes)} meshes of the batch, whole grids ({cells} band cells, "
-                      f"{spent:.1f} s); FP64 exact distance with bounding-box cull, pseudonormal sign; "
-                      f"one-time edge tables and normals excluded"}
+            "sample": f"{done} whole-grid meshes = {passes:.2f} passes over the {len(meshes)}-mesh batch "
+                      f"({cells} band cells, {spent:.1f} s); FP64 exact distance with bounding-box cull, "
+                      f"pseudonormal sign; one-time edge tables and normals excluded"}
 
 
 def summarize_counters(args):
@@ -307,49 +354,12 @@ def summarize_counters(args):
     print("\n".join(lines))
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch64", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
-    ap.add_argument("--summarize-counters", action="store_true",
-                    help="write profiles/traffic.json from rocprofv3 counter CSVs (see --*-csv)")
-    ap.add_argument("--fetch-csv")
-    ap.add_argument("--write-csv")
-    ap.add_argument("--copy-fetch-csv")
-    ap.add_argument("--copy-write-csv")
-    args = ap.parse_args()
-    if args.summarize_counters:
-        return summarize_counters(args)
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this implementation runs on one GPU; multi-GPU runs are not part of it "
-              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def bench_single(args):
     import torch
-
-    if args.calibrate_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
-                          "launches": 3}))
-        return
 
     import meshgen
     import paper_1903_00353_amd as P
 
-    if args.workload == "batch64":
-        return bench_batch(args)
     cfg, desc = WORKLOADS[args.workload]
     name, meshes, grids = meshgen.make_config(cfg)
     v, f = meshes[0]
@@ -358,7 +368,7 @@ def main():
     verts = torch.from_numpy(v).to(dev)
     tris = torch.from_numpy(f).to(dev)
     from paper_1903_00353_amd import autotune
-    schedule, _ = autotune.tune_single(verts, tris, g)
+    schedule = parse_rows(args.small_rows) if args.small_rows else autotune.tune_single(verts, tris, g)[0]
     opts = P.make_options(small_rows=schedule)
     feats = P.csc_build_features(verts, tris, g, opts)
     info = feats.info()
@@ -379,7 +389,7 @@ def main():
         gv.zero_()
         P.csc_sdf_backward(feats, band, gs, gv, n_band_d=out[3])
 
-    # diagnostics (untimed): atomics per scan kernel, band size and vertex references
+    # untimed diagnostics: atomics per scan launch, band size and vertex references
     atomics = P.csc_scan_convert_count(feats, ws)
     forward()
     torch.cuda.synchronize()
@@ -391,32 +401,11 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    P.csc_timing_reset()
-    P.csc_timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    P.csc_timing_enable(False)
-    stages = P.csc_timing_read()
-    # forward-only throughput (untimed by events)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        forward()
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    ms_fwd = (t3 - t2) * 1e3 / args.steps
-    avg = {k: (ms / c if c else 0.0) for k, (ms, c) in stages.items()}
+    ms_step, med_step, min_step = timed_steps(step, args.steps)
+    avg, _ = stage_averages(step, args.steps)
     dom = max(SINGLE_KERNEL_STAGES, key=lambda k: avg[k])
     alg = algorithmic_bytes(dom, info, atomics, M, vert_refs, verts.shape[0])
     achieved = alg / (avg[dom] * 1e-3) / 1e9
-    traffic = load_traffic(args.workload, dom)
     res = {
         "metric": METRIC,
         "value": M / (ms_step * 1e-3),
@@ -433,9 +422,9 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "faces": F, "vertices": int(verts.shape[0]),
                    "grid": list(g.n), "band_cells": g.band, "band_size": M, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic(args.workload, dom),
                      "algorithmic_bytes": alg, "avg_ms": avg[dom]},
-        "fwd": {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd},
+        "step_ms": {"median": med_step, "min": min_step},
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
         "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
                     "edges_big": atomics[4], "vertices_big": atomics[5]},
@@ -443,9 +432,82 @@ def main():
         "features": info,
         "kernel_source_sha": kernel_source_sha(),
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(v, f, g, args.cpu_budget)
+    if not args.timed_only:
+        ms_fwd, med_fwd, min_fwd = timed_steps(forward, args.steps)
+        res["fwd"] = {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd, "median": med_fwd, "min": min_fwd}
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = cpu_baseline(v, f, g, args.cpu_budget)
     print(json.dumps(res))
+
+
+def summarize_trace(args):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv (top kernels)."""
+    import csv
+    rows = list(csv.DictReader(open(args.trace_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# Kernel time, workload {args.workload}", "",
+             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:args.top]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        if name.startswith("at::native::"):
+            name = "torch " + name.split("<")[0].split("::")[-1] + " (2*SDF, zero fill)"
+        if "rocprim" in name:
+            name = "rocprim radix sort (" + name.split("::")[-1][:40] + ")"
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / tot * 100:.1f} |")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--small-rows", help="fixed schedule faces,edges,vertices instead of the autotuned one")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="only the timed fwd+bwd steps (for profiling: no forward-only, per-mesh or CPU legs)")
+    ap.add_argument("--no-graph", action="store_true", help="batch64: time eager steps instead of graph replays")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--summarize-counters", action="store_true",
+                    help="write profiles/traffic.json from rocprofv3 counter CSVs (see --*-csv)")
+    ap.add_argument("--summarize-trace", action="store_true",
+                    help="print a markdown summary of a rocprofv3 kernel_stats.csv (--trace-csv)")
+    ap.add_argument("--trace-csv")
+    ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--fetch-csv")
+    ap.add_argument("--write-csv")
+    ap.add_argument("--copy-fetch-csv")
+    ap.add_argument("--copy-write-csv")
+    args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(args)
+    if args.summarize_trace:
+        return summarize_trace(args)
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this implementation runs on one GPU; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
+                          "launches": 3}))
+        return
+    if args.workload == "batch64":
+        return bench_batch(args)
+    return bench_single(args)
 
 
 if __name__ == "__main__":

@@ -38,6 +38,8 @@ constexpr int BW_SLOTS = 1024;  // > 3 * BW_THREADS insertions: probing always e
 __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
   __shared__ int s_key[BW_SLOTS];
   __shared__ float s_acc[3][BW_SLOTS];
+  __shared__ int s_list[BW_SLOTS];
+  __shared__ int s_n;
   for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
     s_key[k] = -1;
     s_acc[0][k] = 0.f;
@@ -101,14 +103,25 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
       }
     }
   }
+  // gather the occupied slots, then let consecutive lanes add the three
+  // components of one vertex, so one wave instruction covers about 21 vertices
+  // in 12-byte runs instead of 64 scattered addresses
+  if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
-    const int v = s_key[k];
-    if (v < 0) continue;
-    float* dst = P.grad + 3 * (int64_t)v;
-    atomicAdd(dst, s_acc[0][k]);
-    atomicAdd(dst + 1, s_acc[1][k]);
-    atomicAdd(dst + 2, s_acc[2][k]);
+    const bool occ = s_key[k] >= 0;
+    const unsigned long long m = __ballot(occ);
+    const int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&s_n, __popcll(m));
+    base = __shfl(base, leader < 0 ? 0 : leader, 64);
+    if (occ) s_list[base + __popcll(m & ((1ull << lane) - 1))] = k;
+  }
+  __syncthreads();
+  const int n3 = 3 * s_n;
+  for (int k = threadIdx.x; k < n3; k += BW_THREADS) {
+    const int slot = s_list[k / 3], c = k - 3 * (k / 3);
+    atomicAdd(P.grad + 3 * (int64_t)s_key[slot] + c, s_acc[c][slot]);
   }
 }
 

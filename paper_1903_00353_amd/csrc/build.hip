@@ -237,13 +237,14 @@ __global__ void k_edges(const int32_t* __restrict__ T, int64_t nh, int64_t ne, c
 }
 
 // Unit face normal (double precision, stored in single) and the band bricks near
-// the face: every brick within band*h (+ one cell) of its bounding box. A face
-// whose dilated box stays within the 3x3x3 bricks around the brick of its
-// centroid only seeds that brick (k_dilate_bricks covers the rest); larger ones
-// mark every brick of their box directly.
+// the face: every brick holding a cell centre within band*h + eps of the face's
+// bounding box. Every polyhedron of the face, its edges and its vertices lies in
+// that box (the face prism within band*h*|n_k| + eps of the face along each
+// axis, edge wedges and vertex cones within band*h + eps of their feature), so
+// every cell a scan can write has its brick marked.
 __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf,
                             const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float4* fn,
-                            uint8_t* seed, int32_t* flag, int64_t* stats) {
+                            int32_t* flag, int64_t* stats) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
   const d3 a = vload_d(V, T[3 * f]), b = vload_d(V, T[3 * f + 1]), c = vload_d(V, T[3 * f + 2]);
@@ -256,33 +257,26 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
     fn[f] = make_float4((float)(n.x / l), (float)(n.y / l), (float)(n.z / l), 0.f);
   }
   const MeshDesc& g = md[face_mesh[f]];
-  const double r = g.whd + g.h;
+  const double r = g.whd + g.epsd;
   const double X[3][3] = {{a.x, b.x, c.x}, {a.y, b.y, c.y}, {a.z, b.z, c.z}};
-  int lo[3], hi[3], cb[3];
-  bool small = true;
+  int lo[3], hi[3];
   for (int ax = 0; ax < 3; ax++) {
     const double x0 = X[ax][0], x1 = X[ax][1], x2 = X[ax][2];
     const double mn = fmin(x0, fmin(x1, x2)) - r, mx = fmax(x0, fmax(x1, x2)) + r;
-    double lo_c = floor((mn - g.origin[ax]) * g.inv_h - 0.5), hi_c = ceil((mx - g.origin[ax]) * g.inv_h - 0.5);
+    // cells whose centre lies in [mn, mx], widened by 1e-3 cells against rounding
+    // (the scan's own boxes are widened by 1e-4 cells)
+    double lo_c = ceil((mn - g.origin[ax]) * g.inv_h - 0.5 - 1e-3);
+    double hi_c = floor((mx - g.origin[ax]) * g.inv_h - 0.5 + 1e-3);
     lo_c = fmax(lo_c, 0.0);
     hi_c = fmin(hi_c, (double)(g.n[ax] - 1));
     if (!(lo_c <= hi_c)) return;
     lo[ax] = (int)lo_c / BRICK;
     hi[ax] = (int)hi_c / BRICK;
-    const double cc = floor(floor(((x0 + x1 + x2) / 3.0 - g.origin[ax]) * g.inv_h) / BRICK);  // centroid's brick
-    cb[ax] = (int)fmax(-2.0, fmin(cc, (double)g.nb[ax] + 1));
-    small = small && cb[ax] >= 0 && cb[ax] < g.nb[ax] && lo[ax] >= cb[ax] - 1 && hi[ax] <= cb[ax] + 1;
-  }
-  const int64_t base = g.brick_base, sx = g.nb[0], sxy = (int64_t)g.nb[0] * g.nb[1];
-  if (small) {
-    uint8_t* p = &seed[base + cb[0] + sx * cb[1] + sxy * cb[2]];
-    if (*p == 0) *p = 1;
-    return;
   }
   for (int z = lo[2]; z <= hi[2]; z++)
     for (int y = lo[1]; y <= hi[1]; y++)
       for (int x = lo[0]; x <= hi[0]; x++) {
-        int32_t* p = &flag[base + x + sx * y + sxy * z];
+        int32_t* p = &flag[brick_pos(g, x, y, z)];
         if (*p == 0) *p = 1;
       }
 }
@@ -363,35 +357,6 @@ __global__ void k_vertex_queue(const uint32_t* __restrict__ vbits, int64_t nv, c
   int32_t p = off[v];
   if (b & V_POS) q[p++] = (int32_t)(v << 1);
   if (b & V_NEG) q[p++] = (int32_t)((v << 1) | 1);
-}
-
-// flag every brick with a seed among its 27 neighbours in its own mesh's grid
-__global__ void k_dilate_bricks(const uint8_t* __restrict__ seed, int64_t nbt, const int32_t* __restrict__ brick_base,
-                                const MeshDesc* __restrict__ md, int n_meshes, int32_t* flag) {
-  int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= nbt) return;
-  if (flag[b]) return;
-  const int m = find_segment(brick_base, n_meshes + 1, b);
-  const MeshDesc& g = md[m];
-  const int64_t loc = b - g.brick_base;
-  const int nbx = g.nb[0], nby = g.nb[1], nbz = g.nb[2];
-  const int x = (int)(loc % nbx), y = (int)((loc / nbx) % nby), z = (int)(loc / ((int64_t)nbx * nby));
-  for (int dz = -1; dz <= 1; dz++) {
-    int zz = z + dz;
-    if (zz < 0 || zz >= nbz) continue;
-    for (int dy = -1; dy <= 1; dy++) {
-      int yy = y + dy;
-      if (yy < 0 || yy >= nby) continue;
-      for (int dx = -1; dx <= 1; dx++) {
-        int xx = x + dx;
-        if (xx < 0 || xx >= nbx) continue;
-        if (seed[g.brick_base + xx + (int64_t)nbx * (yy + (int64_t)nby * zz)]) {
-          flag[b] = 1;
-          return;
-        }
-      }
-    }
-  }
 }
 
 // slots of the flagged bricks (index = exclusive prefix of the flags), their
@@ -525,6 +490,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
       d.origin[a] = g.origin[a];
       d.n[a] = g.n[a];
       d.nb[a] = (g.n[a] + BRICK - 1) / BRICK;
+      d.nt[a] = (d.nb[a] + TILE - 1) / TILE;
     }
     d.h = g.h;
     d.inv_h = 1.0 / g.h;
@@ -541,7 +507,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
     d.nv = (int32_t)nv[m];
     d.nf = (int32_t)nf[m];
     d.ne = (int32_t)(3 * nf[m] / 2);
-    tb += (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
+    tb += (int64_t)d.nt[0] * d.nt[1] * d.nt[2] * (TILE * TILE * TILE);
     tv += nv[m];
     tf += nf[m];
     te += 3 * nf[m] / 2;
@@ -692,16 +658,12 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   k_edges<<<grid_1d(nh, B), B, 0, s>>>(T, nh, ne, F->t_a, F->t_b, F->edges, F->face_edges);
   // 4. face normals with the band bricks near each face; edge classes
   k_fill_i32<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, tb, 0);
-  k_fill_i32<<<grid_1d((tb + 3) / 4, B), B, 0, s>>>(F->t_a, (tb + 3) / 4, 0);
-  k_face_geom<<<grid_1d(tf, B), B, 0, s>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, (uint8_t*)F->t_a,
-                                            F->t_b, F->d_stats);
+  k_face_geom<<<grid_1d(tf, B), B, 0, s>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, F->t_b, F->d_stats);
   k_edge_class<<<grid_1d(ne, B), B, 0, s>>>(verts_d, T, F->edges, ne, o.force_both_sides, F->edge_cls, F->t_c);
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
   k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, tv, F->d_stats);
   // 5. band bricks
-  k_dilate_bricks<<<grid_1d(tb, B), B, 0, s>>>((const uint8_t*)F->t_a, tb, F->brick_base, F->d_mesh, n_meshes,
-                                               F->t_b);
   CK(exclusive_scan(F->t_b, F->brick_index, tb, F->t_scan, &F->d_stats[ST_NBRICKS], nullptr, s));
   k_brick_fix<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, F->brick_index, F->brick_list, F->brick_mesh, F->brick_base,
                                            n_meshes, F->first_slot, F->d_stats, tb);

@@ -33,12 +33,31 @@ struct MeshDesc {
   double h, inv_h, whd, epsd;
   float hf, whf, eps, band;
   int32_t n[3];
-  int32_t nb[3];
-  int32_t brick_base;           // first brick of this mesh in the batch's brick space
+  int32_t nb[3];                // bricks per axis
+  int32_t nt[3];                // tiles of 4x4x4 bricks per axis
+  int32_t brick_base;           // first brick position of this mesh in the batch's brick space
   int32_t v_off, f_off, e_off;  // first vertex / face / edge of this mesh
   int32_t nv, nf, ne;
-  int32_t pad;
 };
+
+// Position of brick (bx, by, bz) in the batch's brick space: bricks are numbered
+// tile by tile (tiles of 4x4x4 bricks, x fastest), and linearly inside a tile, so
+// that consecutive brick slots (and the band list that follows their order) stay
+// spatially compact.
+constexpr int TILE = 4;
+__host__ __device__ inline int64_t brick_pos(const MeshDesc& G, int bx, int by, int bz) {
+  const int64_t tile = (bx >> 2) + (int64_t)G.nt[0] * ((by >> 2) + (int64_t)G.nt[1] * (bz >> 2));
+  return G.brick_base + (tile << 6) + (bx & 3) + ((by & 3) << 2) + ((bz & 3) << 4);
+}
+__host__ __device__ inline void brick_coords(const MeshDesc& G, int64_t pos, int& bx, int& by, int& bz) {
+  const int64_t p = pos - G.brick_base, tile = p >> 6;
+  const int l = (int)(p & 63);
+  const int tx = (int)(tile % G.nt[0]), ty = (int)((tile / G.nt[0]) % G.nt[1]);
+  const int tz = (int)(tile / ((int64_t)G.nt[0] * G.nt[1]));
+  bx = tx * 4 + (l & 3);
+  by = ty * 4 + ((l >> 2) & 3);
+  bz = tz * 4 + (l >> 4);
+}
 
 // Exclusive prefix sum of in[0..n) into out (may alias in). If total_i64 is not
 // null the sum is stored there; if total_i32 is not null, also there. tmp must

@@ -339,10 +339,17 @@ __device__ inline bool row_range(const Rows& r, int du, int dv, float hf, int& t
   return t0 <= t1;
 }
 
+// the brick slot of the last brick looked up (consecutive candidates of a
+// polyhedron mostly share a brick)
+struct BrickCache {
+  int64_t bl = -1;
+  int32_t slot = -1;
+};
+
 // exact distance at the candidate cells of one row, and the packed atomic minimum
 template <int KIND>
 __device__ inline unsigned scan_row(const ScanArgs& P, const MeshDesc& G, const Poly& q, const Rows& r, int du,
-                                    int dv) {
+                                    int dv, BrickCache& bc) {
   int t0, t1;
   if (!row_range<KIND>(r, du, dv, G.hf, t0, t1)) return 0;
   unsigned issued = 0;
@@ -385,8 +392,12 @@ __device__ inline unsigned scan_row(const ScanArgs& P, const MeshDesc& G, const 
     }
     if (d < G.whf) {
       const int i = q.anc.x + di, j = q.anc.y + dj, k = q.anc.z + dk;
-      const int64_t bl = (int64_t)G.brick_base + (i >> 3) + (int64_t)G.nb[0] * ((j >> 3) + (int64_t)G.nb[1] * (k >> 3));
-      const int32_t slot = P.brick_index[bl];
+      const int64_t bl = brick_pos(G, i >> 3, j >> 3, k >> 3);
+      if (bl != bc.bl) {
+        bc.bl = bl;
+        bc.slot = P.brick_index[bl];
+      }
+      const int32_t slot = bc.slot;
       if (slot >= 0 && slot < P.cap) {
         const unsigned long long key =
             ((unsigned long long)__float_as_uint(d) << 32) | (code << 30) | (uint32_t)q.id;
@@ -434,8 +445,9 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
     const MeshDesc& G = P.md[q.mesh];
     Rows r;
     setup_rows<KIND>(q, G, r);
+    BrickCache bc;
     for (int dv = 0; dv < q.nv; dv++)
-      for (int du = 0; du < q.nu; du++) issued += scan_row<KIND>(P, G, q, r, du, dv);
+      for (int du = 0; du < q.nu; du++) issued += scan_row<KIND>(P, G, q, r, du, dv, bc);
   }
   add_issued(P, issued, 0);
 }
@@ -454,9 +466,10 @@ __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
     Rows r;
     setup_rows<KIND>(q, G, r);
     const int nu = q.nu, rows = nu * q.nv;
+    BrickCache bc;
     for (int row = lane; row < rows; row += 64) {
       const int dv = row / nu, du = row - dv * nu;
-      issued += scan_row<KIND>(P, G, q, r, du, dv);
+      issued += scan_row<KIND>(P, G, q, r, du, dv, bc);
     }
   }
   add_issued(P, issued, 3);
@@ -483,23 +496,24 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
     p[i] = v;
 }
 
-// number of set keys per brick slot (0 for slots past the allocated bricks)
-__global__ __launch_bounds__(512) void k_brick_count(const unsigned long long* __restrict__ keys,
+// number of set keys per brick slot (0 for slots past the allocated bricks): one
+// wavefront per brick, every lane loading its 8 keys at once (lane + 64 r)
+__global__ __launch_bounds__(256) void k_brick_count(const unsigned long long* __restrict__ keys,
                                                      const int64_t* __restrict__ stats, int64_t cap, int32_t* cnt) {
-  __shared__ int ws[8];
+  const int lane = threadIdx.x & 63;
   const int64_t nb = stats[ST_NBRICKS] < cap ? stats[ST_NBRICKS] : cap;
-  for (int64_t s = blockIdx.x; s < cap; s += gridDim.x) {
-    const bool live = s < nb;
-    const unsigned long long k = live ? keys[s * BRICK_CELLS + threadIdx.x] : EMPTY_KEY;
-    const unsigned long long m = __ballot(k != EMPTY_KEY);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = __popcll(m);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int t = 0;
-      for (int w = 0; w < 8; w++) t += ws[w];
-      cnt[s] = t;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t s = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); s < cap; s += nw) {
+    int c = 0;
+    if (s < nb) {
+      const unsigned long long* kp = keys + s * BRICK_CELLS + lane;
+      unsigned long long k[8];
+#pragma unroll
+      for (int r = 0; r < 8; r++) k[r] = kp[64 * r];
+#pragma unroll
+      for (int r = 0; r < 8; r++) c += __popcll(__ballot(k[r] != EMPTY_KEY));
     }
-    __syncthreads();
+    if (lane == 0) cnt[s] = c;
   }
 }
 
@@ -536,72 +550,106 @@ struct SignArgs {
 __device__ inline f3 rel(const float* V, int64_t i, d3 c) { return tof(vload_d(V, i) - c); }
 __device__ inline f3 xyz(float4 a) { return mk(a.x, a.y, a.z); }
 
-// Sign of a band cell from the pseudonormal of the lowest-dimensional feature
-// holding its closest point (face normal; edge: sum of the two face normals;
-// vertex: angle-weighted pseudonormal), Section 4.1.3 and Eq. 8. Writes the band
-// list with each mesh's own feature ids and cell indices.
-__global__ __launch_bounds__(512) void k_sign(SignArgs P) {
-  __shared__ int ws[8];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+// mesh-local feature id of a global one
+__device__ inline int32_t local_id(const SignArgs& P, const MeshDesc& G, int32_t id) {
+  return id < P.nf ? id - G.f_off
+                   : (id < P.nf + P.ne ? G.nf + (int32_t)(id - P.nf - G.e_off)
+                                       : G.nf + G.ne + (int32_t)(id - P.nf - P.ne - G.v_off));
+}
+
+__device__ inline void put_cell(const SignArgs& P, const MeshDesc& G, int64_t out, float sd, int32_t local, int i,
+                                int j, int k) {
+  const int32_t lin = i + G.n[0] * (j + G.n[1] * k);
+  P.sdf[out] = sd;
+  P.feat[out] = local;
+  P.cell[out] = lin;
+  if (P.dense) P.dense[lin] = sd;
+}
+
+// a cell whose winning face candidate had its closest point on the face boundary:
+// recompute the closest point and take the pseudonormal of the feature holding it
+__device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned long long key, int i, int j,
+                                       int k, int64_t out) {
+  const float d = __uint_as_float((uint32_t)(key >> 32));
+  const int32_t id = (int32_t)((uint32_t)key & ID_MASK);
+  const d3 c = mkd(G.origin[0] + (i + 0.5) * G.h, G.origin[1] + (j + 0.5) * G.h, G.origin[2] + (k + 0.5) * G.h);
+  f3 qq = mk(0.f, 0.f, 0.f), N = mk(0.f, 0.f, 0.f);
+  if (id < P.nf) {
+    const int64_t f = id;
+    float wt[3];
+    int r = closest_triangle(mk(0.f, 0.f, 0.f), rel(P.V, P.T[3 * f], c), rel(P.V, P.T[3 * f + 1], c),
+                             rel(P.V, P.T[3 * f + 2], c), qq, wt);
+    if (r == 0) N = xyz(P.fn[f]);
+    else if (r <= 3) {
+      int4 E = P.edges[P.face_edges[3 * f + r - 1]];
+      N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
+    } else N = xyz(P.vinfo[P.T[3 * f + r - 4]]);
+  } else if (id < P.nf + P.ne) {
+    int4 E = P.edges[id - P.nf];
+    float tt;
+    qq = closest_segment(mk(0.f, 0.f, 0.f), rel(P.V, E.x, c), rel(P.V, E.y, c), tt);
+    if (tt <= 0.f) N = xyz(P.vinfo[E.x]);
+    else if (tt >= 1.f) N = xyz(P.vinfo[E.y]);
+    else N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
+  } else {
+    const int64_t v = id - P.nf - P.ne;
+    qq = rel(P.V, v, c);
+    N = xyz(P.vinfo[v]);
+  }
+  const float s = dot(mk(-qq.x, -qq.y, -qq.z), N) >= 0.f ? 1.f : -1.f;
+  put_cell(P, G, out, s * d, local_id(P, G, id), i, j, k);
+}
+
+// Sign of every band cell (Section 4.1.3, Eq. 8) and the compact band list with
+// each mesh's own feature ids and cell indices. One wavefront per brick: lane l
+// holds cells l + 64 r (x = l & 7, y = l >> 3, z = r) for r = 0..7, loaded at
+// once; the output position is the brick's offset plus the rank among the set
+// cells in (r, lane) order. Most keys carry their sign from the scan; the rest
+// (SIGN_OPEN) are finished after the brick's decided cells.
+__global__ __launch_bounds__(256) void k_sign(SignArgs P) {
+  const int lane = threadIdx.x & 63;
   const int64_t nb = P.stats[ST_NBRICKS] < P.cap ? P.stats[ST_NBRICKS] : P.cap;
-  for (int64_t slot = blockIdx.x; slot < nb; slot += gridDim.x) {
-    const unsigned long long key = P.keys[slot * BRICK_CELLS + t];
-    const bool valid = key != EMPTY_KEY;
-    const unsigned long long m = __ballot(valid);
-    if (lane == 0) ws[w] = __popcll(m);
-    __syncthreads();
-    int before = 0;
-    for (int i = 0; i < w; i++) before += ws[i];
-    __syncthreads();
-    if (!valid) continue;
-    const int64_t out = P.boff[slot] + before + lanes_below(m);
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t slot = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); slot < nb; slot += nw) {
+    const unsigned long long* kp = P.keys + slot * BRICK_CELLS + lane;
+    unsigned long long key[8];
+#pragma unroll
+    for (int r = 0; r < 8; r++) key[r] = kp[64 * r];
     const MeshDesc& G = P.md[P.brick_mesh[slot]];
-    const int32_t b = P.brick_list[slot] - G.brick_base;
-    const int bx = b % G.nb[0], by = (b / G.nb[0]) % G.nb[1], bz = b / (G.nb[0] * G.nb[1]);
-    const int i = bx * 8 + (t & 7), j = by * 8 + ((t >> 3) & 7), k = bz * 8 + (t >> 6);
-    const float d = __uint_as_float((uint32_t)(key >> 32));
-    const uint32_t code = ((uint32_t)key) >> 30;
-    const int32_t id = (int32_t)((uint32_t)key & ID_MASK);
-    const d3 c = mkd(G.origin[0] + (i + 0.5) * G.h, G.origin[1] + (j + 0.5) * G.h, G.origin[2] + (k + 0.5) * G.h);
-    f3 qq = mk(0.f, 0.f, 0.f), N = mk(0.f, 0.f, 0.f);
-    int32_t local;
-    if (code != SIGN_OPEN) {  // decided by the winning polyhedron
-      local = id < P.nf ? id - G.f_off
-                        : (id < P.nf + P.ne ? G.nf + (int32_t)(id - P.nf - G.e_off)
-                                            : G.nf + G.ne + (int32_t)(id - P.nf - P.ne - G.v_off));
-    } else if (id < P.nf) {
-      const int64_t f = id;
-      float wt[3];
-      int r = closest_triangle(mk(0.f, 0.f, 0.f), rel(P.V, P.T[3 * f], c), rel(P.V, P.T[3 * f + 1], c),
-                               rel(P.V, P.T[3 * f + 2], c), qq, wt);
-      if (r == 0) N = xyz(P.fn[f]);
-      else if (r <= 3) {
-        int4 E = P.edges[P.face_edges[3 * f + r - 1]];
-        N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
-      } else N = xyz(P.vinfo[P.T[3 * f + r - 4]]);
-      local = id - G.f_off;
-    } else if (id < P.nf + P.ne) {
-      const int64_t e = id - P.nf;
-      int4 E = P.edges[e];
-      float tt;
-      qq = closest_segment(mk(0.f, 0.f, 0.f), rel(P.V, E.x, c), rel(P.V, E.y, c), tt);
-      if (tt <= 0.f) N = xyz(P.vinfo[E.x]);
-      else if (tt >= 1.f) N = xyz(P.vinfo[E.y]);
-      else N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
-      local = G.nf + (int32_t)(e - G.e_off);
-    } else {
-      const int64_t v = id - P.nf - P.ne;
-      qq = rel(P.V, v, c);
-      N = xyz(P.vinfo[v]);
-      local = G.nf + G.ne + (int32_t)(v - G.v_off);
+    int bx, by, bz;
+    brick_coords(G, P.brick_list[slot], bx, by, bz);
+    const int i = bx * 8 + (lane & 7), j = by * 8 + (lane >> 3);
+    const int64_t ob = P.boff[slot];
+    int before = 0;
+    unsigned open_bits = 0;
+    unsigned long long open_pos = 0;  // 9-bit in-brick positions of open cells r = 0..6
+    uint32_t open_pos7 = 0;
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+      const bool valid = key[r] != EMPTY_KEY;
+      const unsigned long long msk = __ballot(valid);
+      if (valid) {
+        const uint32_t pos = (uint32_t)(before + lanes_below(msk));
+        const uint32_t lo = (uint32_t)key[r];
+        const uint32_t code = lo >> 30;
+        if (code == SIGN_OPEN) {
+          open_bits |= 1u << r;
+          if (r < 7) open_pos |= (unsigned long long)pos << (9 * r);
+          else open_pos7 = pos;
+        } else {
+          const float d = __uint_as_float((uint32_t)(key[r] >> 32));
+          put_cell(P, G, ob + pos, code == SIGN_NEG ? -d : d, local_id(P, G, (int32_t)(lo & ID_MASK)), i, j,
+                   bz * 8 + r);
+        }
+      }
+      before += __popcll(msk);
     }
-    const float s = code == SIGN_POS ? 1.f
-                  : (code == SIGN_NEG ? -1.f : (dot(mk(-qq.x, -qq.y, -qq.z), N) >= 0.f ? 1.f : -1.f));
-    const int32_t lin = i + G.n[0] * (j + G.n[1] * k);
-    P.sdf[out] = s * d;
-    P.feat[out] = local;
-    P.cell[out] = lin;
-    if (P.dense) P.dense[lin] = s * d;
+    while (open_bits) {
+      const int r = __ffs(open_bits) - 1;
+      open_bits &= open_bits - 1;
+      const uint32_t pos = r < 7 ? (uint32_t)(open_pos >> (9 * r)) & 511u : open_pos7;
+      sign_open(P, G, kp[64 * r], i, j, bz * 8 + r, ob + pos);
+    }
   }
 }
 
@@ -735,7 +783,7 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
   hipError_t e;
   {
     StageTimer t(TS_COUNT, s);
-    if (cap > 0) k_brick_count<<<PERSIST_BLOCKS, 512, 0, s>>>(keys, f->d_stats, cap, cnt);
+    if (cap > 0) k_brick_count<<<PERSIST_BLOCKS, 256, 0, s>>>(keys, f->d_stats, cap, cnt);
     e = exclusive_scan(cnt, cnt, cap, tmp, n_band_d, cnt + cap, s);
     k_band_offsets<<<1, 64, 0, s>>>(f->first_slot, cnt, f->n_meshes, cap, boff64);
   }
@@ -762,7 +810,7 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
     S.cap = cap;
     S.nf = f->nf;
     S.ne = f->ne;
-    k_sign<<<PERSIST_BLOCKS, 512, 0, s>>>(S);
+    k_sign<<<PERSIST_BLOCKS, 256, 0, s>>>(S);
   }
   e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);

@@ -72,3 +72,16 @@ def assert_parity(rep, exact_membership=False):
     assert rep["feat_bad"] == 0, msg
     if exact_membership:
         assert rep["exempt"] == 0 and rep["n_device"] == rep["n_oracle"], msg
+
+
+def assert_same_sums(a, b, msg=""):
+    """a and b accumulate the same FP32 terms in a different order (float atomics
+    land in whatever order the hardware executes them). The difference of two
+    such sums is bounded by a few hundred ulps of the largest term magnitude for
+    the term counts here; one missing or doubled band-cell contribution is at
+    least 1e-3 of the largest entry. Per coordinate: |a - b| <= 1e-5 max|a|."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = max(np.abs(a).max(initial=0.0), np.abs(b).max(initial=0.0))
+    err = np.abs(a - b).max(initial=0.0)
+    assert err <= 1e-5 * scale, (msg, err, scale)

@@ -47,7 +47,8 @@ enum csc_status {
   CSC_NONMANIFOLD = 2,             /* an edge is not shared by exactly two triangles (open surface) */
   CSC_INCONSISTENT_ORIENTATION = 3,/* a directed edge occurs twice (flipped or duplicated triangle) */
   CSC_DEGENERATE_FACE = 4,         /* a triangle of zero area */
-  CSC_GRID_TOO_LARGE = 5,          /* more than 2^31 - 1 cells, or more than 2^24 bricks */
+  CSC_GRID_TOO_LARGE = 5,          /* over 2^31 - 1 cells, over 65535 cells on an axis, or over
+                                      2^26 brick positions in a batch */
   CSC_OUT_OF_MEMORY = 6,
   CSC_HIP_ERROR = 7,               /* a HIP runtime call failed (see csc_last_hip_error) */
   CSC_WORKSPACE_TOO_SMALL = 8,

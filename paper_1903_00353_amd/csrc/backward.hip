@@ -30,98 +30,118 @@ __device__ inline f3 relb(const float* V, int64_t i, d3 c) {
 }
 
 constexpr int BW_THREADS = 256;
-constexpr int BW_SLOTS = 1024;  // > 3 * BW_THREADS insertions: probing always ends
+constexpr int BW_SLOTS = 2048;                // hash table of (vertex, 3 partial sums) per block
+constexpr int BW_HASH_SHIFT = 21;             // 32 - log2(BW_SLOTS)
+constexpr int BW_FLUSH = BW_SLOTS - 3 * BW_THREADS;  // flush before a chunk could overfill it
+constexpr int BW_BLOCKS = 1024;               // persistent grid: 4 resident blocks of 256 per CU
 
-// One band cell per thread. Each block first sums its cells' contributions per
-// vertex in an LDS hash table (band cells are ordered by brick, so a block's cells
-// share many of their vertices), then adds one value per vertex and axis globally.
+// Each block takes one contiguous run of band cells (band cells follow the
+// tile-ordered bricks, so a run covers a compact piece of surface and shares most
+// of its vertices) in chunks of one cell per thread. Contributions are summed per
+// vertex in an LDS hash table that is added to the global gradient only when
+// another chunk could overfill it, and at the end: one global add per vertex,
+// axis and flush instead of one per band cell.
 __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
   __shared__ int s_key[BW_SLOTS];
   __shared__ float s_acc[3][BW_SLOTS];
-  __shared__ int s_list[BW_SLOTS];
-  __shared__ int s_n;
-  for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
-    s_key[k] = -1;
-    s_acc[0][k] = 0.f;
-    s_acc[1][k] = 0.f;
-    s_acc[2][k] = 0.f;
-  }
-  __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)BW_THREADS + threadIdx.x;
+  __shared__ int s_used;
   int64_t lim = P.n;
   if (P.band_off) lim = P.band_off[P.n_meshes] < lim ? P.band_off[P.n_meshes] : lim;
   else if (P.n_dev && *P.n_dev < lim) lim = *P.n_dev;
-  const float gs = i < lim ? P.gsdf[i] : 0.f;
-  if (gs != 0.f) {
-    const int m = P.band_off ? find_segment(P.band_off, P.n_meshes + 1, i) : 0;
-    const MeshDesc& G = P.md[m];
-    const int32_t lin = P.cell[i], lf = P.feat[i];
-    const int ci = lin % G.n[0], cj = (lin / G.n[0]) % G.n[1], ck = lin / (G.n[0] * G.n[1]);
-    const d3 c = mkd(G.origin[0] + (ci + 0.5) * G.h, G.origin[1] + (cj + 0.5) * G.h, G.origin[2] + (ck + 0.5) * G.h);
-    const f3 zero = mk(0.f, 0.f, 0.f);
-    f3 q;
-    float w[3] = {0.f, 0.f, 0.f};
-    int32_t vid[3] = {0, 0, 0};
-    int mcount;
-    if (lf < G.nf) {
-      const int64_t f = (int64_t)G.f_off + lf;
-      for (int j = 0; j < 3; j++) vid[j] = P.T[3 * f + j];
-      closest_triangle(zero, relb(P.V, vid[0], c), relb(P.V, vid[1], c), relb(P.V, vid[2], c), q, w);
-      mcount = 3;
-    } else if (lf < G.nf + G.ne) {
-      int4 E = P.edges[(int64_t)G.e_off + (lf - G.nf)];
-      vid[0] = E.x;
-      vid[1] = E.y;
-      float t;
-      q = closest_segment(zero, relb(P.V, E.x, c), relb(P.V, E.y, c), t);
-      w[0] = 1.f - t;
-      w[1] = t;
-      mcount = 2;
-    } else {
-      vid[0] = G.v_off + (lf - G.nf - G.ne);
-      q = relb(P.V, vid[0], c);
-      w[0] = 1.f;
-      mcount = 1;
-    }
-    const float d = norm3(q);
-    if (d > 0.f) {
-      const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
-      // c - q = -q in this frame; g = s (c - q) / |c - q|
-      const f3 g = q * (-s / d);
-      for (int k = 0; k < mcount; k++) {
-        const float f = -gs * w[k];
-        if (f == 0.f) continue;
-        unsigned h = ((unsigned)vid[k] * 2654435761u) >> 22;
-        while (true) {
-          int old = atomicCAS(&s_key[h], -1, vid[k]);
-          if (old == -1 || old == vid[k]) break;
-          h = (h + 1) & (BW_SLOTS - 1);
+  // this block's run [c0, c1), a whole number of chunks
+  const int64_t chunks = (lim + BW_THREADS - 1) / BW_THREADS;
+  const int64_t per = (chunks + gridDim.x - 1) / gridDim.x;
+  const int64_t c0 = blockIdx.x * per * BW_THREADS;
+  const int64_t c1 = min(lim, c0 + per * BW_THREADS);
+  if (c0 >= c1) return;  // block-uniform
+  for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
+    s_key[k] = -1;
+    s_acc[0][k] = s_acc[1][k] = s_acc[2][k] = 0.f;
+  }
+  if (threadIdx.x == 0) s_used = 0;
+  __syncthreads();
+  int m = P.band_off ? find_segment(P.band_off, P.n_meshes + 1, c0 + threadIdx.x) : 0;
+  for (int64_t base = c0; base < c1; base += BW_THREADS) {
+    const int64_t i = base + threadIdx.x;
+    const float gs = i < c1 ? P.gsdf[i] : 0.f;
+    if (gs != 0.f) {
+      if (P.band_off) {
+        while (i >= P.band_off[m + 1]) m++;  // cells only move forward through the meshes
+      }
+      const MeshDesc& G = P.md[m];
+      const int32_t lin = P.cell[i], lf = P.feat[i];
+      const int ci = lin % G.n[0], cj = (lin / G.n[0]) % G.n[1], ck = lin / (G.n[0] * G.n[1]);
+      const d3 c = mkd(G.origin[0] + (ci + 0.5) * G.h, G.origin[1] + (cj + 0.5) * G.h, G.origin[2] + (ck + 0.5) * G.h);
+      const f3 zero = mk(0.f, 0.f, 0.f);
+      f3 q;
+      float w[3] = {0.f, 0.f, 0.f};
+      int32_t vid[3] = {0, 0, 0};
+      int mcount;
+      if (lf < G.nf) {
+        const int64_t f = (int64_t)G.f_off + lf;
+        for (int j = 0; j < 3; j++) vid[j] = P.T[3 * f + j];
+        closest_triangle(zero, relb(P.V, vid[0], c), relb(P.V, vid[1], c), relb(P.V, vid[2], c), q, w);
+        mcount = 3;
+      } else if (lf < G.nf + G.ne) {
+        int4 E = P.edges[(int64_t)G.e_off + (lf - G.nf)];
+        vid[0] = E.x;
+        vid[1] = E.y;
+        float t;
+        q = closest_segment(zero, relb(P.V, E.x, c), relb(P.V, E.y, c), t);
+        w[0] = 1.f - t;
+        w[1] = t;
+        mcount = 2;
+      } else {
+        vid[0] = G.v_off + (lf - G.nf - G.ne);
+        q = relb(P.V, vid[0], c);
+        w[0] = 1.f;
+        mcount = 1;
+      }
+      const float d = norm3(q);
+      if (d > 0.f) {
+        const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
+        // c - q = -q in this frame; g = s (c - q) / |c - q|
+        const f3 g = q * (-s / d);
+        for (int k = 0; k < mcount; k++) {
+          const float f = -gs * w[k];
+          if (f == 0.f) continue;
+          unsigned h = ((unsigned)vid[k] * 2654435761u) >> BW_HASH_SHIFT;
+          while (true) {
+            const int old = atomicCAS(&s_key[h], -1, vid[k]);
+            if (old == -1) {
+              atomicAdd(&s_used, 1);
+              break;
+            }
+            if (old == vid[k]) break;
+            h = (h + 1) & (BW_SLOTS - 1);
+          }
+          atomicAdd(&s_acc[0][h], f * g.x);
+          atomicAdd(&s_acc[1][h], f * g.y);
+          atomicAdd(&s_acc[2][h], f * g.z);
         }
-        atomicAdd(&s_acc[0][h], f * g.x);
-        atomicAdd(&s_acc[1][h], f * g.y);
-        atomicAdd(&s_acc[2][h], f * g.z);
       }
     }
-  }
-  // gather the occupied slots, then let consecutive lanes add the three
-  // components of one vertex, so one wave instruction covers about 21 vertices
-  // in 12-byte runs instead of 64 scattered addresses
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
-    const bool occ = s_key[k] >= 0;
-    const unsigned long long m = __ballot(occ);
-    const int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&s_n, __popcll(m));
-    base = __shfl(base, leader < 0 ? 0 : leader, 64);
-    if (occ) s_list[base + __popcll(m & ((1ull << lane) - 1))] = k;
-  }
-  __syncthreads();
-  const int n3 = 3 * s_n;
-  for (int k = threadIdx.x; k < n3; k += BW_THREADS) {
-    const int slot = s_list[k / 3], c = k - 3 * (k / 3);
-    atomicAdd(P.grad + 3 * (int64_t)s_key[slot] + c, s_acc[c][slot]);
+    __syncthreads();
+    const int used = s_used;
+    const bool last = base + BW_THREADS >= c1;
+    __syncthreads();  // every thread has read s_used before the next chunk changes it
+    if (!last && used <= BW_FLUSH) continue;  // block-uniform: room for another chunk
+    // flush: consecutive lanes add the three components of one vertex (a wave
+    // instruction covers about 21 slots in 12-byte runs); the table is then at
+    // least BW_FLUSH / BW_SLOTS full, except at the end of the run
+    for (int k = threadIdx.x; k < 3 * BW_SLOTS; k += BW_THREADS) {
+      const int slot = k / 3, cmp = k - 3 * slot;
+      const int v = s_key[slot];
+      if (v >= 0) atomicAdd(P.grad + 3 * (int64_t)v + cmp, s_acc[cmp][slot]);
+    }
+    __syncthreads();
+    if (last) break;
+    for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
+      s_key[k] = -1;
+      s_acc[0][k] = s_acc[1][k] = s_acc[2][k] = 0.f;
+    }
+    if (threadIdx.x == 0) s_used = 0;
+    __syncthreads();
   }
 }
 
@@ -149,7 +169,8 @@ int backward_impl(const csc_features* f, const float* sdf_d, const int32_t* feat
   A.n = n;
   A.n_meshes = f->n_meshes;
   StageTimer t(TS_BACKWARD, s);
-  k_backward<<<grid_1d(n, BW_THREADS), BW_THREADS, 0, s>>>(A);
+  const int64_t chunks = (n + BW_THREADS - 1) / BW_THREADS;
+  k_backward<<<(int)(chunks < BW_BLOCKS ? chunks : BW_BLOCKS), BW_THREADS, 0, s>>>(A);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);
 }

@@ -218,18 +218,37 @@ __global__ void k_owned(const int32_t* __restrict__ T, int64_t nh, int32_t* flag
   flag[h] = T[h] < T[next_corner((int32_t)h)] ? 1 : 0;
 }
 
-// (an open or non-manifold surface can own more or fewer than 3F/2 half-edges: such
-// a build is rejected, and nothing is written past ne)
-__global__ void k_edges(const int32_t* __restrict__ T, int64_t nh, int64_t ne, const int32_t* __restrict__ twin,
-                        const int32_t* __restrict__ eid, int4* edges, int32_t* face_edges) {
+// Edge records from the owned half-edges (u -> w with u < w) and, for each edge,
+// its class from the exact orientation of its four corners (Section 8.2: the
+// discriminant of the two face normals, evaluated exactly) with the sides to
+// extrude. The third corner of the owning face precedes u in that face; the
+// third corner of the twin's face precedes the twin's start. (An open or
+// non-manifold surface can own more or fewer than 3F/2 half-edges: such a build
+// is rejected, and nothing is written past ne; cls and count are zero-filled
+// beforehand, so edges no half-edge produced stay unclassified and empty.)
+__global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nh, int64_t ne,
+                        const int32_t* __restrict__ twin, const int32_t* __restrict__ eid, int force_both,
+                        int4* edges, int32_t* face_edges, uint8_t* cls, int32_t* count) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (h >= nh) return;
   int32_t u = T[h], w = T[next_corner((int32_t)h)];
   int32_t t = twin[h];
   if (u < w) {
     int32_t e = eid[h];
-    if (e < ne) edges[e] = make_int4(u, w, (int)(h / 3), t >= 0 ? t / 3 : -1);
     face_edges[h] = e < ne ? e : -1;
+    if (e >= ne) return;
+    edges[e] = make_int4(u, w, (int)(h / 3), t >= 0 ? t / 3 : -1);
+    int c = 0, sides = 0;
+    if (t >= 0) {
+      const int32_t c1 = T[prev_corner((int32_t)h)], c2 = T[prev_corner(t)];
+      c = classify_edge(vload_f(V, u), vload_f(V, w), vload_f(V, c1), vload_f(V, c2));
+      if (c == EDGE_CONVEX) sides = 1;
+      else if (c == EDGE_CONCAVE) sides = 2;
+      else if (c == EDGE_UNKNOWN) sides = 3;
+      if (force_both) sides = 3;
+    }
+    cls[e] = (uint8_t)(c | (sides << 2));
+    count[e] = __popc(sides);
   } else {
     int32_t e = t >= 0 ? eid[t] : -1;
     face_edges[h] = e < ne ? e : -1;
@@ -279,30 +298,6 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
         int32_t* p = &flag[brick_pos(g, x, y, z)];
         if (*p == 0) *p = 1;
       }
-}
-
-__device__ inline int32_t third_vertex(const int32_t* T, int64_t f, int32_t a, int32_t b) {
-  int32_t x = T[3 * f], y = T[3 * f + 1], z = T[3 * f + 2];
-  return (x != a && x != b) ? x : ((y != a && y != b) ? y : z);
-}
-
-// edge class (exact orientation of the four float corners) and the sides to extrude
-__global__ void k_edge_class(const float* __restrict__ V, const int32_t* __restrict__ T, const int4* __restrict__ edges,
-                             int64_t ne, int force_both, uint8_t* cls, int32_t* count) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= ne) return;
-  int c = 0, sides = 0;
-  int4 E = edges[e];
-  if (E.x >= 0 && E.z >= 0 && E.w >= 0) {
-    int32_t c1 = third_vertex(T, E.z, E.x, E.y), c2 = third_vertex(T, E.w, E.x, E.y);
-    c = classify_edge(vload_f(V, E.x), vload_f(V, E.y), vload_f(V, c1), vload_f(V, c2));
-    if (c == EDGE_CONVEX) sides = 1;
-    else if (c == EDGE_CONCAVE) sides = 2;
-    else if (c == EDGE_UNKNOWN) sides = 3;
-    if (force_both) sides = 3;
-  }
-  cls[e] = (uint8_t)(c | (sides << 2));
-  count[e] = __popc(sides);
 }
 
 // class statistics: one LDS histogram per block, one global add per bin and block
@@ -423,7 +418,7 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_FEDGES] = sizeof(int32_t) * (size_t)(3 * nf);
   sz[L_EDGES] = sizeof(int4) * (size_t)(ne + 1);
   sz[L_FN] = sizeof(float4) * (size_t)nf;
-  sz[L_ECLS] = (size_t)(ne + 1);
+  sz[L_ECLS] = (size_t)((ne + 4) / 4 * 4);  // whole ints: zero-filled as ints
   sz[L_VINFO] = sizeof(float4) * (size_t)nv;
   sz[L_VBITS] = sizeof(uint32_t) * (size_t)nv;
   sz[L_EPOLY] = sizeof(int32_t) * (size_t)(2 * ne + 1);
@@ -451,6 +446,8 @@ int check_grid(const csc_grid& g) {
     if (g.n[a] <= 0 || !isfinite(g.origin[a])) return CSC_INVALID_ARG;
   if (!finite_pos(g.h) || !(g.band_cells > 0) || !isfinite(g.band_cells)) return CSC_INVALID_ARG;
   if ((int64_t)g.n[0] * g.n[1] * g.n[2] > INT32_MAX) return CSC_GRID_TOO_LARGE;
+  for (int a = 0; a < 3; a++)  // cell offsets inside a polyhedron box are packed in 16 bits
+    if (g.n[a] > 65535) return CSC_GRID_TOO_LARGE;
   return CSC_OK;
 }
 
@@ -654,12 +651,15 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   k_vertex_queue<<<grid_1d(tv, B), B, 0, s>>>(F->vbits, tv, F->t_c, F->vpoly);
   k_owned<<<grid_1d(nh, B), B, 0, s>>>(T, nh, F->t_b);
   k_fill_i32<<<grid_1d(4 * (ne + 1), B), B, 0, s>>>((int32_t*)F->edges, 4 * (ne + 1), -1);
+  k_fill_i32<<<grid_1d(ne, B), B, 0, s>>>(F->t_c, ne, 0);
+  k_fill_i32<<<grid_1d((ne + 3) / 4, B), B, 0, s>>>((int32_t*)F->edge_cls, (ne + 3) / 4, 0);
   CK(exclusive_scan(F->t_b, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
-  k_edges<<<grid_1d(nh, B), B, 0, s>>>(T, nh, ne, F->t_a, F->t_b, F->edges, F->face_edges);
+  // edges with their classes and extrusion sides
+  k_edges<<<grid_1d(nh, B), B, 0, s>>>(verts_d, T, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->edges,
+                                       F->face_edges, F->edge_cls, F->t_c);
   // 4. face normals with the band bricks near each face; edge classes
   k_fill_i32<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, tb, 0);
   k_face_geom<<<grid_1d(tf, B), B, 0, s>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, F->t_b, F->d_stats);
-  k_edge_class<<<grid_1d(ne, B), B, 0, s>>>(verts_d, T, F->edges, ne, o.force_both_sides, F->edge_cls, F->t_c);
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
   k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, tv, F->d_stats);

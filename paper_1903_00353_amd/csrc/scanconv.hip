@@ -292,6 +292,7 @@ struct Rows {
   float sl[5], inv[5], su[5], sv[5], k[5];
   float A[3];       // vertex position (ball test)
   float R2;         // (band*h + eps)^2
+  float hf, eps;    // cell size and slack of the polyhedron's grid
   int nt;           // cells along the row
 };
 
@@ -310,12 +311,15 @@ __device__ inline void setup_rows(const Poly& q, const MeshDesc& G, Rows& r) {
   r.A[1] = pick3(q.g[0], q.g[1], q.g[2], q.ua);
   r.A[2] = pick3(q.g[0], q.g[1], q.g[2], q.va);
   r.R2 = (G.whf + G.eps) * (G.whf + G.eps);
+  r.hf = G.hf;
+  r.eps = G.eps;
   r.nt = q.nt;
 }
 
 // cells [t0, t1] of row (du, dv) that can lie in the polyhedron (conservative)
 template <int KIND>
-__device__ inline bool row_range(const Rows& r, int du, int dv, float hf, int& t0, int& t1) {
+__device__ inline bool row_range(const Rows& r, int du, int dv, int& t0, int& t1) {
+  const float hf = r.hf;
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
   float lo = 0.f, hi = (float)(r.nt - 1);
 #pragma unroll
@@ -339,76 +343,156 @@ __device__ inline bool row_range(const Rows& r, int du, int dv, float hf, int& t
   return t0 <= t1;
 }
 
-// the brick slot of the last brick looked up (consecutive candidates of a
-// polyhedron mostly share a brick)
+// the brick slot of the last brick looked up (consecutive candidates of a lane
+// mostly share a brick)
 struct BrickCache {
   int64_t bl = -1;
   int32_t slot = -1;
 };
 
-// exact distance at the candidate cells of one row, and the packed atomic minimum
+// Candidate cells of a wavefront's polyhedra pass through a small ring in LDS:
+// each lane searches the rows of its own polyhedron (cheap interval tests) and
+// appends the cells it finds; every 64 queued candidates are then finished with
+// all 64 lanes busy, each lane fetching the owning lane's polyhedron by lane
+// permutation. This keeps the exact distance and the atomic, the expensive part,
+// free of the imbalance between polyhedra of very different sizes.
+constexpr int QCAP = 128;  // < 64 left after each drain, plus at most 64 appended per round
+
+__device__ inline unsigned long long pack_cand(int lane, int t, int du, int dv) {
+  return ((unsigned long long)lane << 48) | ((unsigned long long)t << 32) | ((unsigned long long)du << 16) |
+         (unsigned long long)dv;
+}
+
+// exact distance of one queued candidate and its packed atomic minimum; called by
+// all lanes of the wavefront together (lane permutations), `valid` per lane
 template <int KIND>
-__device__ inline unsigned scan_row(const ScanArgs& P, const MeshDesc& G, const Poly& q, const Rows& r, int du,
-                                    int dv, BrickCache& bc) {
-  int t0, t1;
-  if (!row_range<KIND>(r, du, dv, G.hf, t0, t1)) return 0;
-  unsigned issued = 0;
+__device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned long long ent, bool valid,
+                                   BrickCache& bc, unsigned& issued) {
+  const int L = valid ? (int)(ent >> 48) : 0;
+  const int t = (int)((ent >> 32) & 0xffff), du = (int)((ent >> 16) & 0xffff), dv = (int)(ent & 0xffff);
+  const int mesh = __shfl(q.mesh, L, 64), id = __shfl(q.id, L, 64);
+  const int axes = __shfl(q.ra | (q.ua << 2), L, 64);
+  const int ax = __shfl(q.anc.x, L, 64), ay = __shfl(q.anc.y, L, 64), az = __shfl(q.anc.z, L, 64);
+  const f3 g0 = mk(__shfl(q.g[0], L, 64), __shfl(q.g[1], L, 64), __shfl(q.g[2], L, 64));
+  f3 g1 = mk(0.f, 0.f, 0.f), g2 = mk(0.f, 0.f, 0.f), nn = mk(0.f, 0.f, 0.f);
+  float side = 1.f;
+  if constexpr (KIND == KIND_FACE) {
+    g1 = mk(__shfl(q.g[3], L, 64), __shfl(q.g[4], L, 64), __shfl(q.g[5], L, 64));
+    g2 = mk(__shfl(q.g[6], L, 64), __shfl(q.g[7], L, 64), __shfl(q.g[8], L, 64));
+    nn = mk(__shfl(q.cone[0], L, 64), __shfl(q.cone[1], L, 64), __shfl(q.cone[2], L, 64));
+  } else if constexpr (KIND == KIND_EDGE) {
+    g1 = mk(__shfl(q.g[3], L, 64), __shfl(q.g[4], L, 64), __shfl(q.g[5], L, 64));
+    nn = mk(__shfl(q.pl[4][0], L, 64), __shfl(q.pl[4][1], L, 64), __shfl(q.pl[4][2], L, 64));
+    side = __shfl(q.side, L, 64);
+  } else {
+    nn = mk(__shfl(q.cone[0], L, 64), __shfl(q.cone[1], L, 64), __shfl(q.cone[2], L, 64));
+    side = __shfl(q.side, L, 64);
+  }
+  if (!valid) return;
+  const MeshDesc& G = P.md[mesh];
+  const int ra = axes & 3, ua = axes >> 2;
+  const int di = ra == 0 ? t : (ua == 0 ? du : dv);
+  const int dj = ra == 1 ? t : (ua == 1 ? du : dv);
+  const int dk = ra == 2 ? t : (ua == 2 ? du : dv);
   const float hf = G.hf;
-  for (int t = t0; t <= t1; t++) {
-    const int di = q.ra == 0 ? t : (q.ua == 0 ? du : dv);
-    const int dj = q.ra == 1 ? t : (q.ua == 1 ? du : dv);
-    const int dk = q.ra == 2 ? t : (q.ua == 2 ? du : dv);
-    const f3 p = mk(di * hf, dj * hf, dk * hf);
-    float d;
-    uint32_t code;
-    if constexpr (KIND == KIND_FACE) {
-      f3 qq;
-      float w[3];
-      const int region = closest_triangle(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]),
-                                          mk(q.g[6], q.g[7], q.g[8]), qq, w);
-      d = norm3(p - qq);
-      // interior closest point: the face normal is the pseudonormal
-      code = region != 0 ? SIGN_OPEN
-                         : (dot(p - qq, mk(q.cone[0], q.cone[1], q.cone[2])) >= 0.f ? SIGN_POS : SIGN_NEG);
-    } else if constexpr (KIND == KIND_EDGE) {
-      float tt;
-      const f3 qq = closest_segment(p, mk(q.g[0], q.g[1], q.g[2]), mk(q.g[3], q.g[4], q.g[5]), tt);
-      d = norm3(p - qq);
-      // interior of the edge: pseudonormal n1 + n2 = side * (base plane normal) * |n1 + n2|
-      const f3 bis = mk(q.pl[4][0], q.pl[4][1], q.pl[4][2]);
-      const bool ok = tt > 0.f && tt < 1.f && dot(bis, bis) > 0.f;
-      code = !ok ? SIGN_OPEN : (dot(p - qq, bis) * q.side >= 0.f ? SIGN_POS : SIGN_NEG);
-    } else {
-      const f3 rr = p - mk(q.g[0], q.g[1], q.g[2]);
-      const float ct = q.cone[3];
-      const float ta = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2]));
-      if (ct > -1.f) {  // cone discriminant with slack
-        const float te = ta + G.eps;
-        if (!(te >= 0.f && te * te >= ct * ct * dot(rr, rr))) continue;
+  const f3 p = mk(di * hf, dj * hf, dk * hf);
+  float d;
+  uint32_t code;
+  if constexpr (KIND == KIND_FACE) {
+    f3 qq;
+    float w[3];
+    const int region = closest_triangle(p, g0, g1, g2, qq, w);
+    d = norm3(p - qq);
+    // interior closest point: the face normal is the pseudonormal
+    code = region != 0 ? SIGN_OPEN : (dot(p - qq, nn) >= 0.f ? SIGN_POS : SIGN_NEG);
+  } else if constexpr (KIND == KIND_EDGE) {
+    float tt;
+    const f3 qq = closest_segment(p, g0, g1, tt);
+    d = norm3(p - qq);
+    // interior of the edge: pseudonormal n1 + n2 = side * (base plane normal) * |n1 + n2|
+    const bool ok = tt > 0.f && tt < 1.f && dot(nn, nn) > 0.f;
+    code = !ok ? SIGN_OPEN : (dot(p - qq, nn) * side >= 0.f ? SIGN_POS : SIGN_NEG);
+  } else {
+    const f3 rr = p - g0;
+    d = norm3(rr);
+    // the vertex itself: its angle-weighted pseudonormal (axis = side * N)
+    code = dot(rr, nn) * side >= 0.f ? SIGN_POS : SIGN_NEG;
+  }
+  if (!(d < G.whf)) return;
+  const int i = ax + di, j = ay + dj, k = az + dk;
+  const int64_t bl = brick_pos(G, i >> 3, j >> 3, k >> 3);
+  if (bl != bc.bl) {
+    bc.bl = bl;
+    bc.slot = P.brick_index[bl];
+  }
+  const int32_t slot = bc.slot;
+  if (slot >= 0 && slot < P.cap) {
+    const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (code << 30) | (uint32_t)id;
+    atomicMin(&P.keys[(int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)], key);
+    issued++;
+  } else if (slot >= P.cap) {
+    atomicOr((uint32_t*)&P.stats[ST_ERR], ERR_OVERFLOW);
+  }
+}
+
+// Every lane walks rows row0, row0 + rstep, ... below `rows` of its polyhedron q
+// and queues the candidate cells in ring `qb` (this wavefront's own); must be
+// called by all lanes of the wavefront.
+template <int KIND>
+__device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Rows& r, int rows, int row0, int rstep,
+                                      unsigned long long* qb, unsigned& issued) {
+  const int lane = threadIdx.x & 63;
+  int row = row0, t = 0, t1 = -1, du = 0, dv = 0;
+  uint32_t head = 0, tail = 0;  // the same in every lane
+  BrickCache bc;
+  while (true) {
+    while (t > t1 && row < rows) {  // next row of this lane with a candidate interval
+      dv = row / q.nu;
+      du = row - dv * q.nu;
+      row += rstep;
+      int a, b;
+      if (row_range<KIND>(r, du, dv, a, b)) {
+        t = a;
+        t1 = b;
       }
-      d = norm3(rr);
-      // the vertex itself: its angle-weighted pseudonormal (axis = side * N)
-      code = ta * q.side >= 0.f ? SIGN_POS : SIGN_NEG;
     }
-    if (d < G.whf) {
-      const int i = q.anc.x + di, j = q.anc.y + dj, k = q.anc.z + dk;
-      const int64_t bl = brick_pos(G, i >> 3, j >> 3, k >> 3);
-      if (bl != bc.bl) {
-        bc.bl = bl;
-        bc.slot = P.brick_index[bl];
+    const bool has = t <= t1;
+    if (__ballot(has) == 0) break;
+    bool push = has;
+    if constexpr (KIND == KIND_VERT) {  // cone discriminant with slack (Eq. 10)
+      if (has && q.cone[3] > -1.f) {
+        const float hf = r.hf;
+        const int di = q.ra == 0 ? t : (q.ua == 0 ? du : dv);
+        const int dj = q.ra == 1 ? t : (q.ua == 1 ? du : dv);
+        const int dk = q.ra == 2 ? t : (q.ua == 2 ? du : dv);
+        const f3 rr = mk(di * hf, dj * hf, dk * hf) - mk(q.g[0], q.g[1], q.g[2]);
+        const float te = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2])) + r.eps;
+        push = te >= 0.f && te * te >= q.cone[3] * q.cone[3] * dot(rr, rr);
       }
-      const int32_t slot = bc.slot;
-      if (slot >= 0 && slot < P.cap) {
-        const unsigned long long key =
-            ((unsigned long long)__float_as_uint(d) << 32) | (code << 30) | (uint32_t)q.id;
-        atomicMin(&P.keys[(int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)], key);
-        issued++;
-      } else if (slot >= P.cap) {
-        atomicOr((uint32_t*)&P.stats[ST_ERR], ERR_OVERFLOW);
-      }
+    }
+    const unsigned long long pm = __ballot(push);
+    if (push) qb[(tail + lanes_below(pm)) & (QCAP - 1)] = pack_cand(lane, t, du, dv);
+    tail += (uint32_t)__popcll(pm);
+    if (has) t++;
+    if (tail - head >= 64) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const unsigned long long e = qb[(head + lane) & (QCAP - 1)];
+      finish_cand<KIND>(P, q, e, true, bc, issued);
+      head += 64;
     }
   }
-  return issued;
+  if (tail != head) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool valid = (uint32_t)lane < tail - head;
+    const unsigned long long e = valid ? qb[(head + lane) & (QCAP - 1)] : 0ull;
+    finish_cand<KIND>(P, q, e, valid, bc, issued);
+  }
+  // the ring is reused by the next call: finish its reads first
+  __builtin_amdgcn_wave_barrier();
 }
 
 // counter[0] counts the one-thread-per-polyhedron launch, counter[3] the overflow launch
@@ -423,12 +507,13 @@ __device__ inline int64_t item_count(const ScanArgs& P) {
   return P.n_items_d ? (*P.n_items_d < P.n_items ? *P.n_items_d : P.n_items) : P.n_items;
 }
 
-// one thread per polyhedron; polyhedra with more than small_rows rows are appended
+// one polyhedron per lane; polyhedra with more than small_rows rows are appended
 // to the overflow list (one atomic per wavefront)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
+  __shared__ unsigned long long s_q[256 / 64][QCAP];
   const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  Poly q;
+  Poly q = {};
   const int nc = item < item_count(P) ? build_poly<KIND>(P, item, q) : 0;
   const int rows = nc > 0 ? q.nu * q.nv : 0;
   const bool big = rows > P.small_rows;
@@ -441,14 +526,9 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
     if (big) P.big_items[base + lanes_below(m)] = (int32_t)item;
   }
   unsigned issued = 0;
-  if (nc > 0 && !big) {
-    const MeshDesc& G = P.md[q.mesh];
-    Rows r;
-    setup_rows<KIND>(q, G, r);
-    BrickCache bc;
-    for (int dv = 0; dv < q.nv; dv++)
-      for (int du = 0; du < q.nu; du++) issued += scan_row<KIND>(P, G, q, r, du, dv, bc);
-  }
+  Rows r = {};
+  if (nc > 0 && !big) setup_rows<KIND>(q, P.md[q.mesh], r);
+  scan_rows_wave<KIND>(P, q, r, nc > 0 && !big ? rows : 0, 0, 1, s_q[threadIdx.x >> 6], issued);
   add_issued(P, issued, 0);
 }
 
@@ -456,21 +536,16 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
 // every wavefront leaves once the list (final before this launch) is exhausted
 template <int KIND>
 __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
+  __shared__ unsigned long long s_q[QCAP];
   const int lane = threadIdx.x;
   const int32_t n_big = *P.big_count;
   unsigned issued = 0;
   for (int32_t w = blockIdx.x; w < n_big; w += gridDim.x) {
-    Poly q;
-    if (build_poly<KIND>(P, P.big_items[w], q) <= 0) continue;
-    const MeshDesc& G = P.md[q.mesh];
+    Poly q = {};
+    if (build_poly<KIND>(P, P.big_items[w], q) <= 0) continue;  // the same for every lane
     Rows r;
-    setup_rows<KIND>(q, G, r);
-    const int nu = q.nu, rows = nu * q.nv;
-    BrickCache bc;
-    for (int row = lane; row < rows; row += 64) {
-      const int dv = row / nu, du = row - dv * nu;
-      issued += scan_row<KIND>(P, G, q, r, du, dv, bc);
-    }
+    setup_rows<KIND>(q, P.md[q.mesh], r);
+    scan_rows_wave<KIND>(P, q, r, q.nu * q.nv, lane, 64, s_q, issued);
   }
   add_issued(P, issued, 3);
 }

@@ -5,7 +5,7 @@ import pytest
 
 import meshgen
 import oracle
-from parity import assert_parity, assert_same_sums, compare
+from parity import assert_parity, assert_same_sums, compare, vertex_term_scale
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,7 +44,8 @@ def test_batch_equals_single_mesh_runs(graph_safe):
         c2, s2, f2 = batch_band(B, m)
         assert np.array_equal(c1, c2) and np.array_equal(s1, s2) and np.array_equal(f1, f2), m
         g2 = B.grad(m).cpu().numpy()
-        assert_same_sums(g1, g2, m)
+        scale = vertex_term_scale(f, oracle.OracleMesh(v, f).edges, v.shape[0], f1, 2.0 * s1)
+        assert_same_sums(g1, g2, scale, m)
 
 
 def test_full_batch_against_oracle(configs):
@@ -70,6 +71,7 @@ def test_graph_replay_matches_eager():
     vertex update between replays, each equal to an eager step on the same inputs."""
     meshes, grids = small_batch(6)
     B = P.Batch(meshes, grids, graph_safe=True)
+    edges = [oracle.OracleMesh(v, f).edges for v, f in meshes]
     B.capture()
     for it in range(3):
         if it == 2:
@@ -85,7 +87,9 @@ def test_graph_replay_matches_eager():
         eager = [batch_band(B, m) for m in range(len(meshes))]
         for a, b in zip(rep, eager):
             assert all(np.array_equal(x, y) for x, y in zip(a, b)), it
-        assert_same_sums(g_rep.cpu().numpy(), B.grad_verts.cpu().numpy(), it)
+        scale = np.concatenate([vertex_term_scale(f, edges[m], v.shape[0], eager[m][2], 2.0 * eager[m][1])
+                                for m, (v, f) in enumerate(meshes)])
+        assert_same_sums(g_rep.cpu().numpy(), B.grad_verts.cpu().numpy(), scale, it)
         del junk
 
 

@@ -6,7 +6,7 @@ import pytest
 import meshgen
 import oracle
 from meshgen import Grid
-from parity import assert_parity, assert_same_sums, compare
+from parity import assert_parity, assert_same_sums, compare, vertex_term_scale
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -243,4 +243,6 @@ def test_autograd_function():
     feats = P.csc_build_features(verts.detach(), tris, g)
     band = P.csc_scan_convert(feats)
     ref = P.csc_sdf_backward(feats, band, 2.0 * band.sdf)
-    assert_same_sums(verts.grad.cpu().numpy(), ref.cpu().numpy())
+    scale = vertex_term_scale(f, oracle.OracleMesh(v, f).edges, v.shape[0], band.feat.cpu().numpy(),
+                              2.0 * band.sdf.cpu().numpy())
+    assert_same_sums(verts.grad.cpu().numpy(), ref.cpu().numpy(), scale)

@@ -64,6 +64,10 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
   for (int64_t base = c0; base < c1; base += BW_THREADS) {
     const int64_t i = base + threadIdx.x;
     const float gs = i < c1 ? P.gsdf[i] : 0.f;
+    // this cell's contribution to each vertex k of its feature: f_k * g
+    int32_t vid[3] = {-1, -1, -1};
+    f3 con[3] = {mk(0.f, 0.f, 0.f), mk(0.f, 0.f, 0.f), mk(0.f, 0.f, 0.f)};
+    int64_t fkey = -1 - (int64_t)threadIdx.x;  // unique unless the cell contributes
     if (gs != 0.f) {
       if (P.band_off) {
         while (i >= P.band_off[m + 1]) m++;  // cells only move forward through the meshes
@@ -75,25 +79,25 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
       const f3 zero = mk(0.f, 0.f, 0.f);
       f3 q;
       float w[3] = {0.f, 0.f, 0.f};
-      int32_t vid[3] = {0, 0, 0};
       int mcount;
+      int32_t v3[3];
       if (lf < G.nf) {
         const int64_t f = (int64_t)G.f_off + lf;
-        for (int j = 0; j < 3; j++) vid[j] = P.T[3 * f + j];
-        closest_triangle(zero, relb(P.V, vid[0], c), relb(P.V, vid[1], c), relb(P.V, vid[2], c), q, w);
+        for (int j = 0; j < 3; j++) v3[j] = P.T[3 * f + j];
+        closest_triangle(zero, relb(P.V, v3[0], c), relb(P.V, v3[1], c), relb(P.V, v3[2], c), q, w);
         mcount = 3;
       } else if (lf < G.nf + G.ne) {
         int4 E = P.edges[(int64_t)G.e_off + (lf - G.nf)];
-        vid[0] = E.x;
-        vid[1] = E.y;
+        v3[0] = E.x;
+        v3[1] = E.y;
         float t;
         q = closest_segment(zero, relb(P.V, E.x, c), relb(P.V, E.y, c), t);
         w[0] = 1.f - t;
         w[1] = t;
         mcount = 2;
       } else {
-        vid[0] = G.v_off + (lf - G.nf - G.ne);
-        q = relb(P.V, vid[0], c);
+        v3[0] = G.v_off + (lf - G.nf - G.ne);
+        q = relb(P.V, v3[0], c);
         w[0] = 1.f;
         mcount = 1;
       }
@@ -102,23 +106,57 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
         const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
         // c - q = -q in this frame; g = s (c - q) / |c - q|
         const f3 g = q * (-s / d);
-        for (int k = 0; k < mcount; k++) {
-          const float f = -gs * w[k];
-          if (f == 0.f) continue;
-          unsigned h = ((unsigned)vid[k] * 2654435761u) >> BW_HASH_SHIFT;
-          while (true) {
-            const int old = atomicCAS(&s_key[h], -1, vid[k]);
-            if (old == -1) {
-              atomicAdd(&s_used, 1);
-              break;
-            }
-            if (old == vid[k]) break;
-            h = (h + 1) & (BW_SLOTS - 1);
+        for (int k = 0; k < 3; k++) {
+          if (k < mcount) {
+            vid[k] = v3[k];
+            con[k] = g * (-gs * w[k]);
           }
-          atomicAdd(&s_acc[0][h], f * g.x);
-          atomicAdd(&s_acc[1][h], f * g.y);
-          atomicAdd(&s_acc[2][h], f * g.z);
         }
+        fkey = ((int64_t)m << 32) | (uint32_t)lf;
+      }
+    }
+    // Consecutive band cells often share their feature (large triangles cover many
+    // cells). When a wavefront holds enough such runs of equal feature in
+    // consecutive lanes, each run is first summed across its lanes (segmented
+    // inclusive scan) and only its last lane touches the table: far fewer
+    // conflicting LDS atomics on the same few slots. A feature can come back in
+    // a later, separate run of the same wavefront, so runs are told apart by a
+    // run number (count of run heads up to the lane), not by the feature.
+    const int lane = threadIdx.x & 63;
+    const int64_t knext = __shfl_down(fkey, 1, 64), kprev = __shfl_up(fkey, 1, 64);
+    const bool same_next = lane < 63 && knext == fkey;
+    bool owner = fkey >= 0;
+    if (__popcll(__ballot(same_next)) >= 8) {
+      const unsigned long long heads = __ballot(lane == 0 || kprev != fkey);
+      const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+      const int run = __popcll(heads & upto);
+      for (int o = 1; o < 64; o <<= 1) {
+        const int ru = __shfl_up(run, o, 64);
+        const bool take = lane >= o && ru == run;
+        for (int k = 0; k < 3; k++) {
+          const float ux = __shfl_up(con[k].x, o, 64), uy = __shfl_up(con[k].y, o, 64),
+                      uz = __shfl_up(con[k].z, o, 64);
+          if (take) con[k] = con[k] + mk(ux, uy, uz);
+        }
+      }
+      owner = owner && !same_next;
+    }
+    if (owner) {
+      for (int k = 0; k < 3; k++) {
+        if (vid[k] < 0) continue;
+        unsigned h = ((unsigned)vid[k] * 2654435761u) >> BW_HASH_SHIFT;
+        while (true) {
+          const int old = atomicCAS(&s_key[h], -1, vid[k]);
+          if (old == -1) {
+            atomicAdd(&s_used, 1);
+            break;
+          }
+          if (old == vid[k]) break;
+          h = (h + 1) & (BW_SLOTS - 1);
+        }
+        atomicAdd(&s_acc[0][h], con[k].x);
+        atomicAdd(&s_acc[1][h], con[k].y);
+        atomicAdd(&s_acc[2][h], con[k].z);
       }
     }
     __syncthreads();

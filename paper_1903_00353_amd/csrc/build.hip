@@ -86,8 +86,9 @@ __global__ void k_offsets(const uint32_t* __restrict__ key, int64_t nh, int64_t 
     for (int64_t v = k + 1; v <= nv; v++) off[v] = (int32_t)nh;
 }
 
-constexpr int CC_THREADS = 256;
-constexpr int CC_SLOTS = 1024;  // > 3 * CC_THREADS insertions: probing always ends
+constexpr int CC_THREADS = 1024;     // faces per block: more faces share each returning global add
+constexpr int CC_SLOTS = 4096;       // > 3 * CC_THREADS insertions: probing always ends
+constexpr int CC_HASH_SHIFT = 20;    // 32 - log2(CC_SLOTS)
 
 // Corner counts per vertex without library sorting (graph-capturable path): a
 // block counts its corners per vertex in an LDS hash table and reserves one range
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(CC_THREADS) void k_count_corners(const int32_t* __r
 #pragma unroll
     for (int j = 0; j < 3; j++) {
       const int32_t v = tg[3 * f + j];
-      unsigned h = ((unsigned)v * 2654435761u) >> 22;
+      unsigned h = ((unsigned)v * 2654435761u) >> CC_HASH_SHIFT;
       while (true) {
         int old = atomicCAS(&s_key[h], -1, v);
         if (old == -1 || old == v) break;

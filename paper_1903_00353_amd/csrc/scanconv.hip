@@ -75,9 +75,12 @@ __device__ inline d3 vload_d(const float* V, int64_t i) {
   return mkd((double)V[3 * i], (double)V[3 * i + 1], (double)V[3 * i + 2]);
 }
 
+// unit vector of an FP64 direction, normalised in FP32 (plane normals only decide
+// membership, which carries a slack of 1e-3 cells)
 __device__ inline f3 unit_f(d3 v) {
-  double l = len(v);
-  return l > 0 ? tof(v * (1.0 / l)) : mk(0.f, 0.f, 0.f);
+  const f3 w = tof(v);
+  const float l2 = dot(w, w);
+  return l2 > 0.f ? w * __builtin_amdgcn_rsqf(l2) : mk(0.f, 0.f, 0.f);
 }
 
 // axis of the largest |component|
@@ -146,8 +149,7 @@ __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f
   const f3 W[3] = {A, B, C};
   for (int j = 0; j < 3; j++) {
     f3 m = cross(nf, W[(j + 1) % 3] - W[j]);
-    float l = norm3(m);
-    set_plane(q, j, m * (1.f / l), W[j]);
+    set_plane(q, j, m * __builtin_amdgcn_rsqf(dot(m, m)), W[j]);
   }
   float na = dot(nf, A);
   q.pl[3][0] = -nf.x; q.pl[3][1] = -nf.y; q.pl[3][2] = -nf.z; q.pl[3][3] = na + G.whf;
@@ -184,11 +186,12 @@ __device__ inline int build_edge(const ScanArgs& P, const MeshDesc& G, int32_t e
   const double U1[3] = {u1.x, u1.y, u1.z}, U2[3] = {u2.x, u2.y, u2.z}, US[3] = {us.x, us.y, us.z};
   const double A3[3] = {a.x, a.y, a.z}, B3[3] = {b.x, b.y, b.z};
   double lo[3], hi[3];
+  const double tsc = us2 > 1e-12 ? 2.0 * G.whd / us2 : 0.0;
   for (int k = 0; k < 3; k++) {
     double x1 = G.whd * U1[k], x2 = G.whd * U2[k];
     double alo = fmin(0.0, fmin(x1, x2)), ahi = fmax(0.0, fmax(x1, x2));
     if (us2 > 1e-12) {  // the arc lies inside the quadrilateral through the tangent intersection
-      double t = G.whd * 2.0 * US[k] / us2;
+      double t = US[k] * tsc;
       alo = fmin(alo, t);
       ahi = fmax(ahi, t);
     } else {
@@ -232,12 +235,18 @@ __device__ inline int build_vertex(const ScanArgs& P, const MeshDesc& G, int32_t
   d3 ax = mkd(vi.x * sg, vi.y * sg, vi.z * sg);
   d3 p = vload_d(P.V, v);
   const double AX[3] = {ax.x, ax.y, ax.z}, P3[3] = {p.x, p.y, p.z};
-  double tn = hemi ? 0.0 : sqrt(fmax(0.0, 1.0 - ct * ct)) / ct;
+  // box of the cone: FP32 suffices (a relative error near 1e-7 of band*h, far
+  // inside the eps margin the box is grown by); a cone opening to nearly 90
+  // degrees gets the box of its hemisphere, which contains it
+  const float ctf = (float)ct;
+  const bool wide = hemi || !(ctf > 1e-6f);
+  double tn = wide ? 0.0 : (double)(sqrtf(fmaxf(0.f, 1.f - ctf * ctf)) * __builtin_amdgcn_rcpf(ctf));
   double lo[3], hi[3];
   for (int k = 0; k < 3; k++) {
-    double s = sqrt(fmax(0.0, 1.0 - AX[k] * AX[k]));
+    const float axk = (float)AX[k];
+    double s = (double)sqrtf(fmaxf(0.f, 1.f - axk * axk));
     double l, u;
-    if (hemi) {
+    if (wide) {
       l = AX[k] > 0 ? -G.whd * s : -G.whd;
       u = AX[k] < 0 ? G.whd * s : G.whd;
     } else {
@@ -292,7 +301,7 @@ struct Rows {
   float sl[5], inv[5], su[5], sv[5], k[5];
   float A[3];       // vertex position (ball test)
   float R2;         // (band*h + eps)^2
-  float hf, eps;    // cell size and slack of the polyhedron's grid
+  float hf, ihf, eps;  // cell size, its inverse and the slack of the polyhedron's grid
   int nt;           // cells along the row
 };
 
@@ -302,7 +311,7 @@ __device__ inline void setup_rows(const Poly& q, const MeshDesc& G, Rows& r) {
 #pragma unroll
   for (int i = 0; i < NPL; i++) {
     r.sl[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.ra) * G.hf;
-    r.inv[i] = fabsf(r.sl[i]) > 1e-20f ? 1.f / r.sl[i] : 0.f;
+    r.inv[i] = fabsf(r.sl[i]) > 1e-20f ? __builtin_amdgcn_rcpf(r.sl[i]) : 0.f;
     r.su[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.ua) * G.hf;
     r.sv[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.va) * G.hf;
     r.k[i] = q.pl[i][3] + G.eps;
@@ -312,6 +321,7 @@ __device__ inline void setup_rows(const Poly& q, const MeshDesc& G, Rows& r) {
   r.A[2] = pick3(q.g[0], q.g[1], q.g[2], q.va);
   r.R2 = (G.whf + G.eps) * (G.whf + G.eps);
   r.hf = G.hf;
+  r.ihf = (float)G.inv_h;
   r.eps = G.eps;
   r.nt = q.nt;
 }
@@ -333,7 +343,7 @@ __device__ inline bool row_range(const Rows& r, int du, int dv, int& t0, int& t1
     const float qu = du * hf - r.A[1], qv = dv * hf - r.A[2];
     const float disc = r.R2 - qu * qu - qv * qv;
     if (disc < 0.f) return false;
-    const float w = sqrtf(disc) / hf, c = r.A[0] / hf;
+    const float w = sqrtf(disc) * r.ihf, c = r.A[0] * r.ihf;
     lo = fmaxf(lo, c - w);
     hi = fminf(hi, c + w);
   }

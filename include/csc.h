@@ -71,8 +71,10 @@ typedef struct csc_options {
                                1 hemispheres on both sides, 2 no extrusion (ablation only) */
   int32_t force_both_sides; /* 1: extrude every non-flat edge and every vertex on both sides */
   int32_t small_rows[3];    /* schedule (faces, edges, vertices): polyhedra with more rows than this
-                               are walked by a wavefront each instead of a single thread; 0 = 32.
-                               Only the speed depends on it (see the autotuner in the binding). */
+                               go to an overflow pass that gives each one a whole wavefront; the
+                               rest share the rows of their wavefront. 0 = 32; values above 2^24
+                               act as 2^24. Only the speed depends on it (see the autotuner in the
+                               binding). */
 } csc_options;
 
 typedef struct csc_features csc_features; /* opaque, library-owned, device resident */

@@ -13,7 +13,7 @@ import json
 import math
 import os
 
-CANDIDATES = (8, 16, 32, 64, 128, 1 << 30)
+CANDIDATES = (8, 16, 32, 64, 128, 1 << 24)
 KIND_STAGES = ("scan_faces", "scan_edges", "scan_vertices")
 
 

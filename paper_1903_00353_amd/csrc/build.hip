@@ -473,6 +473,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   for (int k = 0; k < 3; k++) {
     if (o.small_rows[k] < 0) return CSC_INVALID_ARG;
     if (o.small_rows[k] == 0) o.small_rows[k] = 32;
+    if (o.small_rows[k] > (1 << 24)) o.small_rows[k] = 1 << 24;  // row totals of a wavefront stay in 32 bits
   }
   std::vector<MeshDesc> mesh((size_t)n_meshes);
   int64_t tv = 0, tf = 0, te = 0, tb = 0;

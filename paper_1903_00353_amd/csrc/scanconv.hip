@@ -445,52 +445,112 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
   }
 }
 
-// Every lane walks rows row0, row0 + rstep, ... below `rows` of its polyhedron q
-// and queues the candidate cells in ring `qb` (this wavefront's own); must be
-// called by all lanes of the wavefront.
+// inclusive prefix sum over the lanes of a wavefront
+__device__ inline int wave_incl_sum(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// cells [t0, t1] of row (du, dv) of the polyhedron held by lane L, its row
+// coefficients fetched by lane permutation; called by all lanes together
 template <int KIND>
-__device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Rows& r, int rows, int row0, int rstep,
+__device__ inline bool row_range_of(const Rows& r, int L, int du, int dv, int& t0, int& t1) {
+  constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
+  Rows o;
+#pragma unroll
+  for (int i = 0; i < NPL; i++) {
+    o.inv[i] = __shfl(r.inv[i], L, 64);
+    o.su[i] = __shfl(r.su[i], L, 64);
+    o.sv[i] = __shfl(r.sv[i], L, 64);
+    o.k[i] = __shfl(r.k[i], L, 64);
+  }
+  o.nt = __shfl(r.nt, L, 64);
+  if constexpr (KIND == KIND_VERT) {
+    o.A[0] = __shfl(r.A[0], L, 64);
+    o.A[1] = __shfl(r.A[1], L, 64);
+    o.A[2] = __shfl(r.A[2], L, 64);
+    o.R2 = __shfl(r.R2, L, 64);
+    o.hf = __shfl(r.hf, L, 64);
+    o.ihf = __shfl(r.ihf, L, 64);
+  }
+  return row_range<KIND>(o, du, dv, t0, t1);
+}
+
+// The rows of the wavefront's polyhedra (lane l holds `rows` rows of its own
+// polyhedron q) are dealt out evenly: in each round lane j takes the j-th next
+// row of the whole wavefront, finds the lane owning it (binary search over the
+// prefix sums of the row counts), computes its interval with the owner's
+// coefficients, and queues its candidate cells in ring `qb` (this wavefront's
+// own) under the owner's lane number. Lanes with many rows thus no longer hold
+// up the others. Must be called by all lanes of the wavefront.
+template <int KIND>
+__device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Rows& r, int rows,
                                       unsigned long long* qb, unsigned& issued) {
   const int lane = threadIdx.x & 63;
-  int row = row0, t = 0, t1 = -1, du = 0, dv = 0;
+  const int incl = wave_incl_sum(rows), excl = incl - rows;
+  const int total = __shfl(incl, 63, 64);
   uint32_t head = 0, tail = 0;  // the same in every lane
   BrickCache bc;
-  while (true) {
-    while (t > t1 && row < rows) {  // next row of this lane with a candidate interval
-      dv = row / q.nu;
-      du = row - dv * q.nu;
-      row += rstep;
-      int a, b;
-      if (row_range<KIND>(r, du, dv, a, b)) {
-        t = a;
-        t1 = b;
-      }
+  for (int base = 0; base < total; base += 64) {
+    const int g = base + lane;
+    int lo = 0, hi = 63;  // the last lane whose rows start at or before g
+#pragma unroll
+    for (int s = 0; s < 6; s++) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (__shfl(excl, mid, 64) <= g) lo = mid;
+      else hi = mid - 1;
     }
-    const bool has = t <= t1;
-    if (__ballot(has) == 0) break;
-    bool push = has;
-    if constexpr (KIND == KIND_VERT) {  // cone discriminant with slack (Eq. 10)
-      if (has && q.cone[3] > -1.f) {
-        const float hf = r.hf;
-        const int di = q.ra == 0 ? t : (q.ua == 0 ? du : dv);
-        const int dj = q.ra == 1 ? t : (q.ua == 1 ? du : dv);
-        const int dk = q.ra == 2 ? t : (q.ua == 2 ? du : dv);
-        const f3 rr = mk(di * hf, dj * hf, dk * hf) - mk(q.g[0], q.g[1], q.g[2]);
-        const float te = dot(rr, mk(q.cone[0], q.cone[1], q.cone[2])) + r.eps;
-        push = te >= 0.f && te * te >= q.cone[3] * q.cone[3] * dot(rr, rr);
-      }
+    const int L = lo;
+    const int rloc = g - __shfl(excl, L, 64), nuL = __shfl(q.nu, L, 64);
+    const int nud = nuL > 0 ? nuL : 1;  // past the last row L may hold no polyhedron
+    const int dv = g < total ? rloc / nud : 0, du = g < total ? rloc - dv * nud : 0;
+    int t = 0, t1 = -1;
+    if (!row_range_of<KIND>(r, L, du, dv, t, t1) || g >= total) t1 = -1;
+    // vertices: the owner's cone for the per-cell discriminant
+    [[maybe_unused]] f3 cg = mk(0.f, 0.f, 0.f), cax = mk(0.f, 0.f, 0.f);
+    [[maybe_unused]] float cct = -2.f, chf = 0.f, ceps = 0.f;
+    [[maybe_unused]] int cra = 0, cua = 0;
+    if constexpr (KIND == KIND_VERT) {
+      cg = mk(__shfl(q.g[0], L, 64), __shfl(q.g[1], L, 64), __shfl(q.g[2], L, 64));
+      cax = mk(__shfl(q.cone[0], L, 64), __shfl(q.cone[1], L, 64), __shfl(q.cone[2], L, 64));
+      cct = __shfl(q.cone[3], L, 64);
+      chf = __shfl(r.hf, L, 64);
+      ceps = __shfl(r.eps, L, 64);
+      const int ax = __shfl(q.ra | (q.ua << 2), L, 64);
+      cra = ax & 3;
+      cua = ax >> 2;
     }
-    const unsigned long long pm = __ballot(push);
-    if (push) qb[(tail + lanes_below(pm)) & (QCAP - 1)] = pack_cand(lane, t, du, dv);
-    tail += (uint32_t)__popcll(pm);
-    if (has) t++;
-    if (tail - head >= 64) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const unsigned long long e = qb[(head + lane) & (QCAP - 1)];
-      finish_cand<KIND>(P, q, e, true, bc, issued);
-      head += 64;
+    while (true) {
+      const bool has = t <= t1;
+      if (__ballot(has) == 0) break;
+      bool push = has;
+      if constexpr (KIND == KIND_VERT) {  // cone discriminant with slack (Eq. 10)
+        if (has && cct > -1.f) {
+          const int di = cra == 0 ? t : (cua == 0 ? du : dv);
+          const int dj = cra == 1 ? t : (cua == 1 ? du : dv);
+          const int dk = cra == 2 ? t : (cua == 2 ? du : dv);
+          const f3 rr = mk(di * chf, dj * chf, dk * chf) - cg;
+          const float te = dot(rr, cax) + ceps;
+          push = te >= 0.f && te * te >= cct * cct * dot(rr, rr);
+        }
+      }
+      const unsigned long long pm = __ballot(push);
+      if (push) qb[(tail + lanes_below(pm)) & (QCAP - 1)] = pack_cand(L, t, du, dv);
+      tail += (uint32_t)__popcll(pm);
+      if (has) t++;
+      if (tail - head >= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned long long e = qb[(head + lane) & (QCAP - 1)];
+        finish_cand<KIND>(P, q, e, true, bc, issued);
+        head += 64;
+      }
     }
   }
   if (tail != head) {
@@ -517,8 +577,9 @@ __device__ inline int64_t item_count(const ScanArgs& P) {
   return P.n_items_d ? (*P.n_items_d < P.n_items ? *P.n_items_d : P.n_items) : P.n_items;
 }
 
-// one polyhedron per lane; polyhedra with more than small_rows rows are appended
-// to the overflow list (one atomic per wavefront)
+// one polyhedron per lane, the rows of a wavefront's polyhedra shared by its
+// lanes; polyhedra with more than small_rows rows are appended to the overflow
+// list (one atomic per wavefront)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   __shared__ unsigned long long s_q[256 / 64][QCAP];
@@ -538,11 +599,11 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   unsigned issued = 0;
   Rows r = {};
   if (nc > 0 && !big) setup_rows<KIND>(q, P.md[q.mesh], r);
-  scan_rows_wave<KIND>(P, q, r, nc > 0 && !big ? rows : 0, 0, 1, s_q[threadIdx.x >> 6], issued);
+  scan_rows_wave<KIND>(P, q, r, nc > 0 && !big ? rows : 0, s_q[threadIdx.x >> 6], issued);
   add_issued(P, issued, 0);
 }
 
-// a wavefront per polyhedron of the overflow list, lanes striding over its rows;
+// a wavefront per polyhedron of the overflow list, its rows dealt out to the lanes;
 // every wavefront leaves once the list (final before this launch) is exhausted
 template <int KIND>
 __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
@@ -555,7 +616,7 @@ __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
     if (build_poly<KIND>(P, P.big_items[w], q) <= 0) continue;  // the same for every lane
     Rows r;
     setup_rows<KIND>(q, P.md[q.mesh], r);
-    scan_rows_wave<KIND>(P, q, r, q.nu * q.nv, lane, 64, s_q, issued);
+    scan_rows_wave<KIND>(P, q, r, lane == 0 ? q.nu * q.nv : 0, s_q, issued);  // lane 0 owns every row
   }
   add_issued(P, issued, 3);
 }

@@ -12,6 +12,7 @@ namespace csc {
 struct BwdArgs {
   const float* V;
   const int32_t* T;          // global vertex indices
+  const float* fv;           // corner positions in face order [nf][9]
   const int4* edges;
   const MeshDesc* md;
   const float* sdf;
@@ -27,6 +28,9 @@ struct BwdArgs {
 
 __device__ inline f3 relb(const float* V, int64_t i, d3 c) {
   return tof(mkd((double)V[3 * i] - c.x, (double)V[3 * i + 1] - c.y, (double)V[3 * i + 2] - c.z));
+}
+__device__ inline f3 relv(const float* p, d3 c) {
+  return tof(mkd((double)p[0] - c.x, (double)p[1] - c.y, (double)p[2] - c.z));
 }
 
 constexpr int BW_THREADS = 256;
@@ -84,7 +88,8 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
       if (lf < G.nf) {
         const int64_t f = (int64_t)G.f_off + lf;
         for (int j = 0; j < 3; j++) v3[j] = P.T[3 * f + j];
-        closest_triangle(zero, relb(P.V, v3[0], c), relb(P.V, v3[1], c), relb(P.V, v3[2], c), q, w);
+        const float* fv = P.fv + 9 * f;
+        closest_triangle(zero, relv(fv, c), relv(fv + 3, c), relv(fv + 6, c), q, w);
         mcount = 3;
       } else if (lf < G.nf + G.ne) {
         int4 E = P.edges[(int64_t)G.e_off + (lf - G.nf)];
@@ -195,6 +200,7 @@ int backward_impl(const csc_features* f, const float* sdf_d, const int32_t* feat
   BwdArgs A;
   A.V = f->verts;
   A.T = f->tris_g;
+  A.fv = f->face_v;
   A.edges = f->edges;
   A.md = f->d_mesh;
   A.sdf = sdf_d;

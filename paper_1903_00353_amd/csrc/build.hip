@@ -264,10 +264,17 @@ __global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__
 // every cell a scan can write has its brick marked.
 __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf,
                             const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float4* fn,
-                            int32_t* flag, int64_t* stats) {
+                            float* fv, int32_t* flag, int64_t* stats) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  const d3 a = vload_d(V, T[3 * f]), b = vload_d(V, T[3 * f + 1]), c = vload_d(V, T[3 * f + 2]);
+  const f3 af = vload_f(V, T[3 * f]), bf = vload_f(V, T[3 * f + 1]), cf = vload_f(V, T[3 * f + 2]);
+  // the corners again in face order: later passes read one contiguous record per
+  // face instead of three vertex gathers
+  float* o = fv + 9 * f;
+  o[0] = af.x; o[1] = af.y; o[2] = af.z;
+  o[3] = bf.x; o[4] = bf.y; o[5] = bf.z;
+  o[6] = cf.x; o[7] = cf.y; o[8] = cf.z;
+  const d3 a = mkd(af.x, af.y, af.z), b = mkd(bf.x, bf.y, bf.z), c = mkd(cf.x, cf.y, cf.z);
   const d3 n = cross(b - a, c - a);
   const double l = len(n);
   if (!(l > 0)) {
@@ -392,7 +399,7 @@ namespace {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 enum {
-  L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FN, L_ECLS,
+  L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FN, L_FV, L_ECLS,
   L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_STATS,
   L_SORT, L_N
 };
@@ -419,6 +426,7 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_FEDGES] = sizeof(int32_t) * (size_t)(3 * nf);
   sz[L_EDGES] = sizeof(int4) * (size_t)(ne + 1);
   sz[L_FN] = sizeof(float4) * (size_t)nf;
+  sz[L_FV] = sizeof(float) * 9 * (size_t)nf;
   sz[L_ECLS] = (size_t)((ne + 4) / 4 * 4);  // whole ints: zero-filled as ints
   sz[L_VINFO] = sizeof(float4) * (size_t)nv;
   sz[L_VBITS] = sizeof(uint32_t) * (size_t)nv;
@@ -581,6 +589,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->face_edges = (int32_t*)(A + L.off[L_FEDGES]);
   F->edges = (int4*)(A + L.off[L_EDGES]);
   F->face_n = (float4*)(A + L.off[L_FN]);
+  F->face_v = (float*)(A + L.off[L_FV]);
   F->edge_cls = (uint8_t*)(A + L.off[L_ECLS]);
   F->vinfo = (float4*)(A + L.off[L_VINFO]);
   F->vbits = (uint32_t*)(A + L.off[L_VBITS]);
@@ -661,7 +670,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                        F->face_edges, F->edge_cls, F->t_c);
   // 4. face normals with the band bricks near each face; edge classes
   k_fill_i32<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, tb, 0);
-  k_face_geom<<<grid_1d(tf, B), B, 0, s>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, F->t_b, F->d_stats);
+  k_face_geom<<<grid_1d(tf, B), B, 0, s>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, F->face_v, F->t_b,
+                                            F->d_stats);
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
   k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, tv, F->d_stats);

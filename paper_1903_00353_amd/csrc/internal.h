@@ -141,6 +141,7 @@ struct csc_features {
   int32_t* face_edges = nullptr;    // [3nf]
   int4* edges = nullptr;            // [ne] (a, b, f_left, f_right), global indices
   float4* face_n = nullptr;         // [nf] unit normal
+  float* face_v = nullptr;          // [nf][3][3] corner positions in face order
   uint8_t* edge_cls = nullptr;      // [ne] class | side bits << 2
   float4* vinfo = nullptr;          // [nv] unit pseudonormal, cone aperture cosine
   uint32_t* vbits = nullptr;        // [nv] class bits

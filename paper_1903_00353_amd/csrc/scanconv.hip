@@ -25,6 +25,7 @@ enum { KIND_FACE = 0, KIND_EDGE = 1, KIND_VERT = 2 };
 struct ScanArgs {
   const float* V;
   const int32_t* T;            // global vertex indices
+  const float* fv;             // corner positions in face order [nf][9]
   const float4* fn;
   const int4* edges;
   const uint8_t* ecls;
@@ -133,7 +134,8 @@ __device__ inline void set_plane(Poly& q, int i, f3 m, f3 through) {
 // Face prism (Section 8.1): three inward side planes through the edges and the two
 // caps |n . (x - a)| <= band*h (both the outward and inward prism at once).
 __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f, Poly& q) {
-  d3 a = vload_d(P.V, P.T[3 * f]), b = vload_d(P.V, P.T[3 * f + 1]), c = vload_d(P.V, P.T[3 * f + 2]);
+  const float* fv = P.fv + 9 * f;
+  d3 a = mkd(fv[0], fv[1], fv[2]), b = mkd(fv[3], fv[4], fv[5]), c = mkd(fv[6], fv[7], fv[8]);
   float4 nn = P.fn[f];
   d3 n = mkd(nn.x, nn.y, nn.z);
   double lo[3], hi[3];
@@ -675,6 +677,7 @@ __global__ void k_band_offsets(const int32_t* __restrict__ first_slot, const int
 struct SignArgs {
   const float* V;
   const int32_t* T;
+  const float* fv;  // corner positions in face order
   const float4* fn;
   const int4* edges;
   const int32_t* face_edges;
@@ -723,8 +726,9 @@ __device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned 
   if (id < P.nf) {
     const int64_t f = id;
     float wt[3];
-    int r = closest_triangle(mk(0.f, 0.f, 0.f), rel(P.V, P.T[3 * f], c), rel(P.V, P.T[3 * f + 1], c),
-                             rel(P.V, P.T[3 * f + 2], c), qq, wt);
+    const float* fv = P.fv + 9 * f;
+    int r = closest_triangle(mk(0.f, 0.f, 0.f), tof(mkd(fv[0], fv[1], fv[2]) - c), tof(mkd(fv[3], fv[4], fv[5]) - c),
+                             tof(mkd(fv[6], fv[7], fv[8]) - c), qq, wt);
     if (r == 0) N = xyz(P.fn[f]);
     else if (r <= 3) {
       int4 E = P.edges[P.face_edges[3 * f + r - 1]];
@@ -846,6 +850,7 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   ScanArgs A;
   A.V = f->verts;
   A.T = f->tris_g;
+  A.fv = f->face_v;
   A.fn = f->face_n;
   A.edges = f->edges;
   A.ecls = f->edge_cls;
@@ -939,6 +944,7 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
     SignArgs S;
     S.V = f->verts;
     S.T = f->tris_g;
+    S.fv = f->face_v;
     S.fn = f->face_n;
     S.edges = f->edges;
     S.face_edges = f->face_edges;

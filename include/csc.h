@@ -172,6 +172,23 @@ int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, 
                      int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream);
 
 /*
+ * Interior fill of a dense field (Section 11.3): the band leaves the cells of the
+ * solid's interior farther than band_cells*h from the surface at +infinity, a
+ * second zero crossing; this sets them to -infinity. dense_d: the float32
+ * [n[2]][n[1]][n[0]] grid that csc_scan_convert wrote for this handle (band
+ * values, +infinity elsewhere), modified in place on `stream` (queued after the
+ * scan on the same stream). Along each z column an unset cell takes the side
+ * (sign) of the nearest band cell before it in the column, or of the first one
+ * after it; a column with no band cell stays +infinity. Exact for a closed
+ * surface when band_cells >= 1/2 (a column cannot cross the surface between two
+ * cell centres without passing a band cell); surfaces cut by the grid boundary
+ * are handled as long as every z column that meets the solid meets the band.
+ * Single-mesh handles only. Errors: INVALID_ARG (null, not built, batched
+ * handle), HIP_ERROR.
+ */
+int csc_interior_fill(const csc_features* f, float* dense_d, void* stream);
+
+/*
  * Batched scan conversion (as csc_scan_convert for every mesh of a batched
  * handle, in one set of launches, with no host synchronisation). The band of
  * mesh m is entries [band_off_d[m], band_off_d[m+1]) of sdf_d / feat_d / cell_d,
@@ -221,7 +238,7 @@ int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_b
  * Per-stage timing with HIP events recorded on the stream of each call (stages:
  * 0 build_features, 1 init_keys, 2 scan_faces, 3 scan_edges, 4 scan_vertices,
  * 5 brick_count, 6 sign, 7 backward, 8 scan_faces_big, 9 scan_edges_big,
- * 10 scan_vertices_big; stages 2-4 time the one-thread-per-polyhedron launch of
+ * 10 scan_vertices_big, 11 interior_fill; stages 2-4 time the one-thread-per-polyhedron launch of
  * each kind and 8-10 the wave-per-polyhedron launch over its overflow list,
  * every other stage one launch or the whole build). While enabled, every call records a pair
  * of events around each stage; csc_timing_read waits for the recorded events and

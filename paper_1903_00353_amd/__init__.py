@@ -61,10 +61,10 @@ EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspac
            "csc_sdf_backward", "csc_features_free", "csc_error_string", "csc_last_hip_error",
            "csc_classify_edge", "csc_classify_vertex", "csc_scan_convert_count", "csc_timing_enable",
            "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name", "csc_build_features_batched",
-           "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched"]
+           "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched", "csc_interior_fill"]
 CSC_BUILD_NO_SYNC = 1
 CSC_BUILD_GRAPH_SAFE = 2
-N_STAGES = 11
+N_STAGES = 12
 
 _lib = None
 
@@ -102,6 +102,8 @@ def lib():
     L.csc_build_features_batched.restype = C.c_int
     L.csc_build_features_batched.argtypes = [P, P, P, P, C.POINTER(csc_grid), C.c_int32, C.POINTER(csc_options),
                                              C.c_int32, P, C.POINTER(C.c_void_p)]
+    L.csc_interior_fill.restype = C.c_int
+    L.csc_interior_fill.argtypes = [P, P, P]
     L.csc_features_sync.restype = C.c_int
     L.csc_features_sync.argtypes = [P, P]
     L.csc_scan_convert_batched.restype = C.c_int
@@ -444,14 +446,25 @@ def csc_classify_vertex(v, ring, options=None):
     return int(bits), ax, float(ct.value)
 
 
-def sdf(verts, tris, grid, options=None, dense=False):
-    """Narrow-band SDF of one mesh: returns (sdf, feat, cell[, dense]) device tensors."""
+def csc_interior_fill(f: Features, dense, stream=None):
+    """Set the off-band cells inside the solid of a dense field written by
+    csc_scan_convert to -inf, in place."""
+    _check(lib().csc_interior_fill(f.handle, _ptr(dense), _stream(stream)), "csc_interior_fill")
+    return dense
+
+
+def sdf(verts, tris, grid, options=None, dense=False, fill_interior=False):
+    """Narrow-band SDF of one mesh: returns (sdf, feat, cell[, dense]) device tensors;
+    with fill_interior the dense field holds -inf in the solid's interior beyond the band."""
     import torch
     f = csc_build_features(verts, tris, grid, options)
     d = None
-    if dense:
+    if dense or fill_interior:
+        dense = True
         d = torch.empty(int(grid.n[2]) * int(grid.n[1]) * int(grid.n[0]), dtype=torch.float32, device=verts.device)
     band = csc_scan_convert(f, dense=d)
+    if fill_interior:
+        csc_interior_fill(f, d)
     out = (band.sdf.clone(), band.feat.clone(), band.cell.clone())
     f.free()
     return out + ((d.view(int(grid.n[2]), int(grid.n[1]), int(grid.n[0])),) if dense else ())

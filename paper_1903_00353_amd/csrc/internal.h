@@ -77,7 +77,7 @@ int check_device();          // CSC_OK or CSC_UNSUPPORTED_DEVICE / CSC_HIP_ERROR
 // timed stages (csc_timing_*)
 enum {
   TS_BUILD = 0, TS_INIT, TS_SCAN_FACE, TS_SCAN_EDGE, TS_SCAN_VERT, TS_COUNT, TS_SIGN, TS_BACKWARD,
-  TS_SCAN_FACE_BIG, TS_SCAN_EDGE_BIG, TS_SCAN_VERT_BIG, N_STAGES
+  TS_SCAN_FACE_BIG, TS_SCAN_EDGE_BIG, TS_SCAN_VERT_BIG, TS_FILL, N_STAGES
 };
 
 // Records a pair of events around its scope on stream s when timing is enabled

@@ -16,7 +16,8 @@ double g_ms[csc::N_STAGES];
 int64_t g_calls[csc::N_STAGES];
 const char* g_names[csc::N_STAGES] = {"build_features", "init_keys",      "scan_faces",     "scan_edges",
                                       "scan_vertices",  "brick_count",    "sign",           "backward",
-                                      "scan_faces_big", "scan_edges_big", "scan_vertices_big"};
+                                      "scan_faces_big", "scan_edges_big", "scan_vertices_big",
+                                      "interior_fill"};
 
 void drain_locked() {
   for (Rec& r : g_pending) {

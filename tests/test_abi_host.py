@@ -90,6 +90,7 @@ def test_null_handle_calls():
     assert L.csc_sdf_backward(None, None, None, None, 0, None, None, None, None) == 1
     assert L.csc_scan_convert_count(None, None, 0, None, None) == 1
     assert L.csc_features_info(None, None) == 1
+    assert L.csc_interior_fill(None, None, None) == 1
     L.csc_features_free(None)
 
 
@@ -97,7 +98,8 @@ def test_timing_api_without_device():
     P.csc_timing_reset()
     t = P.csc_timing_read()
     assert list(t) == ["build_features", "init_keys", "scan_faces", "scan_edges", "scan_vertices", "brick_count",
-                       "sign", "backward", "scan_faces_big", "scan_edges_big", "scan_vertices_big"]
+                       "sign", "backward", "scan_faces_big", "scan_edges_big", "scan_vertices_big",
+                       "interior_fill"]
     assert all(v == (0.0, 0) for v in t.values())
 
 

@@ -24,13 +24,19 @@ __global__ __launch_bounds__(256) void k_interior_fill(float* dense, int n0, int
   const float inf = __builtin_inff();
   int first = -1;       // first band cell of the column
   bool inside = false;  // side of the last band cell seen
-  for (int k = 0; k < n2; k++) {
-    const float v = p[k * plane];
-    if (v != inf) {
-      inside = signbit(v);
-      if (first < 0) first = k;
-    } else if (inside) {
-      p[k * plane] = -inf;
+  constexpr int U = 8;  // z steps loaded together
+  for (int k0 = 0; k0 < n2; k0 += U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) v[u] = k0 + u < n2 ? p[(k0 + u) * plane] : inf;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (v[u] != inf) {
+        inside = signbit(v[u]);
+        if (first < 0) first = k0 + u;
+      } else if (inside && k0 + u < n2) {
+        p[(k0 + u) * plane] = -inf;
+      }
     }
   }
   if (first > 0 && signbit(p[first * plane])) {  // the column starts inside the solid

@@ -883,7 +883,7 @@ void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s) {
     k_scan_small<KIND><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
   }
   StageTimer t(stage_big, s);
-  k_scan_big<KIND><<<PERSIST_BLOCKS, 64, 0, s>>>(A);
+  k_scan_big<KIND><<<4 * PERSIST_BLOCKS, 64, 0, s>>>(A);  // 8 wavefronts per SIMD
 }
 
 // key initialisation and the scan launches of the three kinds; counters

@@ -94,6 +94,20 @@ def _icosahedron():
     return v, f
 
 
+def bipyramid(n: int = 24, radius: float = 0.3, height: float = 0.25, twist: float = 0.1, centre=CENTRE):
+    """Two cones on an n-gon: the two apexes have n incident triangles each (fans of
+    high degree); the ring is rotated by ``twist`` radians about z and tilted
+    slightly so that no face is axis-aligned."""
+    k = np.arange(n)
+    a = 2.0 * np.pi * k / n + twist
+    ring = np.stack([radius * np.cos(a), radius * np.sin(a), 0.02 * np.sin(3 * a)], 1)
+    v = np.concatenate([ring, [[0.0, 0.0, height], [0.0, 0.0, -height]]]) + np.asarray(centre, dtype=np.float64)
+    top, bot = n, n + 1
+    nxt = (k + 1) % n
+    tris = np.concatenate([np.stack([k, nxt, np.full(n, top)], 1), np.stack([nxt, k, np.full(n, bot)], 1)])
+    return _finish(v, tris)
+
+
 def unit_icosphere(level: int):
     """Unit-sphere directions and faces of an icosahedron subdivided ``level`` times."""
     v, f = _icosahedron()

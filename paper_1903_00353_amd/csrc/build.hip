@@ -147,7 +147,7 @@ __global__ void k_sort_segments(const int32_t* __restrict__ off, int32_t* vc, in
 }
 
 constexpr int VK_THREADS = 128;
-constexpr int VK_MAXD = 16;  // fans up to this degree are staged in LDS
+constexpr int VK_MAXD = 12;  // fans up to this degree are staged in LDS (18 KB per block: 4 wavefronts per SIMD)
 
 // Per vertex u, over its fan of corners (staged in LDS):
 //  * twins: the out-edge u -> w of corner c (half-edge c) pairs with the unique
@@ -303,8 +303,7 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
   for (int z = lo[2]; z <= hi[2]; z++)
     for (int y = lo[1]; y <= hi[1]; y++)
       for (int x = lo[0]; x <= hi[0]; x++) {
-        int32_t* p = &flag[brick_pos(g, x, y, z)];
-        if (*p == 0) *p = 1;
+        flag[brick_pos(g, x, y, z)] = 1;  // plain stores: no read to wait for
       }
 }
 

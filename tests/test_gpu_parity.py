@@ -92,6 +92,16 @@ def test_ragged_offset_grid():
     assert_parity(rep)
 
 
+@pytest.mark.parametrize("n", [24, 40])
+def test_high_degree_fans(n):
+    """Apexes with more incident triangles than the vertex pass stages in LDS."""
+    v, f = meshgen.bipyramid(n)
+    g = Grid.unit(64, 3)
+    rep, feats, *_ = check(v, f, g)
+    assert rep["n_oracle"] > 1000
+    assert_parity(rep)
+
+
 def test_empty_and_tiny_grids():
     v, f = meshgen.icosphere(2, 0.3)
     g = Grid(n=(16, 16, 16), h=1 / 64, band=3, origin=(5.0, 5.0, 5.0))

@@ -147,21 +147,26 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
       owner = owner && !same_next;
     }
     if (owner) {
+      // first probe of all three vertices at once (independent LDS round trips),
+      // then linear probing only where the home slot holds another vertex
+      unsigned h[3];
+      int old[3];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        h[k] = ((unsigned)vid[k] * 2654435761u) >> BW_HASH_SHIFT;
+        old[k] = vid[k] >= 0 ? atomicCAS(&s_key[h[k]], -1, vid[k]) : vid[k];
+      }
+#pragma unroll
       for (int k = 0; k < 3; k++) {
         if (vid[k] < 0) continue;
-        unsigned h = ((unsigned)vid[k] * 2654435761u) >> BW_HASH_SHIFT;
-        while (true) {
-          const int old = atomicCAS(&s_key[h], -1, vid[k]);
-          if (old == -1) {
-            atomicAdd(&s_used, 1);
-            break;
-          }
-          if (old == vid[k]) break;
-          h = (h + 1) & (BW_SLOTS - 1);
+        while (old[k] != -1 && old[k] != vid[k]) {
+          h[k] = (h[k] + 1) & (BW_SLOTS - 1);
+          old[k] = atomicCAS(&s_key[h[k]], -1, vid[k]);
         }
-        atomicAdd(&s_acc[0][h], con[k].x);
-        atomicAdd(&s_acc[1][h], con[k].y);
-        atomicAdd(&s_acc[2][h], con[k].z);
+        if (old[k] == -1) atomicAdd(&s_used, 1);
+        atomicAdd(&s_acc[0][h[k]], con[k].x);
+        atomicAdd(&s_acc[1][h[k]], con[k].y);
+        atomicAdd(&s_acc[2][h[k]], con[k].z);
       }
     }
     __syncthreads();

@@ -436,6 +436,7 @@ def bench_single(args):
         ms_fwd, med_fwd, min_fwd = timed_steps(forward, args.steps)
         res["fwd"] = {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd, "median": med_fwd, "min": min_fwd}
         res["interior_fill"] = bench_interior_fill(P, feats, ws, out, g, max(3, args.steps // 4))
+        res["weld"] = bench_weld(P, verts, tris, 5)
         if not args.no_cpu_baseline:
             res["cpu_baseline"] = cpu_baseline(v, f, g, args.cpu_budget)
     print(json.dumps(res))
@@ -458,6 +459,25 @@ def summarize_trace(args):
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / tot * 100:.1f} |")
     print("\n".join(lines))
+
+
+def bench_weld(P, verts, tris, reps):
+    """Triangle-soup ingestion: the workload mesh flattened to a soup (one
+    position per corner, as an STL file lists it) and welded back into an
+    indexed mesh, device resident; wall clock per call (the call synchronises
+    and allocates its temporaries)."""
+    import torch
+    soup = verts[tris.long()].contiguous()
+    vw, tw = P.csc_weld_soup(soup)
+    ok = vw.shape[0] == verts.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.csc_weld_soup(soup)
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    n = 3 * int(tris.shape[0])
+    return {"ms": ms, "faces": int(tris.shape[0]), "corners": n, "vertices": int(vw.shape[0]),
+            "vertices_recovered": bool(ok), "corners_per_s": n / (ms * 1e-3)}
 
 
 def bench_interior_fill(P, feats, ws, out, g, reps):

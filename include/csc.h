@@ -172,6 +172,27 @@ int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, 
                      int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream);
 
 /*
+ * Triangle-soup ingestion (Section 7, Sections 7.1-7.2): weld the corners of an
+ * STL-style soup, where every triangle carries its own three corner positions,
+ * into an indexed mesh. Corners with equal positions (exact float equality, -0
+ * equal to +0) become one vertex; vertices are numbered in order of first
+ * appearance in the soup (corner order 3f + j), and tris_d[f][j] is the vertex
+ * of corner j of triangle f, so triangle order and corner order (orientation)
+ * are kept. Equal positions are grouped by sorting on the exact coordinates (not
+ * on coarse Morton codes), so no group needs a sequential pass.
+ *
+ * soup_d: float32 [nf][3][3] device. verts_d: float32 [3*nf][3] device (room for
+ * every corner being distinct); the first *nv rows are written. tris_d: int32
+ * [nf][3] device. nv: host pointer receiving the vertex count. Allocates
+ * temporaries (44 bytes per corner plus the radix sort's storage) with
+ * hipMallocAsync on `stream` and synchronises it before returning. Triangles that collapse (two corners at
+ * one position) are not removed here; csc_build_features rejects them.
+ * Errors: INVALID_ARG (null, nf <= 0, 3*nf >= 2^31, non-finite coordinate),
+ * OUT_OF_MEMORY, UNSUPPORTED_DEVICE, HIP_ERROR.
+ */
+int csc_weld_soup(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris_d, int64_t* nv, void* stream);
+
+/*
  * Interior fill of a dense field (Section 11.3): the band leaves the cells of the
  * solid's interior farther than band_cells*h from the surface at +infinity, a
  * second zero crossing; this sets them to -infinity. dense_d: the float32

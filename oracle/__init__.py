@@ -17,6 +17,10 @@ float32 mesh arrays from ``meshgen``.
     cell's closest feature held fixed;
   * the generalised winding number (an independent inside/outside test).
 
+``weld_soup`` (NumPy) turns a triangle soup into an indexed mesh by exact
+equality of corner positions (Section 7), vertices numbered in order of first
+appearance.
+
 ``allpairs_distance`` is a second, literal all-pairs implementation in NumPy
 using a different formulation of the point-triangle distance (projection onto
 the plane, else the nearest of the three edges), used to pin the C code.
@@ -250,3 +254,22 @@ def allpairs_distance(verts, tris, points, chunk=4096):
         d2 = np.where(inside, dplane2, de)
         out[s:s + chunk] = np.sqrt(d2.min(axis=1))
     return out
+
+
+def weld_soup(soup):
+    """Indexed mesh of a triangle soup (Section 7: every STL triangle lists its
+    own corners; equal positions are one vertex). soup: [F, 3, 3] float32.
+    Positions compare by float value (-0 == +0). Vertices are numbered in order
+    of first appearance in corner order 3f + j; returns (verts [V, 3] float32
+    holding each vertex's first corner as given, tris [F, 3] int32)."""
+    c = np.asarray(soup, dtype=np.float32).reshape(-1, 3)
+    key = np.where(c == 0, np.float32(0), c)                      # -0 -> +0
+    _, first, inverse = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    inverse = inverse.reshape(-1)
+    order = np.argsort(first, kind="stable")                      # groups by first appearance
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    tris = rank[inverse].astype(np.int32).reshape(-1, 3)
+    verts = c[first[order]].copy()
+    return verts, tris
+

@@ -61,7 +61,8 @@ EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspac
            "csc_sdf_backward", "csc_features_free", "csc_error_string", "csc_last_hip_error",
            "csc_classify_edge", "csc_classify_vertex", "csc_scan_convert_count", "csc_timing_enable",
            "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name", "csc_build_features_batched",
-           "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched", "csc_interior_fill"]
+           "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched", "csc_interior_fill",
+           "csc_weld_soup"]
 CSC_BUILD_NO_SYNC = 1
 CSC_BUILD_GRAPH_SAFE = 2
 N_STAGES = 12
@@ -102,6 +103,8 @@ def lib():
     L.csc_build_features_batched.restype = C.c_int
     L.csc_build_features_batched.argtypes = [P, P, P, P, C.POINTER(csc_grid), C.c_int32, C.POINTER(csc_options),
                                              C.c_int32, P, C.POINTER(C.c_void_p)]
+    L.csc_weld_soup.restype = C.c_int
+    L.csc_weld_soup.argtypes = [P, C.c_int64, P, P, C.POINTER(C.c_int64), P]
     L.csc_interior_fill.restype = C.c_int
     L.csc_interior_fill.argtypes = [P, P, P]
     L.csc_features_sync.restype = C.c_int
@@ -444,6 +447,22 @@ def csc_classify_vertex(v, ring, options=None):
     bits = lib().csc_classify_vertex(v.ctypes.data_as(C.c_void_p), ring.ctypes.data_as(C.c_void_p), ring.shape[0],
                                      C.byref(opt), ax.ctypes.data_as(C.c_void_p), C.byref(ct))
     return int(bits), ax, float(ct.value)
+
+
+def csc_weld_soup(soup, stream=None):
+    """Indexed mesh from a triangle soup: soup float32 [F, 3, 3] (or [3F, 3]) on the
+    device -> (verts float32 [V, 3], tris int32 [F, 3]); synchronises."""
+    import torch
+    soup = soup.contiguous().reshape(-1, 3, 3)
+    if soup.dtype != torch.float32:
+        raise TypeError("soup must be float32")
+    nf = int(soup.shape[0])
+    verts = torch.empty(3 * nf, 3, dtype=torch.float32, device=soup.device)
+    tris = torch.empty(nf, 3, dtype=torch.int32, device=soup.device)
+    nv = C.c_int64(0)
+    _check(lib().csc_weld_soup(_ptr(soup), nf, _ptr(verts), _ptr(tris), C.byref(nv), _stream(stream)),
+           "csc_weld_soup")
+    return verts[: nv.value], tris
 
 
 def csc_interior_fill(f: Features, dense, stream=None):

@@ -286,3 +286,48 @@ def test_feature_distance_every_region():
         tt = np.clip((P - a) @ (b - a) / ((b - a) @ (b - a)), 0, 1)
         ref = np.linalg.norm(P - (a + tt[:, None] * (b - a)), axis=1)
         assert np.max(np.abs(d - ref)) <= 1e-12, e
+
+
+# ---------------------------------------------------------------- soup welding
+def _weld_brute(soup):
+    """Pairwise definition: corner i is vertex k where k counts the distinct
+    positions among corners 0..i (first appearance), equality by value."""
+    c = np.asarray(soup, dtype=np.float32).reshape(-1, 3).astype(np.float64)
+    ids, reps = [], []
+    for i in range(c.shape[0]):
+        for k, r in enumerate(reps):
+            if np.all(c[r] == c[i]):
+                ids.append(k)
+                break
+        else:
+            ids.append(len(reps))
+            reps.append(i)
+    return c[reps].astype(np.float32), np.array(ids, dtype=np.int32).reshape(-1, 3)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_weld_matches_pairwise_definition(seed):
+    rng = np.random.default_rng(seed)
+    pool = rng.integers(-3, 4, size=(15, 3)).astype(np.float32) * np.float32(0.25)
+    pool[0] = [0.0, -0.0, 0.0]                   # -0 and +0 are one position
+    pool[1] = [-0.0, 0.0, -0.0]
+    soup = pool[rng.integers(0, 15, size=(40, 3))]
+    v, t = oracle.weld_soup(soup)
+    vb, tb = _weld_brute(soup)
+    assert np.array_equal(t, tb)
+    assert np.array_equal(v, vb)
+    assert np.all(v[t] == soup)                  # every corner maps to its own position
+
+
+def test_weld_inverts_flattening():
+    """A mesh flattened to a soup welds back to itself when its vertices first
+    appear in index order (icosphere: vertex ids grow with face order)."""
+    v, f = meshgen.cube()
+    soup = v[f]
+    vw, tw = oracle.weld_soup(soup)
+    assert vw.shape == v.shape and tw.shape == f.shape
+    # same mesh up to renumbering: positions of every corner agree
+    assert np.array_equal(vw[tw], v[f])
+    first = np.unique(f.reshape(-1), return_index=True)[1]
+    perm = f.reshape(-1)[np.sort(first)]         # original ids in order of first appearance
+    assert np.array_equal(vw, v[perm])

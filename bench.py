@@ -437,6 +437,7 @@ def bench_single(args):
         res["fwd"] = {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd, "median": med_fwd, "min": min_fwd}
         res["interior_fill"] = bench_interior_fill(P, feats, ws, out, g, max(3, args.steps // 4))
         res["weld"] = bench_weld(P, verts, tris, 5)
+        res["ablation_per_cell_scan"] = bench_per_cell(P, verts, tris, g, schedule, ws, out, max(3, args.steps // 4))
         if not args.no_cpu_baseline:
             res["cpu_baseline"] = cpu_baseline(v, f, g, args.cpu_budget)
     print(json.dumps(res))
@@ -459,6 +460,25 @@ def summarize_trace(args):
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / tot * 100:.1f} |")
     print("\n".join(lines))
+
+
+def bench_per_cell(P, verts, tris, g, schedule, ws, out, reps):
+    """Ablation: the forward pass with every box cell tested by itself (Alg. 2 as
+    printed, scan_mode 1) instead of row intervals; per-stage times."""
+    opts = P.make_options(small_rows=schedule, scan_mode=1)
+    f1 = P.csc_build_features(verts, tris, g, opts)
+    nbytes, _ = P.csc_scan_convert_workspace(f1)
+    if nbytes > ws.numel():
+        return None
+
+    def fwd():
+        P.csc_build_features(verts, tris, g, opts, reuse=f1)
+        P.csc_scan_convert(f1, ws, out, sync_count=False)
+
+    fwd()
+    avg, ms = stage_averages(fwd, reps)
+    f1.free()
+    return {"fwd_ms": ms, "stages_ms": {k: round(v, 4) for k, v in avg.items() if k.startswith("scan_")}}
 
 
 def bench_weld(P, verts, tris, reps):

@@ -75,6 +75,10 @@ typedef struct csc_options {
                                rest share the rows of their wavefront. 0 = 32; values above 2^24
                                act as 2^24. Only the speed depends on it (see the autotuner in the
                                binding). */
+  int32_t scan_mode;        /* 0 (default): each row of a polyhedron's box is intersected with its
+                               half-spaces at once; 1: every cell of the box is tested by itself
+                               (Alg. 2 as printed), an ablation that costs more and gives the same
+                               field up to ties between features */
 } csc_options;
 
 typedef struct csc_features csc_features; /* opaque, library-owned, device resident */

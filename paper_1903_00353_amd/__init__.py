@@ -43,7 +43,8 @@ class csc_grid(C.Structure):
 
 class csc_options(C.Structure):
     _fields_ = [("eps_rel", C.c_float), ("ruff_mode", C.c_int32), ("saddle_mode", C.c_int32),
-                ("force_both_sides", C.c_int32), ("small_rows", C.c_int32 * 3)]
+                ("force_both_sides", C.c_int32), ("small_rows", C.c_int32 * 3),
+                ("scan_mode", C.c_int32)]
 
 
 class csc_feature_info(C.Structure):
@@ -147,10 +148,12 @@ def make_grid(grid) -> csc_grid:
     return g
 
 
-def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0, small_rows=(0, 0, 0)) -> csc_options:
+def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0, small_rows=(0, 0, 0),
+                 scan_mode=0) -> csc_options:
     o = csc_options(float(eps_rel), int(ruff_mode), int(saddle_mode), int(force_both_sides))
     for k in range(3):
         o.small_rows[k] = int(small_rows[k])
+    o.scan_mode = int(scan_mode)
     return o
 
 

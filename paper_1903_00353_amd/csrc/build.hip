@@ -474,7 +474,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   if (!verts_d || !tris_d || !nv || !nf || !grids || !out || n_meshes <= 0) return CSC_INVALID_ARG;
   csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}};
   if (opt) o = *opt;
-  if (!(o.eps_rel >= 0) || !(o.eps_rel < 0.5f) || o.ruff_mode < 0 || o.ruff_mode > 1 || o.saddle_mode < 0 ||
+  if (!(o.eps_rel >= 0) || !(o.eps_rel < 0.5f) || o.ruff_mode < 0 || o.ruff_mode > 1 || o.scan_mode < 0 || o.scan_mode > 1 || o.saddle_mode < 0 ||
       o.saddle_mode > 2)
     return CSC_INVALID_ARG;
   for (int k = 0; k < 3; k++) {

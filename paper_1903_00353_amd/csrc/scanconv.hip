@@ -45,6 +45,7 @@ struct ScanArgs {
   int64_t cap;                  // bricks the key store holds
   int64_t nf, ne, n_items;      // totals; n_items = launch bound
   int32_t small_rows;           // more rows: one wavefront per polyhedron
+  int32_t per_cell;             // 1: test every box cell by itself (Alg. 2) instead of row intervals
 };
 
 // Packed key of a candidate: float bits of |d| in the high word; the low word
@@ -458,10 +459,11 @@ __device__ inline int wave_incl_sum(int v) {
   return v;
 }
 
-// cells [t0, t1] of row (du, dv) of the polyhedron held by lane L, its row
-// coefficients fetched by lane permutation; called by all lanes together
+// the row coefficients of the polyhedron held by lane L, fetched by lane
+// permutation (with the row-axis slopes when each cell is tested on its own);
+// called by all lanes together
 template <int KIND>
-__device__ inline bool row_range_of(const Rows& r, int L, int du, int dv, int& t0, int& t1) {
+__device__ inline Rows rows_of(const Rows& r, int L, bool per_cell) {
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
   Rows o;
 #pragma unroll
@@ -470,6 +472,10 @@ __device__ inline bool row_range_of(const Rows& r, int L, int du, int dv, int& t
     o.su[i] = __shfl(r.su[i], L, 64);
     o.sv[i] = __shfl(r.sv[i], L, 64);
     o.k[i] = __shfl(r.k[i], L, 64);
+  }
+  if (per_cell) {
+#pragma unroll
+    for (int i = 0; i < NPL; i++) o.sl[i] = __shfl(r.sl[i], L, 64);
   }
   o.nt = __shfl(r.nt, L, 64);
   if constexpr (KIND == KIND_VERT) {
@@ -480,7 +486,22 @@ __device__ inline bool row_range_of(const Rows& r, int L, int du, int dv, int& t
     o.hf = __shfl(r.hf, L, 64);
     o.ihf = __shfl(r.ihf, L, 64);
   }
-  return row_range<KIND>(o, du, dv, t0, t1);
+  return o;
+}
+
+// Alg. 2 for one cell: every half-space with slack (and, for vertices, the
+// ball of radius band*h); the per-cell alternative to the row interval
+template <int KIND>
+__device__ inline bool cell_in(const Rows& o, int t, int du, int dv) {
+  constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
+  bool in = true;
+#pragma unroll
+  for (int i = 0; i < NPL; i++) in = in && o.sl[i] * t + o.su[i] * du + o.sv[i] * dv + o.k[i] >= 0.f;
+  if constexpr (KIND == KIND_VERT) {
+    const float qt = t * o.hf - o.A[0], qu = du * o.hf - o.A[1], qv = dv * o.hf - o.A[2];
+    in = in && qt * qt + qu * qu + qv * qv <= o.R2;
+  }
+  return in;
 }
 
 // The rows of the wavefront's polyhedra (lane l holds `rows` rows of its own
@@ -512,7 +533,14 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
     const int nud = nuL > 0 ? nuL : 1;  // past the last row L may hold no polyhedron
     const int dv = g < total ? rloc / nud : 0, du = g < total ? rloc - dv * nud : 0;
     int t = 0, t1 = -1;
-    if (!row_range_of<KIND>(r, L, du, dv, t, t1) || g >= total) t1 = -1;
+    const Rows o = rows_of<KIND>(r, L, P.per_cell);
+    if (P.per_cell) {  // every cell of the row, each tested by itself below
+      t = 0;
+      t1 = o.nt - 1;
+    } else if (!row_range<KIND>(o, du, dv, t, t1)) {
+      t1 = -1;
+    }
+    if (g >= total) t1 = -1;
     // vertices: the owner's cone for the per-cell discriminant
     [[maybe_unused]] f3 cg = mk(0.f, 0.f, 0.f), cax = mk(0.f, 0.f, 0.f);
     [[maybe_unused]] float cct = -2.f, chf = 0.f, ceps = 0.f;
@@ -530,9 +558,9 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
     while (true) {
       const bool has = t <= t1;
       if (__ballot(has) == 0) break;
-      bool push = has;
+      bool push = has && (!P.per_cell || cell_in<KIND>(o, t, du, dv));
       if constexpr (KIND == KIND_VERT) {  // cone discriminant with slack (Eq. 10)
-        if (has && cct > -1.f) {
+        if (push && cct > -1.f) {
           const int di = cra == 0 ? t : (cua == 0 ? du : dv);
           const int dj = cra == 1 ? t : (cua == 1 ? du : dv);
           const int dk = cra == 2 ? t : (cua == 2 ? du : dv);
@@ -872,6 +900,7 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.ne = f->ne;
   A.n_items = 0;
   A.small_rows = 32;
+  A.per_cell = 0;
   return A;
 }
 
@@ -900,14 +929,17 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.counter = counters;
   A.n_items = f->nf;
   A.small_rows = f->opt.small_rows[0];
+  A.per_cell = f->opt.scan_mode == 1;
   launch_kind<KIND_FACE>(A, TS_SCAN_FACE, TS_SCAN_FACE_BIG, s);
   A.small_rows = f->opt.small_rows[1];
+  A.per_cell = f->opt.scan_mode == 1;
   A.items = f->epoly;
   A.n_items = 2 * f->ne;
   A.n_items_d = &f->d_stats[ST_NEPOLY];
   A.counter = counters ? counters + 1 : nullptr;
   launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, TS_SCAN_EDGE_BIG, s);
   A.small_rows = f->opt.small_rows[2];
+  A.per_cell = f->opt.scan_mode == 1;
   A.items = f->vpoly;
   A.n_items = 2 * f->nv;
   A.n_items_d = &f->d_stats[ST_NVPOLY];

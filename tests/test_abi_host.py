@@ -45,7 +45,8 @@ def _grid(n=(8, 8, 8), h=0.125, band=2.0, origin=(0.0, 0.0, 0.0)):
 
 
 @pytest.mark.parametrize("case", ["null", "nv0", "nf0", "odd_faces", "grid_n", "grid_h", "band", "origin_nan",
-                                  "too_many_cells", "long_axis", "bad_option"])
+                                  "too_many_cells", "long_axis", "bad_option",
+                                  "bad_scan_mode"])
 def test_host_argument_checks(case):
     """Checked on the host before any device call: these never need a GPU."""
     L = P.lib()
@@ -76,6 +77,8 @@ def test_host_argument_checks(case):
         g.n[0], g.n[1], g.n[2] = 65536, 4, 4
     elif case == "bad_option":
         opt.saddle_mode = 7
+    elif case == "bad_scan_mode":
+        opt.scan_mode = 2
     code = L.csc_build_features(v, nv, t, nf, C.byref(g), C.byref(opt), None, C.byref(out))
     expect = {"odd_faces": 2, "too_many_cells": 5, "long_axis": 5}.get(case, 1)
     assert code == expect

@@ -102,6 +102,34 @@ def test_high_degree_fans(n):
     assert_parity(rep)
 
 
+def test_ruff_vertices(configs):
+    """A strongly jittered sphere (radial noise of about one edge length, still an
+    embedded surface) has ruff vertices (Section 3.3): some incident normal
+    points away from the pseudonormal. The default extrudes hemispheres there
+    (Section 4.1.3, proven complete) and must match the oracle. The paper's
+    positive-normal cone (ruff_mode 1, Section 3.3: "sufficient in practice") is
+    run as an ablation and its outcome printed."""
+    v, f = meshgen.icosphere(3, 0.35, 0.04, seed=0)
+    g = Grid.unit(96, 3)
+    rep, feats, *_ = check(v, f, g)
+    assert feats.info()["vertices_ruff"] > 0
+    assert_parity(rep)
+    rep1, *_ = check(v, f, g, options=P.make_options(ruff_mode=1))
+    print("ruff_mode 1 (cone):", {k: rep1[k] for k in ("missing", "extra", "max_err_d")}, flush=True)
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_per_cell_scan_ablation(configs, cfg):
+    """Alg. 2 as printed (every box cell tested by itself, scan_mode 1) gives the
+    same field as the row intervals: parity against the oracle."""
+    name, meshes, grids = configs(cfg)
+    v, f = meshes[0]
+    k = int(grids[0].n[2]) // 2
+    rep, *_ = check(v, f, grids[0], options=P.make_options(scan_mode=1), k_range=(k - 24, k + 24))
+    assert rep["n_oracle"] > 1000
+    assert_parity(rep)
+
+
 def test_empty_and_tiny_grids():
     v, f = meshgen.icosphere(2, 0.3)
     g = Grid(n=(16, 16, 16), h=1 / 64, band=3, origin=(5.0, 5.0, 5.0))

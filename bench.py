@@ -282,6 +282,14 @@ def bench_batch(args):
     res["per_mesh"] = {"value": M_per / (ms_per_mesh * 1e-3), "ms_per_step": ms_per_mesh, "median": med_pm,
                        "min": min_pm, "band_size": M_per}
     res["speedup_batched_vs_per_mesh"] = ms_per_mesh / ms_graph
+    # ablation: forward with every box cell tested by itself (Alg. 2 as printed)
+    B2 = P.Batch(meshes, grids, options=P.make_options(small_rows=schedule, scan_mode=1), device=dev, backward=False,
+                 graph_safe=True)
+    B2.step()
+    avg2, ms2 = stage_averages(B2.step, max(3, args.steps // 4))
+    res["ablation_per_cell_scan"] = {"fwd_ms": ms2, "fwd_ms_row_intervals": ms_fwd,
+                                     "stages_ms": {k: round(v, 4) for k, v in avg2.items() if k.startswith("scan_")}}
+    del B2
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_batch(meshes, grids, args.cpu_budget)
     print(json.dumps(res))

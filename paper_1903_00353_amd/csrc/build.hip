@@ -89,6 +89,7 @@ __global__ void k_offsets(const uint32_t* __restrict__ key, int64_t nh, int64_t 
 constexpr int CC_THREADS = 1024;     // faces per block: more faces share each returning global add
 constexpr int CC_SLOTS = 4096;       // > 3 * CC_THREADS insertions: probing always ends
 constexpr int CC_HASH_SHIFT = 20;    // 32 - log2(CC_SLOTS)
+static_assert(CC_SLOTS % CC_THREADS == 0, "each thread flushes a whole number of slots");
 
 // Corner counts per vertex without library sorting (graph-capturable path): a
 // block counts its corners per vertex in an LDS hash table and reserves one range
@@ -102,24 +103,40 @@ __global__ __launch_bounds__(CC_THREADS) void k_count_corners(const int32_t* __r
   }
   __syncthreads();
   const int64_t f = blockIdx.x * (int64_t)CC_THREADS + threadIdx.x;
+  // the three corners' LDS round trips are issued together: first probes, then
+  // linear probing only where the home slot holds another vertex, then the ranks
   int hs[3] = {0, 0, 0}, rank[3] = {0, 0, 0};
   if (f < nf) {
+    int32_t v[3];
+    int old[3];
 #pragma unroll
     for (int j = 0; j < 3; j++) {
-      const int32_t v = tg[3 * f + j];
-      unsigned h = ((unsigned)v * 2654435761u) >> CC_HASH_SHIFT;
-      while (true) {
-        int old = atomicCAS(&s_key[h], -1, v);
-        if (old == -1 || old == v) break;
-        h = (h + 1) & (CC_SLOTS - 1);
-      }
-      hs[j] = (int)h;
-      rank[j] = atomicAdd(&s_cnt[h], 1);
+      v[j] = tg[3 * f + j];
+      hs[j] = (int)(((unsigned)v[j] * 2654435761u) >> CC_HASH_SHIFT);
+      old[j] = atomicCAS(&s_key[hs[j]], -1, v[j]);
     }
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      while (old[j] != -1 && old[j] != v[j]) {
+        hs[j] = (hs[j] + 1) & (CC_SLOTS - 1);
+        old[j] = atomicCAS(&s_key[hs[j]], -1, v[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; j++) rank[j] = atomicAdd(&s_cnt[hs[j]], 1);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS)
-    if (s_key[k] >= 0) s_base[k] = atomicAdd(&cnt[s_key[k]], s_cnt[k]);
+  // one returning global add per vertex present in the block; the adds of a
+  // thread's slots are issued before any result is used
+  constexpr int PER = CC_SLOTS / CC_THREADS;
+  int got[PER];
+#pragma unroll
+  for (int u = 0; u < PER; u++) {
+    const int k = threadIdx.x + u * CC_THREADS;
+    got[u] = s_key[k] >= 0 ? atomicAdd(&cnt[s_key[k]], s_cnt[k]) : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < PER; u++) s_base[threadIdx.x + u * CC_THREADS] = got[u];
   __syncthreads();
   if (f < nf) {
 #pragma unroll

@@ -274,11 +274,13 @@ __global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__
 }
 
 // Unit face normal (double precision, stored in single) and the band bricks near
-// the face: every brick holding a cell centre within band*h + eps of the face's
-// bounding box. Every polyhedron of the face, its edges and its vertices lies in
+// the face: the bricks holding a cell centre within band*h + eps of the face's
+// bounding box, less those whose centres all lie farther than that from the
+// face's plane. Every polyhedron of the face, its edges and its vertices lies in
 // that box (the face prism within band*h*|n_k| + eps of the face along each
-// axis, edge wedges and vertex cones within band*h + eps of their feature), so
-// every cell a scan can write has its brick marked.
+// axis, edge wedges and vertex cones within band*h + eps of their feature), and
+// a scan writes only cells within band*h of a feature, so every cell a scan can
+// write has its brick marked by one of the faces holding its feature.
 __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf,
                             const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float4* fn,
                             float* fv, int32_t* flag, int64_t* stats) {
@@ -317,9 +319,23 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
     lo[ax] = (int)lo_c / BRICK;
     hi[ax] = (int)hi_c / BRICK;
   }
+  // A brick is kept only if some cell centre in it can lie within r of the face's
+  // plane: a cell within band*h of an edge or vertex is that close to a face
+  // holding it, and no key is written farther out. The centres of brick (x, y, z)
+  // fill a box of half-width 3.5 h around origin + (8 x + 4) h, whose distance to
+  // the plane is at least |n.(c - a)| - 3.5 h |n|_1. The test gets 1e-3 h of slack
+  // over r against rounding; a degenerate face keeps its whole box.
+  const bool cull = l > 0;
+  const d3 un = cull ? mkd(n.x / l, n.y / l, n.z / l) : mkd(0.0, 0.0, 0.0);
+  const double ext = 3.5 * g.h * (fabs(un.x) + fabs(un.y) + fabs(un.z)), lim = r + 1e-3 * g.h;
   for (int z = lo[2]; z <= hi[2]; z++)
     for (int y = lo[1]; y <= hi[1]; y++)
       for (int x = lo[0]; x <= hi[0]; x++) {
+        if (cull) {
+          const d3 c = mkd(g.origin[0] + (8 * x + 4) * g.h, g.origin[1] + (8 * y + 4) * g.h,
+                           g.origin[2] + (8 * z + 4) * g.h);
+          if (fabs(dot(un, c - a)) - ext > lim) continue;
+        }
         flag[brick_pos(g, x, y, z)] = 1;  // plain stores: no read to wait for
       }
 }

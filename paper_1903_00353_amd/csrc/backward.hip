@@ -33,6 +33,61 @@ __device__ inline f3 relv(const float* p, d3 c) {
   return tof(mkd((double)p[0] - c.x, (double)p[1] - c.y, (double)p[2] - c.z));
 }
 
+// the per-cell inputs of one band cell; gs = 0 past the end of the run
+struct BwCell {
+  float gs, sd;
+  int32_t lin, lf;
+};
+
+__device__ inline BwCell load_cell(const BwdArgs& P, int64_t i, int64_t end) {
+  BwCell c = {0.f, 0.f, 0, 0};
+  if (i < end) {
+    c.gs = P.gsdf[i];
+    c.sd = P.sdf[i];
+    c.lin = P.cell[i];
+    c.lf = P.feat[i];
+  }
+  return c;
+}
+
+// what a thread needs of the mesh its cells belong to, kept in registers until
+// its cells reach the next mesh
+struct BwMesh {
+  double ox, oy, oz, h, inv_n0, inv_n1;
+  int n0, n1, nf, ne, f_off, e_off, v_off;
+  int64_t end;  // first band cell past this mesh
+};
+
+__device__ inline BwMesh load_mesh(const BwdArgs& P, int m) {
+  const MeshDesc& G = P.md[m];
+  BwMesh M;
+  M.ox = G.origin[0];
+  M.oy = G.origin[1];
+  M.oz = G.origin[2];
+  M.h = G.h;
+  M.n0 = G.n[0];
+  M.n1 = G.n[1];
+  M.inv_n0 = 1.0 / G.n[0];
+  M.inv_n1 = 1.0 / G.n[1];
+  M.nf = G.nf;
+  M.ne = G.ne;
+  M.f_off = G.f_off;
+  M.e_off = G.e_off;
+  M.v_off = G.v_off;
+  M.end = P.band_off ? P.band_off[m + 1] : INT64_MAX;
+  return M;
+}
+
+// floor(a / d) for 0 <= a < 2^31 and 0 < d < 2^16, with inv = 1 / d rounded: the
+// product is within one of the quotient, and the remainder puts it right
+__device__ inline int div_floor(int a, int d, double inv) {
+  int q = (int)((double)a * inv);
+  const int64_t r = (int64_t)a - (int64_t)q * d;
+  q += r >= d ? 1 : 0;
+  q -= r < 0 ? 1 : 0;
+  return q;
+}
+
 constexpr int BW_THREADS = 256;
 constexpr int BW_SLOTS = 2048;                // hash table of (vertex, 3 partial sums) per block
 constexpr int BW_HASH_SHIFT = 21;             // 32 - log2(BW_SLOTS)
@@ -65,34 +120,41 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
   if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
   int m = P.band_off ? find_segment(P.band_off, P.n_meshes + 1, c0 + threadIdx.x) : 0;
+  BwMesh M = load_mesh(P, m);
+  // the four per-cell values of the next chunk are loaded while this one is
+  // processed: only the feature's own data is waited for inside a chunk
+  BwCell nxt = load_cell(P, c0 + threadIdx.x, c1);
   for (int64_t base = c0; base < c1; base += BW_THREADS) {
     const int64_t i = base + threadIdx.x;
-    const float gs = i < c1 ? P.gsdf[i] : 0.f;
+    const BwCell cur = nxt;
+    nxt = load_cell(P, i + BW_THREADS, c1);
+    const float gs = cur.gs;
     // this cell's contribution to each vertex k of its feature: f_k * g
     int32_t vid[3] = {-1, -1, -1};
     f3 con[3] = {mk(0.f, 0.f, 0.f), mk(0.f, 0.f, 0.f), mk(0.f, 0.f, 0.f)};
     int64_t fkey = -1 - (int64_t)threadIdx.x;  // unique unless the cell contributes
     if (gs != 0.f) {
-      if (P.band_off) {
-        while (i >= P.band_off[m + 1]) m++;  // cells only move forward through the meshes
+      if (i >= M.end) {  // cells only move forward through the meshes
+        while (i >= P.band_off[m + 1]) m++;
+        M = load_mesh(P, m);
       }
-      const MeshDesc& G = P.md[m];
-      const int32_t lin = P.cell[i], lf = P.feat[i];
-      const int ci = lin % G.n[0], cj = (lin / G.n[0]) % G.n[1], ck = lin / (G.n[0] * G.n[1]);
-      const d3 c = mkd(G.origin[0] + (ci + 0.5) * G.h, G.origin[1] + (cj + 0.5) * G.h, G.origin[2] + (ck + 0.5) * G.h);
+      const int32_t lin = cur.lin, lf = cur.lf;
+      const int row = div_floor(lin, M.n0, M.inv_n0), ck = div_floor(row, M.n1, M.inv_n1);
+      const int ci = lin - row * M.n0, cj = row - ck * M.n1;
+      const d3 c = mkd(M.ox + (ci + 0.5) * M.h, M.oy + (cj + 0.5) * M.h, M.oz + (ck + 0.5) * M.h);
       const f3 zero = mk(0.f, 0.f, 0.f);
       f3 q;
       float w[3] = {0.f, 0.f, 0.f};
       int mcount;
       int32_t v3[3];
-      if (lf < G.nf) {
-        const int64_t f = (int64_t)G.f_off + lf;
+      if (lf < M.nf) {
+        const int64_t f = (int64_t)M.f_off + lf;
         for (int j = 0; j < 3; j++) v3[j] = P.T[3 * f + j];
         const float* fv = P.fv + 9 * f;
         closest_triangle(zero, relv(fv, c), relv(fv + 3, c), relv(fv + 6, c), q, w);
         mcount = 3;
-      } else if (lf < G.nf + G.ne) {
-        int4 E = P.edges[(int64_t)G.e_off + (lf - G.nf)];
+      } else if (lf < M.nf + M.ne) {
+        int4 E = P.edges[(int64_t)M.e_off + (lf - M.nf)];
         v3[0] = E.x;
         v3[1] = E.y;
         float t;
@@ -101,14 +163,14 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
         w[1] = t;
         mcount = 2;
       } else {
-        v3[0] = G.v_off + (lf - G.nf - G.ne);
+        v3[0] = M.v_off + (lf - M.nf - M.ne);
         q = relb(P.V, v3[0], c);
         w[0] = 1.f;
         mcount = 1;
       }
       const float d = norm3(q);
       if (d > 0.f) {
-        const float s = P.sdf[i] < 0.f ? -1.f : 1.f;
+        const float s = cur.sd < 0.f ? -1.f : 1.f;
         // c - q = -q in this frame; g = s (c - q) / |c - q|
         const f3 g = q * (-s / d);
         for (int k = 0; k < 3; k++) {

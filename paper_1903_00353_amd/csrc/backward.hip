@@ -88,19 +88,58 @@ __device__ inline int div_floor(int a, int d, double inv) {
   return q;
 }
 
+// DPP lane moves (gfx9 encodings): lane l reads lane l + 1 (wave_shl:1), l - 1
+// (wave_shr:1), l - k within its row of 16 (row_shr:k), or lane 15 / 31 (the last
+// of the row before, row_bcast). Lanes without a source keep `id`.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWS = 0xf>
+__device__ inline int dpp_i(int id, int x) {
+  return __builtin_amdgcn_update_dpp(id, x, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ inline float dpp_f(float id, float x) {
+  return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(id), __float_as_int(x)));
+}
+
+// one step of the segmented inclusive scan over the lanes: add the partial sums
+// of the source lane where it lies in the same run. Row shifts 1, 2, 4, 8 scan
+// each row of 16; the two broadcasts carry row 0 into row 1 and row 2 into
+// row 3, then rows 0-1 into rows 2-3.
+template <int CTRL, int ROWS>
+__device__ inline void seg_step(int run, f3 (&con)[3]) {
+  const bool take = dpp_i<CTRL, ROWS>(-1, run) == run;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const float ux = dpp_f<CTRL, ROWS>(0.f, con[k].x), uy = dpp_f<CTRL, ROWS>(0.f, con[k].y),
+                uz = dpp_f<CTRL, ROWS>(0.f, con[k].z);
+    if (take) con[k] = con[k] + mk(ux, uy, uz);
+  }
+}
+
+// The pass is bound by the latency of its loads and of the table's LDS round
+// trips, so occupancy comes first: a 16 KB table per block of 256 lets 8 blocks
+// share a CU, and the register budget is held to 64 for 8 wavefronts per SIMD.
 constexpr int BW_THREADS = 256;
-constexpr int BW_SLOTS = 2048;                // hash table of (vertex, 3 partial sums) per block
-constexpr int BW_HASH_SHIFT = 21;             // 32 - log2(BW_SLOTS)
-constexpr int BW_FLUSH = BW_SLOTS - 3 * BW_THREADS;  // flush before a chunk could overfill it
-constexpr int BW_BLOCKS = 1024;               // persistent grid: 4 resident blocks of 256 per CU
+constexpr int BW_WAVES_PER_SIMD = 8;
+constexpr int BW_SLOTS = 1024;                // hash table of (vertex, 3 partial sums) per block
+constexpr int BW_FLUSH = 512;                 // flush once more slots than this are taken
+constexpr int BW_PROBES = 16;                 // a vertex not placed within this many slots goes to HBM
+constexpr int BW_BLOCKS = 2048;               // persistent grid: 8 resident blocks of 256 per CU
+constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x >> 1); }
+constexpr int BW_HASH_SHIFT = 32 - log2i(BW_SLOTS);
+static_assert((BW_SLOTS & (BW_SLOTS - 1)) == 0 && BW_FLUSH < BW_SLOTS, "table size");
 
 // Each block takes one contiguous run of band cells (band cells follow the
 // tile-ordered bricks, so a run covers a compact piece of surface and shares most
 // of its vertices) in chunks of one cell per thread. Contributions are summed per
-// vertex in an LDS hash table that is added to the global gradient only when
-// another chunk could overfill it, and at the end: one global add per vertex,
-// axis and flush instead of one per band cell.
-__global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
+// vertex in an LDS hash table (linear probing) that is added to the global
+// gradient once it is more than BW_FLUSH slots full, and at the end: one global
+// add per vertex, axis and flush instead of one per band cell. Probing stops
+// after BW_PROBES slots; such a vertex's contribution goes to the gradient
+// directly, so a full table costs time, never correctness.
+__global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdArgs P) {
   __shared__ int s_key[BW_SLOTS];
   __shared__ float s_acc[3][BW_SLOTS];
   __shared__ int s_used;
@@ -121,13 +160,9 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
   __syncthreads();
   int m = P.band_off ? find_segment(P.band_off, P.n_meshes + 1, c0 + threadIdx.x) : 0;
   BwMesh M = load_mesh(P, m);
-  // the four per-cell values of the next chunk are loaded while this one is
-  // processed: only the feature's own data is waited for inside a chunk
-  BwCell nxt = load_cell(P, c0 + threadIdx.x, c1);
   for (int64_t base = c0; base < c1; base += BW_THREADS) {
     const int64_t i = base + threadIdx.x;
-    const BwCell cur = nxt;
-    nxt = load_cell(P, i + BW_THREADS, c1);
+    const BwCell cur = load_cell(P, i, c1);
     const float gs = cur.gs;
     // this cell's contribution to each vertex k of its feature: f_k * g
     int32_t vid[3] = {-1, -1, -1};
@@ -188,29 +223,32 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
     // inclusive scan) and only its last lane touches the table: far fewer
     // conflicting LDS atomics on the same few slots. A feature can come back in
     // a later, separate run of the same wavefront, so runs are told apart by a
-    // run number (count of run heads up to the lane), not by the feature.
+    // run number (count of run heads up to the lane), not by the feature. All
+    // lane moves are DPP operands of vector instructions, which leaves the LDS
+    // to the table.
     const int lane = threadIdx.x & 63;
-    const int64_t knext = __shfl_down(fkey, 1, 64), kprev = __shfl_up(fkey, 1, 64);
-    const bool same_next = lane < 63 && knext == fkey;
+    const int klo = (int)fkey, khi = (int)(fkey >> 32);
+    // every lane moves both halves before anything is compared: a DPP read from a
+    // lane switched off by a branch would return the fallback
+    const int nlo = dpp_i<DPP_WAVE_SHL1>(~klo, klo), nhi = dpp_i<DPP_WAVE_SHL1>(~khi, khi);
+    const int plo = dpp_i<DPP_WAVE_SHR1>(~klo, klo), phi = dpp_i<DPP_WAVE_SHR1>(~khi, khi);
+    const bool same_next = (nlo == klo) & (nhi == khi);
+    const bool same_prev = (plo == klo) & (phi == khi);
     bool owner = fkey >= 0;
     if (__popcll(__ballot(same_next)) >= 8) {
-      const unsigned long long heads = __ballot(lane == 0 || kprev != fkey);
+      const unsigned long long heads = __ballot(!same_prev);
       const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
       const int run = __popcll(heads & upto);
-      for (int o = 1; o < 64; o <<= 1) {
-        const int ru = __shfl_up(run, o, 64);
-        const bool take = lane >= o && ru == run;
-        for (int k = 0; k < 3; k++) {
-          const float ux = __shfl_up(con[k].x, o, 64), uy = __shfl_up(con[k].y, o, 64),
-                      uz = __shfl_up(con[k].z, o, 64);
-          if (take) con[k] = con[k] + mk(ux, uy, uz);
-        }
-      }
+      seg_step<DPP_ROW_SHR1, 0xf>(run, con);
+      seg_step<DPP_ROW_SHR2, 0xf>(run, con);
+      seg_step<DPP_ROW_SHR4, 0xf>(run, con);
+      seg_step<DPP_ROW_SHR8, 0xf>(run, con);
+      seg_step<DPP_ROW_BCAST15, 0xa>(run, con);
+      seg_step<DPP_ROW_BCAST31, 0xc>(run, con);
       owner = owner && !same_next;
     }
+    int n_new = 0;
     if (owner) {
-      // first probe of all three vertices at once (independent LDS round trips),
-      // then linear probing only where the home slot holds another vertex
       unsigned h[3];
       int old[3];
 #pragma unroll
@@ -221,15 +259,26 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
 #pragma unroll
       for (int k = 0; k < 3; k++) {
         if (vid[k] < 0) continue;
-        while (old[k] != -1 && old[k] != vid[k]) {
+        for (int probe = 1; old[k] != -1 && old[k] != vid[k] && probe < BW_PROBES; probe++) {
           h[k] = (h[k] + 1) & (BW_SLOTS - 1);
           old[k] = atomicCAS(&s_key[h[k]], -1, vid[k]);
         }
-        if (old[k] == -1) atomicAdd(&s_used, 1);
-        atomicAdd(&s_acc[0][h[k]], con[k].x);
-        atomicAdd(&s_acc[1][h[k]], con[k].y);
-        atomicAdd(&s_acc[2][h[k]], con[k].z);
+        if (old[k] == -1 || old[k] == vid[k]) {
+          if (old[k] == -1) n_new++;
+          atomicAdd(&s_acc[0][h[k]], con[k].x);
+          atomicAdd(&s_acc[1][h[k]], con[k].y);
+          atomicAdd(&s_acc[2][h[k]], con[k].z);
+        } else {  // crowded neighbourhood: straight to the gradient
+          atomicAdd(P.grad + 3 * (int64_t)vid[k], con[k].x);
+          atomicAdd(P.grad + 3 * (int64_t)vid[k] + 1, con[k].y);
+          atomicAdd(P.grad + 3 * (int64_t)vid[k] + 2, con[k].z);
+        }
       }
+    }
+    {
+      // new slots of the wavefront, counted with ballots: one add to s_used
+      const int c = __popcll(__ballot(n_new >= 1)) + __popcll(__ballot(n_new >= 2)) + __popcll(__ballot(n_new >= 3));
+      if (lane == 0 && c) atomicAdd(&s_used, c);
     }
     __syncthreads();
     const int used = s_used;
@@ -237,8 +286,8 @@ __global__ __launch_bounds__(BW_THREADS) void k_backward(BwdArgs P) {
     __syncthreads();  // every thread has read s_used before the next chunk changes it
     if (!last && used <= BW_FLUSH) continue;  // block-uniform: room for another chunk
     // flush: consecutive lanes add the three components of one vertex (a wave
-    // instruction covers about 21 slots in 12-byte runs); the table is then at
-    // least BW_FLUSH / BW_SLOTS full, except at the end of the run
+    // instruction covers about 21 slots in 12-byte runs); the table is then
+    // more than BW_FLUSH / BW_SLOTS full, except at the end of the run
     for (int k = threadIdx.x; k < 3 * BW_SLOTS; k += BW_THREADS) {
       const int slot = k / 3, cmp = k - 3 * slot;
       const int v = s_key[slot];

@@ -123,10 +123,29 @@ __device__ inline void seg_step(int run, f3 (&con)[3]) {
 // share a CU, and the register budget is held to 64 for 8 wavefronts per SIMD.
 constexpr int BW_THREADS = 256;
 constexpr int BW_WAVES_PER_SIMD = 8;
-constexpr int BW_SLOTS = 1024;                // hash table of (vertex, 3 partial sums) per block
-constexpr int BW_FLUSH = 512;                 // flush once more slots than this are taken
+constexpr int BW_SLOTS = 512;                 // hash table of (vertex, 3 partial sums) per block
+constexpr int BW_FLUSH = 256;                 // flush once more slots than this are taken
 constexpr int BW_PROBES = 16;                 // a vertex not placed within this many slots goes to HBM
 constexpr int BW_BLOCKS = 2048;               // persistent grid: 8 resident blocks of 256 per CU
+// LDS adds of floats are slow on this chip where 64-bit integer adds are not,
+// so the table sums in fixed point: c * 2^fx goes in as an integer when that is
+// exact (magnitude at least 2^23, so the float is integer-valued), otherwise c
+// goes straight to the gradient
+__device__ inline void add_fixed(unsigned long long* slot, float c, int fx, float* direct) {
+  const float v = ldexpf(c, fx);
+  if (fabsf(v) >= 8388608.f && fabsf(v) < 1.1e12f) {  // 2^23 <= |v| < 2^40 (or so)
+    atomicAdd(slot, (unsigned long long)(long long)v);
+  } else if (c != 0.f) {
+    atomicAdd(direct, c);
+  }
+}
+
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
 constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x >> 1); }
 constexpr int BW_HASH_SHIFT = 32 - log2i(BW_SLOTS);
 static_assert((BW_SLOTS & (BW_SLOTS - 1)) == 0 && BW_FLUSH < BW_SLOTS, "table size");
@@ -141,8 +160,9 @@ static_assert((BW_SLOTS & (BW_SLOTS - 1)) == 0 && BW_FLUSH < BW_SLOTS, "table si
 // directly, so a full table costs time, never correctness.
 __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdArgs P) {
   __shared__ int s_key[BW_SLOTS];
-  __shared__ float s_acc[3][BW_SLOTS];
+  __shared__ unsigned long long s_acc[3][BW_SLOTS];  // fixed-point sums, two's complement
   __shared__ int s_used;
+  __shared__ float s_gmax[BW_THREADS / 64];
   int64_t lim = P.n;
   if (P.band_off) lim = P.band_off[P.n_meshes] < lim ? P.band_off[P.n_meshes] : lim;
   else if (P.n_dev && *P.n_dev < lim) lim = *P.n_dev;
@@ -154,10 +174,28 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
   if (c0 >= c1) return;  // block-uniform
   for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
     s_key[k] = -1;
-    s_acc[0][k] = s_acc[1][k] = s_acc[2][k] = 0.f;
+    s_acc[0][k] = s_acc[1][k] = s_acc[2][k] = 0ull;
   }
   if (threadIdx.x == 0) s_used = 0;
+  // Fixed-point scale of this block: 2^fx with fx such that the largest finite
+  // |dL/dSDF| of the run, which bounds every contribution (|g| = 1, 0 <= w <= 1),
+  // scales to below 2^40. A scaled contribution of at least 2^23 in magnitude is
+  // an integer-valued float, converted exactly; such terms are summed exactly in
+  // 64-bit integers (no overflow below 2^23 terms per slot), in any order. The
+  // rest (tiny or non-finite) are added to the gradient as floats.
+  float gmax = 0.f;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += BW_THREADS) {
+    const float a = fabsf(P.gsdf[i]);
+    if (a <= __FLT_MAX__) gmax = fmaxf(gmax, a);
+  }
+  gmax = wave_max(gmax);
+  if ((threadIdx.x & 63) == 0) s_gmax[threadIdx.x >> 6] = gmax;
   __syncthreads();
+#pragma unroll
+  for (int w = 0; w < BW_THREADS / 64; w++) gmax = fmaxf(gmax, s_gmax[w]);
+  int gexp = 0;
+  (void)frexpf(gmax, &gexp);  // gmax < 2^gexp
+  const int fx = 40 - gexp;
   int m = P.band_off ? find_segment(P.band_off, P.n_meshes + 1, c0 + threadIdx.x) : 0;
   BwMesh M = load_mesh(P, m);
   for (int64_t base = c0; base < c1; base += BW_THREADS) {
@@ -265,9 +303,9 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
         }
         if (old[k] == -1 || old[k] == vid[k]) {
           if (old[k] == -1) n_new++;
-          atomicAdd(&s_acc[0][h[k]], con[k].x);
-          atomicAdd(&s_acc[1][h[k]], con[k].y);
-          atomicAdd(&s_acc[2][h[k]], con[k].z);
+          add_fixed(&s_acc[0][h[k]], con[k].x, fx, P.grad + 3 * (int64_t)vid[k]);
+          add_fixed(&s_acc[1][h[k]], con[k].y, fx, P.grad + 3 * (int64_t)vid[k] + 1);
+          add_fixed(&s_acc[2][h[k]], con[k].z, fx, P.grad + 3 * (int64_t)vid[k] + 2);
         } else {  // crowded neighbourhood: straight to the gradient
           atomicAdd(P.grad + 3 * (int64_t)vid[k], con[k].x);
           atomicAdd(P.grad + 3 * (int64_t)vid[k] + 1, con[k].y);
@@ -291,13 +329,14 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
     for (int k = threadIdx.x; k < 3 * BW_SLOTS; k += BW_THREADS) {
       const int slot = k / 3, cmp = k - 3 * slot;
       const int v = s_key[slot];
-      if (v >= 0) atomicAdd(P.grad + 3 * (int64_t)v + cmp, s_acc[cmp][slot]);
+      const long long q = (long long)s_acc[cmp][slot];
+      if (v >= 0 && q != 0) atomicAdd(P.grad + 3 * (int64_t)v + cmp, (float)ldexp((double)q, -fx));
     }
     __syncthreads();
     if (last) break;
     for (int k = threadIdx.x; k < BW_SLOTS; k += BW_THREADS) {
       s_key[k] = -1;
-      s_acc[0][k] = s_acc[1][k] = s_acc[2][k] = 0.f;
+      s_acc[0][k] = s_acc[1][k] = s_acc[2][k] = 0ull;
     }
     if (threadIdx.x == 0) s_used = 0;
     __syncthreads();

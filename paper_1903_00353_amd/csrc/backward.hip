@@ -129,15 +129,21 @@ constexpr int BW_PROBES = 16;                 // a vertex not placed within this
 constexpr int BW_BLOCKS = 2048;               // persistent grid: 8 resident blocks of 256 per CU
 // LDS adds of floats are slow on this chip where 64-bit integer adds are not,
 // so the table sums in fixed point: c * 2^fx goes in as an integer when that is
-// exact (magnitude at least 2^23, so the float is integer-valued), otherwise c
-// goes straight to the gradient
+// exact (magnitude at least 2^23, so the float is integer-valued) and below 2^42
+// (no overflow), otherwise c goes straight to the gradient
 __device__ inline void add_fixed(unsigned long long* slot, float c, int fx, float* direct) {
   const float v = ldexpf(c, fx);
-  if (fabsf(v) >= 8388608.f && fabsf(v) < 1.1e12f) {  // 2^23 <= |v| < 2^40 (or so)
+  if (fabsf(v) >= 8388608.f && fabsf(v) < 4398046511104.f) {  // 2^23 <= |v| < 2^42
     atomicAdd(slot, (unsigned long long)(long long)v);
   } else if (c != 0.f) {
     atomicAdd(direct, c);
   }
+}
+
+// max(m, |a|) over finite a only
+__device__ inline float fmax_finite(float m, float a) {
+  const float b = fabsf(a);
+  return b <= __FLT_MAX__ ? fmaxf(m, b) : m;
 }
 
 __device__ inline float wave_max(float v) {
@@ -177,17 +183,16 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
     s_acc[0][k] = s_acc[1][k] = s_acc[2][k] = 0ull;
   }
   if (threadIdx.x == 0) s_used = 0;
-  // Fixed-point scale of this block: 2^fx with fx such that the largest finite
-  // |dL/dSDF| of the run, which bounds every contribution (|g| = 1, 0 <= w <= 1),
-  // scales to below 2^40. A scaled contribution of at least 2^23 in magnitude is
-  // an integer-valued float, converted exactly; such terms are summed exactly in
-  // 64-bit integers (no overflow below 2^23 terms per slot), in any order. The
-  // rest (tiny or non-finite) are added to the gradient as floats.
+  // Fixed-point scale of this block: 2^fx, with fx such that the largest finite
+  // |dL/dSDF| of the block's first chunk scales to just below 2^40. Every term is
+  // bounded by its cell's |dL/dSDF| (|g| = 1, 0 <= w <= 1). A scaled term of
+  // magnitude in [2^23, 2^42) is an integer-valued float, converted exactly, and
+  // summed exactly in 64-bit integers (a slot gets fewer than 2^20 terms between
+  // flushes: no overflow), in any order. Terms outside that window (tiny, much
+  // larger than the first chunk's, or non-finite) are added to the gradient as
+  // floats, so the scale only decides speed, never the result.
   float gmax = 0.f;
-  for (int64_t i = c0 + threadIdx.x; i < c1; i += BW_THREADS) {
-    const float a = fabsf(P.gsdf[i]);
-    if (a <= __FLT_MAX__) gmax = fmaxf(gmax, a);
-  }
+  if (c0 + threadIdx.x < c1) gmax = fmax_finite(0.f, P.gsdf[c0 + threadIdx.x]);
   gmax = wave_max(gmax);
   if ((threadIdx.x & 63) == 0) s_gmax[threadIdx.x >> 6] = gmax;
   __syncthreads();

@@ -239,6 +239,31 @@ def test_backward_matches_oracle_gradient(configs):
     assert np.abs(gv - ref).max() <= 1e-3 * np.abs(ref).max()
 
 
+def test_backward_wide_range_upstream(configs):
+    """The adjoint sums each block's terms in fixed point scaled to the block's
+    largest |dL/dSDF|, and sends terms too small for that scale to the gradient
+    as floats. Upstream values spread over 40 decades, with exact zeros, put
+    most terms on that second path; every vertex must still match the oracle
+    within 1e-5 of its sum of |terms|. An all-zero upstream gives exact zeros."""
+    name, meshes, grids = configs(2)
+    v, f = meshes[0]
+    g = grids[0]
+    feats, band = run_device(v, f, g)
+    cell, sdf, feat = to_np(band)
+    rng = np.random.default_rng(17)
+    up = (2.0 * sdf * 10.0 ** rng.uniform(-20, 20, sdf.shape[0])).astype(np.float32)
+    up[rng.random(sdf.shape[0]) < 0.1] = 0.0
+    print("[case]", name, "wide-range upstream", up.shape, flush=True)
+    gv = P.csc_sdf_backward(feats, band, torch.from_numpy(up).cuda()).cpu().numpy().astype(np.float64)
+    om = oracle.OracleMesh(v, f)
+    ref = om.grad(g, cell, feat, np.sign(sdf), up.astype(np.float64))
+    scale = vertex_term_scale(f, om.edges, v.shape[0], feat, up)
+    assert np.all(np.isfinite(gv))
+    assert_same_sums(gv, ref, scale, "wide-range upstream")
+    z = P.csc_sdf_backward(feats, band, torch.zeros_like(band.sdf)).cpu().numpy()
+    assert not np.any(z)
+
+
 def test_backward_matches_finite_differences():
     """Device gradient of L = sum SDF^2 against FP64 central differences of the oracle
     distance over the device band set (cells at a kink excluded from both sides)."""

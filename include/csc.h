@@ -128,8 +128,9 @@ int csc_build_features(const float* verts_d, int64_t nv, const int32_t* tris_d, 
  *     grids and options, so that nothing is allocated or copied from the host:
  *     the call can then be captured into a graph. Errors are read later by
  *     csc_features_sync.
- *   CSC_BUILD_GRAPH_SAFE: group corners without the library radix sort (which
- *     clears memory with memset nodes); required when capturing.
+ *   CSC_BUILD_GRAPH_SAFE: accepted for compatibility. Every build now groups
+ *     corners with the library's own radix sort (kernels only, no memset
+ *     nodes), so every build is safe to capture.
  * Errors as csc_build_features.
  */
 #define CSC_BUILD_NO_SYNC 1

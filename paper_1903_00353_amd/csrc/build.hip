@@ -86,83 +86,6 @@ __global__ void k_offsets(const uint32_t* __restrict__ key, int64_t nh, int64_t 
     for (int64_t v = k + 1; v <= nv; v++) off[v] = (int32_t)nh;
 }
 
-constexpr int CC_THREADS = 1024;     // faces per block: more faces share each returning global add
-constexpr int CC_SLOTS = 4096;       // > 3 * CC_THREADS insertions: probing always ends
-constexpr int CC_HASH_SHIFT = 20;    // 32 - log2(CC_SLOTS)
-static_assert(CC_SLOTS % CC_THREADS == 0, "each thread flushes a whole number of slots");
-
-// Corner counts per vertex without library sorting (graph-capturable path): a
-// block counts its corners per vertex in an LDS hash table and reserves one range
-// per vertex with a single global atomic; each corner gets base + rank.
-__global__ __launch_bounds__(CC_THREADS) void k_count_corners(const int32_t* __restrict__ tg, int64_t nf, int32_t* cnt,
-                                                             int32_t* slot) {
-  __shared__ int s_key[CC_SLOTS], s_cnt[CC_SLOTS], s_base[CC_SLOTS];
-  for (int k = threadIdx.x; k < CC_SLOTS; k += CC_THREADS) {
-    s_key[k] = -1;
-    s_cnt[k] = 0;
-  }
-  __syncthreads();
-  const int64_t f = blockIdx.x * (int64_t)CC_THREADS + threadIdx.x;
-  // the three corners' LDS round trips are issued together: first probes, then
-  // linear probing only where the home slot holds another vertex, then the ranks
-  int hs[3] = {0, 0, 0}, rank[3] = {0, 0, 0};
-  if (f < nf) {
-    int32_t v[3];
-    int old[3];
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-      v[j] = tg[3 * f + j];
-      hs[j] = (int)(((unsigned)v[j] * 2654435761u) >> CC_HASH_SHIFT);
-      old[j] = atomicCAS(&s_key[hs[j]], -1, v[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-      while (old[j] != -1 && old[j] != v[j]) {
-        hs[j] = (hs[j] + 1) & (CC_SLOTS - 1);
-        old[j] = atomicCAS(&s_key[hs[j]], -1, v[j]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 3; j++) rank[j] = atomicAdd(&s_cnt[hs[j]], 1);
-  }
-  __syncthreads();
-  // one returning global add per vertex present in the block; the adds of a
-  // thread's slots are issued before any result is used
-  constexpr int PER = CC_SLOTS / CC_THREADS;
-  int got[PER];
-#pragma unroll
-  for (int u = 0; u < PER; u++) {
-    const int k = threadIdx.x + u * CC_THREADS;
-    got[u] = s_key[k] >= 0 ? atomicAdd(&cnt[s_key[k]], s_cnt[k]) : 0;
-  }
-#pragma unroll
-  for (int u = 0; u < PER; u++) s_base[threadIdx.x + u * CC_THREADS] = got[u];
-  __syncthreads();
-  if (f < nf) {
-#pragma unroll
-    for (int j = 0; j < 3; j++) slot[3 * f + j] = s_base[hs[j]] + rank[j];
-  }
-}
-
-__global__ void k_scatter_corners(const int32_t* __restrict__ tg, int64_t nh, const int32_t* __restrict__ off,
-                                  const int32_t* __restrict__ slot, int32_t* vc) {
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= nh) return;
-  vc[off[tg[c]] + slot[c]] = (int32_t)c;
-}
-
-// deterministic order of each vertex's corners (ascending index)
-__global__ void k_sort_segments(const int32_t* __restrict__ off, int32_t* vc, int64_t nv) {
-  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  int32_t s = off[v], e = off[v + 1];
-  for (int32_t i = s + 1; i < e; i++) {
-    int32_t x = vc[i], j = i - 1;
-    while (j >= s && vc[j] > x) { vc[j + 1] = vc[j]; j--; }
-    vc[j + 1] = x;
-  }
-}
-
 constexpr int VK_THREADS = 128;
 constexpr int VK_MAXD = 12;  // fans up to this degree are staged in LDS (18 KB per block: 4 wavefronts per SIMD)
 
@@ -557,7 +480,6 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   int dc = check_device();
   if (dc != CSC_OK) return dc;
 
-  const bool graph_safe = (flags & CSC_BUILD_GRAPH_SAFE) != 0;
   const bool no_sync = (flags & CSC_BUILD_NO_SYNC) != 0;
   hipStream_t s = (hipStream_t)stream;
   csc_features* F = *out;
@@ -573,8 +495,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   };
   int sort_bits = 1;
   while (sort_bits < 31 && ((int64_t)1 << sort_bits) < tv) sort_bits++;
-  size_t sort_bytes = graph_safe ? F->t_sort_bytes : sort_pairs_tmp_bytes(3 * tf, sort_bits);
-  if (!graph_safe && sort_bytes == 0) return fail(fail_hip(hipErrorInvalidValue));
+  const size_t sort_bytes = sort_pairs_tmp_bytes(3 * tf, sort_bits);
+  if (sort_bytes == 0) return fail(fail_hip(hipErrorInvalidValue));
   Layout L = layout(n_meshes, tv, tf, tb, sort_bytes);
   const bool config_changed = fresh || !same_config(F, mesh, o) || F->arena_bytes < L.total || F->nv != tv ||
                               F->nf != tf;
@@ -636,8 +558,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->t_c = (int32_t*)(A + L.off[L_TC]);
   F->t_scan = (int32_t*)(A + L.off[L_TSCAN]);
   F->d_stats = (int64_t*)(A + L.off[L_STATS]);
-  F->t_sort = graph_safe ? F->t_sort : (void*)(A + L.off[L_SORT]);
-  if (!graph_safe) F->t_sort_bytes = sort_bytes;
+  F->t_sort = (void*)(A + L.off[L_SORT]);
+  F->t_sort_bytes = sort_bytes;
   F->built = F->synced = false;
 
 #define CK(x)                                        \
@@ -673,19 +595,12 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                             F->d_stats);
   k_vert_mesh<<<grid_1d(tv, B), B, 0, s>>>(tv, F->v_off, n_meshes, F->vert_mesh);
   const int32_t* T = F->tris_g;
-  // 2. vertex -> corner table
-  if (graph_safe) {
-    k_fill_i32<<<grid_1d(tv + 1, B), B, 0, s>>>(F->t_a, tv + 1, 0);
-    k_count_corners<<<grid_1d(tf, CC_THREADS), CC_THREADS, 0, s>>>(T, tf, F->t_a, F->t_c);
-    CK(exclusive_scan(F->t_a, F->vtx_off, tv + 1, F->t_scan, nullptr, nullptr, s));
-    k_scatter_corners<<<grid_1d(nh, B), B, 0, s>>>(T, nh, F->vtx_off, F->t_c, F->vtx_corners);
-    k_sort_segments<<<grid_1d(tv, B), B, 0, s>>>(F->vtx_off, F->vtx_corners, tv);
-  } else {
-    k_iota<<<grid_1d(nh, B), B, 0, s>>>(F->t_a, nh);
-    CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, F->t_a, F->vtx_corners, nh,
-                  sort_bits, s));
-    k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, tv, F->vtx_off);
-  }
+  // 2. vertex -> corner table: corners sorted by vertex (stable: each vertex's
+  // corners in ascending order), then the segment starts
+  k_iota<<<grid_1d(nh, B), B, 0, s>>>(F->t_a, nh);
+  CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, F->t_a, F->vtx_corners, nh,
+                sort_bits, s));
+  k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, tv, F->vtx_off);
   // 3. per vertex: twins, pseudonormal, class, cone; then edge numbering
   k_vertex<<<grid_1d(tv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, T, tv, F->vtx_off, F->vtx_corners, o.ruff_mode,
                                                         o.saddle_mode, o.force_both_sides, F->t_a, F->vinfo,

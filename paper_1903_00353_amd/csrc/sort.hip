@@ -1,22 +1,193 @@
-// Stable device radix sort of (key, value) pairs (hipCUB / rocPRIM), used to
-// group triangle corners by vertex.
-#include <hipcub/hipcub.hpp>
-
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits, 8 bits
+// per pass. It groups triangle corners by vertex (stable, so each vertex's
+// corners come out in ascending order) and orders soup corners by coordinate.
+//
+// Each pass runs three launches over tiles of RS_TILE pairs:
+//  * k_rs_hist: the digit histogram of every tile, stored digit-major
+//    (hist[d * ntiles + tile]), counted with LDS integer atomics;
+//  * an exclusive scan of that array: the output offset of (digit, tile);
+//  * k_rs_scatter: every tile ranks its pairs stably per digit, stages them in
+//    LDS in digit order and writes each digit's run to its offset, so that
+//    consecutive threads write consecutive addresses.
+// Tile item (w, r, lane) is pair (w * RS_ROUNDS + r) * 64 + lane of the tile:
+// wave w takes its pairs in RS_ROUNDS rounds of 64 consecutive ones, so the
+// order of (w, r, lane) is the input order and ranks follow it. Inside a round
+// the lanes holding the same digit are found with 8 ballots (one per digit bit);
+// each wave keeps running per-digit counts in LDS, advanced by the last lane of
+// each digit group. No memset and no host synchronisation: safe to capture in a
+// graph.
 #include "internal.h"
 
 namespace csc {
 
-size_t sort_pairs_tmp_bytes(int64_t n, int bits) {
-  size_t tmp = 0;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                                    (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, bits,
-                                                    (hipStream_t)0);
-  return e == hipSuccess ? tmp : 0;
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 4096 pairs
+constexpr int RS_BINS = 256;
+static_assert(RS_BINS == RS_THREADS, "one digit per thread in the per-tile tables");
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                        int64_t ntiles, int32_t* hist) {
+  __shared__ int s_h[RS_BINS];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  s_h[t] = 0;
+  __syncthreads();
+  const int64_t base = blockIdx.x * (int64_t)RS_TILE + w * (RS_ROUNDS * 64) + lane;
+#pragma unroll 8
+  for (int r = 0; r < RS_ROUNDS; r++)
+    if (base + r * 64 < n) atomicAdd(&s_h[(keys[base + r * 64] >> shift) & (RS_BINS - 1)], 1);
+  __syncthreads();
+  hist[(int64_t)t * ntiles + blockIdx.x] = s_h[t];
 }
 
+// exclusive scan of one value per thread across the block
+__device__ inline int rs_block_excl(int v, int* s_w) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  int before = 0;
+#pragma unroll
+  for (int u = 0; u < RS_WAVES; u++) before += u < w ? s_w[u] : 0;
+  return before + inc - v;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                           const int32_t* __restrict__ vin, uint32_t* kout,
+                                                           int32_t* vout, int64_t n, int shift, int64_t ntiles,
+                                                           const int32_t* __restrict__ off) {
+  __shared__ int s_cnt[RS_WAVES][RS_BINS];  // running, then starting, tile position of each digit per wave
+  __shared__ int s_start[RS_BINS];          // first tile position of each digit
+  __shared__ int s_out[RS_BINS];            // output offset of each digit's run
+  __shared__ int s_w[RS_WAVES];
+  __shared__ uint32_t s_k[RS_TILE];
+  __shared__ int32_t s_v[RS_TILE];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+#pragma unroll
+  for (int u = 0; u < RS_WAVES; u++) s_cnt[u][t] = 0;
+  s_out[t] = off[(int64_t)t * ntiles + blockIdx.x];
+  __syncthreads();
+  const int64_t tile0 = blockIdx.x * (int64_t)RS_TILE;
+  const int64_t base = tile0 + w * (RS_ROUNDS * 64) + lane;
+  uint32_t k[RS_ROUNDS];
+  int32_t v[RS_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; r++) {
+    const bool ok = base + r * 64 < n;
+    k[r] = ok ? kin[base + r * 64] : 0u;
+    v[r] = ok ? vin[base + r * 64] : 0;
+  }
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const unsigned long long above = lane == 63 ? 0ull : (~0ull << (lane + 1));
+  int pos[RS_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; r++) {
+    const bool ok = base + r * 64 < n;
+    const int d = (int)((k[r] >> shift) & (RS_BINS - 1));
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      const unsigned long long m = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    // all lanes read the digit's count before its last lane advances it; LDS
+    // executes a wavefront's operations in order
+    const int prev = ok ? s_cnt[w][d] : 0;
+    pos[r] = prev + __popcll(peers & below);
+    if (ok && (peers & above) == 0) s_cnt[w][d] = prev + __popcll(peers);
+  }
+  __syncthreads();
+  {
+    // digit t: its start in the tile (digit order), then each wave's start
+    int c[RS_WAVES], tot = 0;
+#pragma unroll
+    for (int u = 0; u < RS_WAVES; u++) {
+      c[u] = s_cnt[u][t];
+      tot += c[u];
+    }
+    int acc = rs_block_excl(tot, s_w);
+    s_start[t] = acc;
+#pragma unroll
+    for (int u = 0; u < RS_WAVES; u++) {
+      s_cnt[u][t] = acc;
+      acc += c[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; r++) {
+    if (base + r * 64 < n) {
+      const int p = s_cnt[w][(k[r] >> shift) & (RS_BINS - 1)] + pos[r];
+      s_k[p] = k[r];
+      s_v[p] = v[r];
+    }
+  }
+  __syncthreads();
+  // the tile in digit order: position j of digit d goes to that digit's run
+  const int tn = (int)(n - tile0 < RS_TILE ? n - tile0 : RS_TILE);
+  for (int j = t; j < tn; j += RS_THREADS) {
+    const uint32_t key = s_k[j];
+    const int d = (int)((key >> shift) & (RS_BINS - 1));
+    const int64_t p = (int64_t)s_out[d] + (j - s_start[d]);
+    kout[p] = key;
+    vout[p] = s_v[j];
+  }
+}
+
+namespace {
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+int64_t rs_tiles(int64_t n) { return (n + RS_TILE - 1) / RS_TILE; }
+}  // namespace
+
+// temporary storage: the other key and value buffers, the digit-major tile
+// histogram and its scan's temporaries
+size_t sort_pairs_tmp_bytes(int64_t n, int bits) {
+  if (n < 0 || bits <= 0 || bits > 32) return 0;
+  const int64_t h = RS_BINS * rs_tiles(n);
+  return al(sizeof(uint32_t) * (size_t)n) + al(sizeof(int32_t) * (size_t)n) + al(sizeof(int32_t) * (size_t)h) +
+         al(sizeof(int32_t) * (size_t)scan_tmp_ints(h)) + 256;
+}
+
+// keys_in/vals_in are read only; the result lands in keys_out/vals_out, which
+// must not overlap the inputs. Offsets are int32: n < 2^31.
 hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint32_t* keys_out,
                       const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits, hipStream_t s) {
-  return hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys_in, keys_out, vals_in, vals_out, (int)n, 0, bits, s);
+  if (n == 0) return hipSuccess;
+  if (n < 0 || n >= INT32_MAX || bits <= 0 || bits > 32 || !tmp || tmp_bytes < sort_pairs_tmp_bytes(n, bits))
+    return hipErrorInvalidValue;
+  const int64_t ntiles = rs_tiles(n), h = RS_BINS * ntiles;
+  if (ntiles > INT32_MAX) return hipErrorInvalidValue;
+  char* p = (char*)tmp;
+  uint32_t* kalt = (uint32_t*)p;
+  p += al(sizeof(uint32_t) * (size_t)n);
+  int32_t* valt = (int32_t*)p;
+  p += al(sizeof(int32_t) * (size_t)n);
+  int32_t* hist = (int32_t*)p;
+  p += al(sizeof(int32_t) * (size_t)h);
+  int32_t* scan_tmp = (int32_t*)p;
+  const int passes = (bits + 7) / 8;
+  const uint32_t* ks = keys_in;
+  const int32_t* vs = vals_in;
+  for (int q = 0; q < passes; q++) {
+    // the last pass writes the output; before it, passes alternate so that
+    // they do too: ... -> alt -> out -> alt -> out
+    const bool to_out = ((passes - 1 - q) & 1) == 0;
+    uint32_t* kd = to_out ? keys_out : kalt;
+    int32_t* vd = to_out ? vals_out : valt;
+    k_rs_hist<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ks, n, 8 * q, ntiles, hist);
+    hipError_t e = exclusive_scan(hist, hist, h, scan_tmp, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_rs_scatter<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ks, vs, kd, vd, n, 8 * q, ntiles, hist);
+    ks = kd;
+    vs = vd;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace csc

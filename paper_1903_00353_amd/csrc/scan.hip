@@ -1,5 +1,6 @@
-// Exclusive prefix sum over int32 (three passes: tile sums, scan of the tile
-// sums in one block, scan of each tile plus its offset).
+// Exclusive prefix sum over int32 (tile sums, then either each tile's own
+// offset from the sums before it, or a scan of the tile sums in one block
+// followed by each tile's scan plus its offset).
 #include "internal.h"
 
 namespace csc {
@@ -104,6 +105,51 @@ __global__ __launch_bounds__(SB) void k_scan_tiles(const int32_t* in, int32_t* o
   }
 }
 
+// With few tiles each block adds up the sums of the tiles before it itself (at
+// most SHORT_TILES ints, coalesced), which saves the launch that scans the tile
+// sums; the last block stores the total.
+constexpr int64_t SHORT_TILES = 4096;
+
+__global__ __launch_bounds__(SB) void k_scan_tiles_short(const int32_t* in, int32_t* out, int64_t n,
+                                                         const int32_t* __restrict__ sums, int64_t* total_i64,
+                                                         int32_t* total_i32) {
+  __shared__ int tile[STILE];
+  __shared__ int ws[SB / 64];
+  const int64_t base = (int64_t)blockIdx.x * STILE;
+  int pre = 0;
+  for (int j = threadIdx.x; j < (int)blockIdx.x; j += SB) pre += sums[j];
+  for (int i = threadIdx.x; i < STILE; i += SB) {
+    const int64_t idx = base + i;
+    tile[i] = idx < n ? in[idx] : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) pre += __shfl_down(pre, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = pre;
+  __syncthreads();
+  int offset = 0;
+#pragma unroll
+  for (int w = 0; w < SB / 64; w++) offset += ws[w];
+  int loc[SITEMS];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SITEMS; k++) {
+    loc[k] = s;
+    s += tile[threadIdx.x * SITEMS + k];
+  }
+  int tot;
+  const int ex = block_excl_scan<SB>(s, &tot) + offset;
+#pragma unroll
+  for (int k = 0; k < SITEMS; k++) tile[threadIdx.x * SITEMS + k] = ex + loc[k];
+  __syncthreads();
+  for (int i = threadIdx.x; i < STILE; i += SB) {
+    const int64_t idx = base + i;
+    if (idx < n) out[idx] = tile[i];
+  }
+  if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
+    if (total_i64) *total_i64 = offset + tot;
+    if (total_i32) *total_i32 = offset + tot;
+  }
+}
+
 int64_t scan_tmp_ints(int64_t n) { return (n + STILE - 1) / STILE + 1; }
 
 hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t* total_i64,
@@ -111,8 +157,12 @@ hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* t
   int64_t nb = (n + STILE - 1) / STILE;
   if (nb < 1) nb = 1;
   k_tile_sums<<<(unsigned)nb, SB, 0, s>>>(in, n, tmp);
-  k_scan_sums<<<1, 1024, 0, s>>>(tmp, nb, total_i64, total_i32);
-  k_scan_tiles<<<(unsigned)nb, SB, 0, s>>>(in, out, n, tmp);
+  if (nb <= SHORT_TILES) {
+    k_scan_tiles_short<<<(unsigned)nb, SB, 0, s>>>(in, out, n, tmp, total_i64, total_i32);
+  } else {
+    k_scan_sums<<<1, 1024, 0, s>>>(tmp, nb, total_i64, total_i32);
+    k_scan_tiles<<<(unsigned)nb, SB, 0, s>>>(in, out, n, tmp);
+  }
   return hipGetLastError();
 }
 

@@ -70,10 +70,6 @@ __global__ void k_vert_mesh(int64_t nv, const int32_t* __restrict__ v_off, int n
   if (v < nv) vert_mesh[v] = find_segment(v_off, n_meshes + 1, v);
 }
 
-__global__ void k_iota(int32_t* p, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = (int32_t)i;
-}
 
 // Segment offsets of the corners sorted by vertex: off[v] = first position whose
 // vertex is >= v (vertices without corners get empty segments), off[nv] = nh.
@@ -597,8 +593,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   const int32_t* T = F->tris_g;
   // 2. vertex -> corner table: corners sorted by vertex (stable: each vertex's
   // corners in ascending order), then the segment starts
-  k_iota<<<grid_1d(nh, B), B, 0, s>>>(F->t_a, nh);
-  CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, F->t_a, F->vtx_corners, nh,
+  CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, nullptr, F->vtx_corners, nh,
                 sort_bits, s));
   k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, tv, F->vtx_off);
   // 3. per vertex: twins, pseudonormal, class, cone; then edge numbering

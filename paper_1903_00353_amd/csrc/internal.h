@@ -66,7 +66,8 @@ int64_t scan_tmp_ints(int64_t n);
 hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t* total_i64,
                           int32_t* total_i32, hipStream_t s);
 
-// stable radix sort of n (key, value) pairs on the low `bits` key bits
+// stable radix sort of n (key, value) pairs on the low `bits` key bits; vals_in
+// null: the values are 0, 1, ..., n-1
 size_t sort_pairs_tmp_bytes(int64_t n, int bits);
 hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint32_t* keys_out,
                       const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits, hipStream_t s);

@@ -1,20 +1,22 @@
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits, 8 bits
-// per pass. It groups triangle corners by vertex (stable, so each vertex's
-// corners come out in ascending order) and orders soup corners by coordinate.
+// per pass (wider digits make the digit-major histogram as long as the data:
+// 11-bit digits in tiles of 2048 pairs doubled the sort time). It groups
+// triangle corners by vertex (stable, so each vertex's corners come out in
+// ascending order) and orders soup corners by coordinate.
 //
-// Each pass runs three launches over tiles of RS_TILE pairs:
+// Each pass runs three launches over tiles of RsCfg::TILE pairs:
 //  * k_rs_hist: the digit histogram of every tile, stored digit-major
 //    (hist[d * ntiles + tile]), counted with LDS integer atomics;
 //  * an exclusive scan of that array: the output offset of (digit, tile);
 //  * k_rs_scatter: every tile ranks its pairs stably per digit, stages them in
 //    LDS in digit order and writes each digit's run to its offset, so that
 //    consecutive threads write consecutive addresses.
-// Tile item (w, r, lane) is pair (w * RS_ROUNDS + r) * 64 + lane of the tile:
-// wave w takes its pairs in RS_ROUNDS rounds of 64 consecutive ones, so the
-// order of (w, r, lane) is the input order and ranks follow it. Inside a round
-// the lanes holding the same digit are found with 8 ballots (one per digit bit);
-// each wave keeps running per-digit counts in LDS, advanced by the last lane of
-// each digit group. No memset and no host synchronisation: safe to capture in a
+// Tile item (w, r, lane) is pair (w * ROUNDS + r) * 64 + lane of the tile: wave
+// w takes its pairs in ROUNDS rounds of 64 consecutive ones, so the order of
+// (w, r, lane) is the input order and ranks follow it. Inside a round the lanes
+// holding the same digit are found with one ballot per digit bit; each wave
+// keeps running per-digit counts in LDS, advanced by the last lane of each
+// digit group. No memset and no host synchronisation: safe to capture in a
 // graph.
 #include "internal.h"
 
@@ -22,23 +24,31 @@ namespace csc {
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_ROUNDS = 16;
-constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 4096 pairs
-constexpr int RS_BINS = 256;
-static_assert(RS_BINS == RS_THREADS, "one digit per thread in the per-tile tables");
 
+// digit width and tile length: 8-bit digits in tiles of 4096 pairs
+template <int RB>
+struct RsCfg {
+  static constexpr int BINS = 1 << RB;
+  static constexpr int ROUNDS = 16;
+  static constexpr int TILE = RS_THREADS * ROUNDS;
+  static constexpr int PER = BINS / RS_THREADS;  // digits per thread in the per-tile tables
+  static_assert(BINS % RS_THREADS == 0, "whole digits per thread");
+};
+
+template <int RB>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                         int64_t ntiles, int32_t* hist) {
-  __shared__ int s_h[RS_BINS];
+  using C = RsCfg<RB>;
+  __shared__ int s_h[C::BINS];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  s_h[t] = 0;
+  for (int b = t; b < C::BINS; b += RS_THREADS) s_h[b] = 0;
   __syncthreads();
-  const int64_t base = blockIdx.x * (int64_t)RS_TILE + w * (RS_ROUNDS * 64) + lane;
+  const int64_t base = blockIdx.x * (int64_t)C::TILE + w * (C::ROUNDS * 64) + lane;
 #pragma unroll 8
-  for (int r = 0; r < RS_ROUNDS; r++)
-    if (base + r * 64 < n) atomicAdd(&s_h[(keys[base + r * 64] >> shift) & (RS_BINS - 1)], 1);
+  for (int r = 0; r < C::ROUNDS; r++)
+    if (base + r * 64 < n) atomicAdd(&s_h[(keys[base + r * 64] >> shift) & (C::BINS - 1)], 1);
   __syncthreads();
-  hist[(int64_t)t * ntiles + blockIdx.x] = s_h[t];
+  for (int b = t; b < C::BINS; b += RS_THREADS) hist[(int64_t)b * ntiles + blockIdx.x] = s_h[b];
 }
 
 // exclusive scan of one value per thread across the block
@@ -58,41 +68,45 @@ __device__ inline int rs_block_excl(int v, int* s_w) {
   return before + inc - v;
 }
 
+// vin may be null: the values are then the input positions
+template <int RB>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                            const int32_t* __restrict__ vin, uint32_t* kout,
                                                            int32_t* vout, int64_t n, int shift, int64_t ntiles,
                                                            const int32_t* __restrict__ off) {
-  __shared__ int s_cnt[RS_WAVES][RS_BINS];  // running, then starting, tile position of each digit per wave
-  __shared__ int s_start[RS_BINS];          // first tile position of each digit
-  __shared__ int s_out[RS_BINS];            // output offset of each digit's run
+  using C = RsCfg<RB>;
+  __shared__ int s_cnt[RS_WAVES][C::BINS];  // running, then starting, tile position of each digit per wave
+  __shared__ int s_delta[C::BINS];          // output offset of each digit's run minus its tile start
   __shared__ int s_w[RS_WAVES];
-  __shared__ uint32_t s_k[RS_TILE];
-  __shared__ int32_t s_v[RS_TILE];
+  __shared__ uint32_t s_k[C::TILE];
+  __shared__ int32_t s_v[C::TILE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (int b = t; b < C::BINS; b += RS_THREADS) {
 #pragma unroll
-  for (int u = 0; u < RS_WAVES; u++) s_cnt[u][t] = 0;
-  s_out[t] = off[(int64_t)t * ntiles + blockIdx.x];
+    for (int u = 0; u < RS_WAVES; u++) s_cnt[u][b] = 0;
+  }
   __syncthreads();
-  const int64_t tile0 = blockIdx.x * (int64_t)RS_TILE;
-  const int64_t base = tile0 + w * (RS_ROUNDS * 64) + lane;
-  uint32_t k[RS_ROUNDS];
-  int32_t v[RS_ROUNDS];
+  const int64_t tile0 = blockIdx.x * (int64_t)C::TILE;
+  const int64_t base = tile0 + w * (C::ROUNDS * 64) + lane;
+  uint32_t k[C::ROUNDS];
+  int32_t v[C::ROUNDS];
 #pragma unroll
-  for (int r = 0; r < RS_ROUNDS; r++) {
-    const bool ok = base + r * 64 < n;
-    k[r] = ok ? kin[base + r * 64] : 0u;
-    v[r] = ok ? vin[base + r * 64] : 0;
+  for (int r = 0; r < C::ROUNDS; r++) {
+    const int64_t i = base + r * 64;
+    const bool ok = i < n;
+    k[r] = ok ? kin[i] : 0u;
+    v[r] = ok ? (vin ? vin[i] : (int32_t)i) : 0;
   }
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const unsigned long long above = lane == 63 ? 0ull : (~0ull << (lane + 1));
-  int pos[RS_ROUNDS];
+  int pos[C::ROUNDS];
 #pragma unroll
-  for (int r = 0; r < RS_ROUNDS; r++) {
+  for (int r = 0; r < C::ROUNDS; r++) {
     const bool ok = base + r * 64 < n;
-    const int d = (int)((k[r] >> shift) & (RS_BINS - 1));
+    const int d = (int)((k[r] >> shift) & (C::BINS - 1));
     unsigned long long peers = __ballot(ok);
 #pragma unroll
-    for (int b = 0; b < 8; b++) {
+    for (int b = 0; b < RB; b++) {
       const unsigned long long m = __ballot((d >> b) & 1);
       peers &= ((d >> b) & 1) ? m : ~m;
     }
@@ -104,37 +118,44 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
   }
   __syncthreads();
   {
-    // digit t: its start in the tile (digit order), then each wave's start
-    int c[RS_WAVES], tot = 0;
+    // digits t * PER .. t * PER + PER - 1: their starts in the tile (digit
+    // order), each wave's start, and where their runs go
+    int tot[C::PER], sum = 0;
 #pragma unroll
-    for (int u = 0; u < RS_WAVES; u++) {
-      c[u] = s_cnt[u][t];
-      tot += c[u];
+    for (int q = 0; q < C::PER; q++) {
+      tot[q] = 0;
+#pragma unroll
+      for (int u = 0; u < RS_WAVES; u++) tot[q] += s_cnt[u][t * C::PER + q];
+      sum += tot[q];
     }
-    int acc = rs_block_excl(tot, s_w);
-    s_start[t] = acc;
+    int acc = rs_block_excl(sum, s_w);
 #pragma unroll
-    for (int u = 0; u < RS_WAVES; u++) {
-      s_cnt[u][t] = acc;
-      acc += c[u];
+    for (int q = 0; q < C::PER; q++) {
+      const int d = t * C::PER + q;
+      s_delta[d] = off[(int64_t)d * ntiles + blockIdx.x] - acc;
+#pragma unroll
+      for (int u = 0; u < RS_WAVES; u++) {
+        const int c = s_cnt[u][d];
+        s_cnt[u][d] = acc;
+        acc += c;
+      }
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < RS_ROUNDS; r++) {
+  for (int r = 0; r < C::ROUNDS; r++) {
     if (base + r * 64 < n) {
-      const int p = s_cnt[w][(k[r] >> shift) & (RS_BINS - 1)] + pos[r];
+      const int p = s_cnt[w][(k[r] >> shift) & (C::BINS - 1)] + pos[r];
       s_k[p] = k[r];
       s_v[p] = v[r];
     }
   }
   __syncthreads();
   // the tile in digit order: position j of digit d goes to that digit's run
-  const int tn = (int)(n - tile0 < RS_TILE ? n - tile0 : RS_TILE);
+  const int tn = (int)(n - tile0 < C::TILE ? n - tile0 : C::TILE);
   for (int j = t; j < tn; j += RS_THREADS) {
     const uint32_t key = s_k[j];
-    const int d = (int)((key >> shift) & (RS_BINS - 1));
-    const int64_t p = (int64_t)s_out[d] + (j - s_start[d]);
+    const int64_t p = (int64_t)s_delta[(key >> shift) & (C::BINS - 1)] + j;
     kout[p] = key;
     vout[p] = s_v[j];
   }
@@ -142,27 +163,39 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
 
 namespace {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
-int64_t rs_tiles(int64_t n) { return (n + RS_TILE - 1) / RS_TILE; }
+
+constexpr int RS_RB = 8;  // digit bits per pass
+
+void rs_plan(int bits, int& passes, int& rb) {
+  rb = RS_RB;
+  passes = (bits + RS_RB - 1) / RS_RB;
+}
+
+int64_t rs_tile(int) { return RsCfg<RS_RB>::TILE; }
 }  // namespace
 
 // temporary storage: the other key and value buffers, the digit-major tile
 // histogram and its scan's temporaries
 size_t sort_pairs_tmp_bytes(int64_t n, int bits) {
   if (n < 0 || bits <= 0 || bits > 32) return 0;
-  const int64_t h = RS_BINS * rs_tiles(n);
+  int passes, rb;
+  rs_plan(bits, passes, rb);
+  const int64_t h = ((int64_t)1 << rb) * ((n + rs_tile(rb) - 1) / rs_tile(rb));
   return al(sizeof(uint32_t) * (size_t)n) + al(sizeof(int32_t) * (size_t)n) + al(sizeof(int32_t) * (size_t)h) +
          al(sizeof(int32_t) * (size_t)scan_tmp_ints(h)) + 256;
 }
 
-// keys_in/vals_in are read only; the result lands in keys_out/vals_out, which
-// must not overlap the inputs. Offsets are int32: n < 2^31.
+// keys_in/vals_in are read only (vals_in null: the values are 0, 1, ..., n-1);
+// the result lands in keys_out/vals_out, which must not overlap the inputs.
+// Offsets are int32: n < 2^31.
 hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint32_t* keys_out,
                       const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (n < 0 || n >= INT32_MAX || bits <= 0 || bits > 32 || !tmp || tmp_bytes < sort_pairs_tmp_bytes(n, bits))
     return hipErrorInvalidValue;
-  const int64_t ntiles = rs_tiles(n), h = RS_BINS * ntiles;
-  if (ntiles > INT32_MAX) return hipErrorInvalidValue;
+  int passes, rb;
+  rs_plan(bits, passes, rb);
+  const int64_t ntiles = (n + rs_tile(rb) - 1) / rs_tile(rb), h = ((int64_t)1 << rb) * ntiles;
   char* p = (char*)tmp;
   uint32_t* kalt = (uint32_t*)p;
   p += al(sizeof(uint32_t) * (size_t)n);
@@ -171,7 +204,6 @@ hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint
   int32_t* hist = (int32_t*)p;
   p += al(sizeof(int32_t) * (size_t)h);
   int32_t* scan_tmp = (int32_t*)p;
-  const int passes = (bits + 7) / 8;
   const uint32_t* ks = keys_in;
   const int32_t* vs = vals_in;
   for (int q = 0; q < passes; q++) {
@@ -180,10 +212,12 @@ hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint
     const bool to_out = ((passes - 1 - q) & 1) == 0;
     uint32_t* kd = to_out ? keys_out : kalt;
     int32_t* vd = to_out ? vals_out : valt;
-    k_rs_hist<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ks, n, 8 * q, ntiles, hist);
+    const int shift = rb * q;
+    const unsigned g = (unsigned)ntiles;
+    k_rs_hist<RS_RB><<<g, RS_THREADS, 0, s>>>(ks, n, shift, ntiles, hist);
     hipError_t e = exclusive_scan(hist, hist, h, scan_tmp, nullptr, nullptr, s);
     if (e != hipSuccess) return e;
-    k_rs_scatter<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ks, vs, kd, vd, n, 8 * q, ntiles, hist);
+    k_rs_scatter<RS_RB><<<g, RS_THREADS, 0, s>>>(ks, vs, kd, vd, n, shift, ntiles, hist);
     ks = kd;
     vs = vd;
   }

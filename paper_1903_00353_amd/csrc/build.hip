@@ -36,20 +36,12 @@ __global__ void k_zero_i64(int64_t* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-__global__ void k_check_verts(const float* __restrict__ V, int64_t nv, int64_t* stats) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= 3 * nv) return;
-  if (!isfinite(V[i])) atomicOr(err_word(stats), ERR_NONFINITE);
-}
-
 // Per face: its mesh, index range and repeated-corner checks, global indices. A
 // face with a bad index is replaced by three copies of its mesh's first vertex so
 // that every later access stays in bounds (the build then reports the error).
-__global__ void k_globalize(const int32_t* __restrict__ T, int64_t nf, const int32_t* __restrict__ f_off,
-                            const int32_t* __restrict__ v_off, int n_meshes, int32_t* tg, int32_t* face_mesh,
-                            int64_t* stats) {
-  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (f >= nf) return;
+__device__ inline void globalize_face(const int32_t* __restrict__ T, int64_t f, const int32_t* __restrict__ f_off,
+                                      const int32_t* __restrict__ v_off, int n_meshes, int32_t* tg,
+                                      int32_t* face_mesh, int32_t* owned, int64_t* stats) {
   const int m = find_segment(f_off, n_meshes + 1, f);
   const int32_t nvm = v_off[m + 1] - v_off[m], vo = v_off[m];
   int32_t a = T[3 * f], b = T[3 * f + 1], c = T[3 * f + 2];
@@ -63,13 +55,44 @@ __global__ void k_globalize(const int32_t* __restrict__ T, int64_t nf, const int
   tg[3 * f + 1] = b + vo;
   tg[3 * f + 2] = c + vo;
   face_mesh[f] = m;
+  // half-edge u -> w numbers its edge when u < w
+  owned[3 * f] = a < b ? 1 : 0;
+  owned[3 * f + 1] = b < c ? 1 : 0;
+  owned[3 * f + 2] = c < a ? 1 : 0;
 }
 
-__global__ void k_vert_mesh(int64_t nv, const int32_t* __restrict__ v_off, int n_meshes, int32_t* vert_mesh) {
-  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v < nv) vert_mesh[v] = find_segment(v_off, n_meshes + 1, v);
+// the input passes in one launch: finite coordinates (thread i < 3 nv); global
+// indices and owned half-edges of face i < nf; mesh of vertex i < nv
+__global__ void k_inputs(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ T, int64_t nf,
+                         const int32_t* __restrict__ f_off, const int32_t* __restrict__ v_off, int n_meshes,
+                         int32_t* tg, int32_t* face_mesh, int32_t* owned, int32_t* vert_mesh, int64_t* stats) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < 3 * nv && !isfinite(V[i])) atomicOr(err_word(stats), ERR_NONFINITE);
+  if (i < nf) globalize_face(T, i, f_off, v_off, n_meshes, tg, face_mesh, owned, stats);
+  if (i < nv) vert_mesh[i] = find_segment(v_off, n_meshes + 1, i);
 }
 
+struct FillJob {
+  int32_t* p;
+  int64_t n;
+  int32_t v;
+};
+
+// three fills in one launch, over the concatenated ranges
+__global__ void k_fill3(FillJob a, FillJob b, FillJob c) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < a.n) {
+    a.p[i] = a.v;
+    return;
+  }
+  i -= a.n;
+  if (i < b.n) {
+    b.p[i] = b.v;
+    return;
+  }
+  i -= b.n;
+  if (i < c.n) c.p[i] = c.v;
+}
 
 // Segment offsets of the corners sorted by vertex: off[v] = first position whose
 // vertex is >= v (vertices without corners get empty segments), off[nv] = nh.
@@ -147,12 +170,6 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
   vinfo[v] = make_float4((float)cl.axis.x, (float)cl.axis.y, (float)cl.axis.z, cf);
   vbits[v] = cl.bits;
   count[v] = ((cl.bits & V_POS) ? 1 : 0) + ((cl.bits & V_NEG) ? 1 : 0);
-}
-
-__global__ void k_owned(const int32_t* __restrict__ T, int64_t nh, int32_t* flag) {
-  int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (h >= nh) return;
-  flag[h] = T[h] < T[next_corner((int32_t)h)] ? 1 : 0;
 }
 
 // Edge records from the owned half-edges (u -> w with u < w) and, for each edge,
@@ -586,10 +603,10 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   const int64_t nh = 3 * tf, ne = te;
   // 1. inputs: finite coordinates, per-mesh index ranges, global indices
   k_zero_i64<<<1, 64, 0, s>>>(F->d_stats, ST_COUNT);
-  k_check_verts<<<grid_1d(3 * tv, B), B, 0, s>>>(verts_d, tv, F->d_stats);
-  k_globalize<<<grid_1d(tf, B), B, 0, s>>>(tris_d, tf, F->f_off, F->v_off, n_meshes, F->tris_g, F->face_mesh,
-                                            F->d_stats);
-  k_vert_mesh<<<grid_1d(tv, B), B, 0, s>>>(tv, F->v_off, n_meshes, F->vert_mesh);
+  // (the owned half-edge flags wait in face_edges, which k_edges fills later)
+  k_inputs<<<grid_1d(3 * tv > tf ? 3 * tv : tf, B), B, 0, s>>>(verts_d, tv, tris_d, tf, F->f_off, F->v_off, n_meshes,
+                                                               F->tris_g, F->face_mesh, F->face_edges,
+                                                               F->vert_mesh, F->d_stats);
   const int32_t* T = F->tris_g;
   // 2. vertex -> corner table: corners sorted by vertex (stable: each vertex's
   // corners in ascending order), then the segment starts
@@ -602,11 +619,12 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                                         F->vbits, F->t_c, F->d_stats);
   CK(exclusive_scan(F->t_c, F->t_c, tv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
   k_vertex_queue<<<grid_1d(tv, B), B, 0, s>>>(F->vbits, tv, F->t_c, F->vpoly);
-  k_owned<<<grid_1d(nh, B), B, 0, s>>>(T, nh, F->t_b);
-  k_fill_i32<<<grid_1d(4 * (ne + 1), B), B, 0, s>>>((int32_t*)F->edges, 4 * (ne + 1), -1);
-  k_fill_i32<<<grid_1d(ne, B), B, 0, s>>>(F->t_c, ne, 0);
-  k_fill_i32<<<grid_1d((ne + 3) / 4, B), B, 0, s>>>((int32_t*)F->edge_cls, (ne + 3) / 4, 0);
-  CK(exclusive_scan(F->t_b, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
+  {
+    const FillJob a = {(int32_t*)F->edges, 4 * (ne + 1), -1}, b = {F->t_c, ne, 0},
+                  c = {(int32_t*)F->edge_cls, (ne + 3) / 4, 0};
+    k_fill3<<<grid_1d(a.n + b.n + c.n, B), B, 0, s>>>(a, b, c);
+  }
+  CK(exclusive_scan(F->face_edges, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
   // edges with their classes and extrusion sides
   k_edges<<<grid_1d(nh, B), B, 0, s>>>(verts_d, T, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->edges,
                                        F->face_edges, F->edge_cls, F->t_c);

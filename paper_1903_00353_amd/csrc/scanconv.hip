@@ -855,7 +855,7 @@ WsLayout ws_layout(const csc_features* f, int64_t cap) {
   L.big = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(cap + 1));
   int64_t mx = f->nf > 2 * f->ne ? f->nf : 2 * f->ne;
   mx = mx > 2 * f->nv ? mx : 2 * f->nv;
-  L.boff = L.big + au(sizeof(int32_t) * (size_t)(mx + 2));
+  L.boff = L.big + au(sizeof(int32_t) * (size_t)(mx + 4));
   L.ctr = L.boff + au(sizeof(int64_t) * (size_t)(f->n_meshes + 1));
   L.total = L.ctr + au(8 * sizeof(unsigned long long));
   return L;
@@ -906,7 +906,6 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
 
 template <int KIND>
 void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s) {
-  k_zero_i32<<<1, 64, 0, s>>>(A.big_count, 1);
   {
     StageTimer t(stage, s);
     k_scan_small<KIND><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
@@ -916,16 +915,19 @@ void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s) {
 }
 
 // key initialisation and the scan launches of the three kinds; counters
-// (3 slots) may be null; big: overflow list (count, then items)
+// (3 slots) may be null; big: overflow lists (the three kinds' counts, a
+// fourth slot for alignment, then the items, shared: each kind's overflow
+// pass ends before the next kind's small pass fills it)
 void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, unsigned long long* counters,
                int32_t* big, hipStream_t s) {
   {
     StageTimer t(TS_INIT, s);
     k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap);
+    k_zero_i32<<<1, 64, 0, s>>>(big, 3);
   }
   ScanArgs A = scan_args(f, keys, cap);
   A.big_count = big;
-  A.big_items = big + 1;
+  A.big_items = big + 4;
   A.counter = counters;
   A.n_items = f->nf;
   A.small_rows = f->opt.small_rows[0];
@@ -937,6 +939,7 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.n_items = 2 * f->ne;
   A.n_items_d = &f->d_stats[ST_NEPOLY];
   A.counter = counters ? counters + 1 : nullptr;
+  A.big_count = big + 1;
   launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, TS_SCAN_EDGE_BIG, s);
   A.small_rows = f->opt.small_rows[2];
   A.per_cell = f->opt.scan_mode == 1;
@@ -944,6 +947,7 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.n_items = 2 * f->nv;
   A.n_items_d = &f->d_stats[ST_NVPOLY];
   A.counter = counters ? counters + 2 : nullptr;
+  A.big_count = big + 2;
   launch_kind<KIND_VERT>(A, TS_SCAN_VERT, TS_SCAN_VERT_BIG, s);
 }
 

@@ -276,29 +276,50 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
       }
 }
 
-// class statistics: one LDS histogram per block, one global add per bin and block
+// class statistics: each thread counts 16 edge-class bytes and 4 vertex words per
+// 16-byte load (both arrays start 256-byte aligned), one LDS histogram per
+// block, one global add per bin and block
+__device__ inline void count_edge_class(int c, int (&loc)[9]) {
+  c &= 3;
+  loc[0] += c == EDGE_CONVEX;
+  loc[1] += c == EDGE_CONCAVE;
+  loc[2] += c == EDGE_FLAT;
+  loc[3] += c == EDGE_UNKNOWN;
+}
+__device__ inline void count_vertex_class(uint32_t b, int (&loc)[9]) {
+  loc[4] += (b & V_CONVEX) != 0;
+  loc[5] += (b & V_CONCAVE) != 0;
+  loc[6] += (b & V_FLAT) != 0;
+  loc[7] += (b & V_SADDLE) != 0;
+  loc[8] += (b & V_RUFF) != 0;
+}
+
 __global__ __launch_bounds__(256) void k_class_stats(const uint8_t* __restrict__ ecls, int64_t ne,
                                                      const uint32_t* __restrict__ vbits, int64_t nv, int64_t* stats) {
   __shared__ int h[16];
   if (threadIdx.x < 16) h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
   int loc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ne; i += stride) {
-    int c = ecls[i] & 3;
-    loc[0] += c == EDGE_CONVEX;
-    loc[1] += c == EDGE_CONCAVE;
-    loc[2] += c == EDGE_FLAT;
-    loc[3] += c == EDGE_UNKNOWN;
+  const uint4* e16 = reinterpret_cast<const uint4*>(ecls);
+  for (int64_t i = t0; i < ne / 16; i += stride) {
+    const uint4 x = e16[i];
+    const uint32_t wv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+      for (int k = 0; k < 4; k++) count_edge_class((int)((wv[q] >> (8 * k)) & 0xffu), loc);
   }
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += stride) {
-    uint32_t b = vbits[i];
-    loc[4] += (b & V_CONVEX) != 0;
-    loc[5] += (b & V_CONCAVE) != 0;
-    loc[6] += (b & V_FLAT) != 0;
-    loc[7] += (b & V_SADDLE) != 0;
-    loc[8] += (b & V_RUFF) != 0;
+  for (int64_t i = ne / 16 * 16 + t0; i < ne; i += stride) count_edge_class(ecls[i], loc);
+  const uint4* v4 = reinterpret_cast<const uint4*>(vbits);
+  for (int64_t i = t0; i < nv / 4; i += stride) {
+    const uint4 x = v4[i];
+    count_vertex_class(x.x, loc);
+    count_vertex_class(x.y, loc);
+    count_vertex_class(x.z, loc);
+    count_vertex_class(x.w, loc);
   }
+  for (int64_t i = nv / 4 * 4 + t0; i < nv; i += stride) count_vertex_class(vbits[i], loc);
 #pragma unroll
   for (int k = 0; k < 9; k++) {
     int x = loc[k];
@@ -634,7 +655,11 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                             F->d_stats);
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
-  k_class_stats<<<256, 256, 0, s>>>(F->edge_cls, ne, F->vbits, tv, F->d_stats);
+  {
+    const int64_t items = (ne / 16 > tv / 4 ? ne / 16 : tv / 4) + 1;
+    k_class_stats<<<grid_1d(items < 1024 * 256 ? items : 1024 * 256, 256), 256, 0, s>>>(F->edge_cls, ne, F->vbits,
+                                                                                       tv, F->d_stats);
+  }
   // 5. band bricks
   CK(exclusive_scan(F->t_b, F->brick_index, tb, F->t_scan, &F->d_stats[ST_NBRICKS], nullptr, s));
   k_brick_fix<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, F->brick_index, F->brick_list, F->brick_mesh, F->brick_base,

@@ -57,6 +57,12 @@ def test_config_parity(configs, k):
     v, f = meshes[0]
     rep, feats, band, om, o = check(v, f, grids[0])
     assert_parity(rep)
+    # class statistics: every edge has exactly one class, every vertex with a
+    # fan at most one of convex / concave / flat / saddle
+    inf = feats.info()
+    assert sum(inf[c] for c in ("edges_convex", "edges_concave", "edges_flat", "edges_unknown")) == inf["n_edges"]
+    nv_cls = sum(inf[c] for c in ("vertices_convex", "vertices_concave", "vertices_flat", "vertices_saddle"))
+    assert 0 < nv_cls <= inf["n_vertices"]
 
 
 def test_large_sphere_sampled_planes(configs):

@@ -376,30 +376,44 @@ __device__ inline unsigned long long pack_cand(int lane, int t, int du, int dv) 
          (unsigned long long)dv;
 }
 
+// a value of the polyhedron held by lane L. With UNI every lane holds the same
+// polyhedron (the overflow pass): the value is read from the first active lane,
+// a scalar broadcast instead of an LDS permutation. (Taking the lane's own value
+// directly would let the compiler fuse the setup arithmetic into the distance
+// arithmetic and round differently from the one-lane-per-polyhedron pass.)
+__device__ inline int first_lane(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline float first_lane(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+
+template <bool UNI, typename T>
+__device__ inline T from_lane(T x, int L) {
+  if constexpr (UNI) return first_lane(x);
+  else return __shfl(x, L, 64);
+}
+
 // exact distance of one queued candidate and its packed atomic minimum; called by
 // all lanes of the wavefront together (lane permutations), `valid` per lane
-template <int KIND>
+template <int KIND, bool UNI>
 __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned long long ent, bool valid,
                                    BrickCache& bc, unsigned& issued) {
   const int L = valid ? (int)(ent >> 48) : 0;
   const int t = (int)((ent >> 32) & 0xffff), du = (int)((ent >> 16) & 0xffff), dv = (int)(ent & 0xffff);
-  const int mesh = __shfl(q.mesh, L, 64), id = __shfl(q.id, L, 64);
-  const int axes = __shfl(q.ra | (q.ua << 2), L, 64);
-  const int ax = __shfl(q.anc.x, L, 64), ay = __shfl(q.anc.y, L, 64), az = __shfl(q.anc.z, L, 64);
-  const f3 g0 = mk(__shfl(q.g[0], L, 64), __shfl(q.g[1], L, 64), __shfl(q.g[2], L, 64));
+  const int mesh = from_lane<UNI>(q.mesh, L), id = from_lane<UNI>(q.id, L);
+  const int axes = from_lane<UNI>(q.ra | (q.ua << 2), L);
+  const int ax = from_lane<UNI>(q.anc.x, L), ay = from_lane<UNI>(q.anc.y, L), az = from_lane<UNI>(q.anc.z, L);
+  const f3 g0 = mk(from_lane<UNI>(q.g[0], L), from_lane<UNI>(q.g[1], L), from_lane<UNI>(q.g[2], L));
   f3 g1 = mk(0.f, 0.f, 0.f), g2 = mk(0.f, 0.f, 0.f), nn = mk(0.f, 0.f, 0.f);
   float side = 1.f;
   if constexpr (KIND == KIND_FACE) {
-    g1 = mk(__shfl(q.g[3], L, 64), __shfl(q.g[4], L, 64), __shfl(q.g[5], L, 64));
-    g2 = mk(__shfl(q.g[6], L, 64), __shfl(q.g[7], L, 64), __shfl(q.g[8], L, 64));
-    nn = mk(__shfl(q.cone[0], L, 64), __shfl(q.cone[1], L, 64), __shfl(q.cone[2], L, 64));
+    g1 = mk(from_lane<UNI>(q.g[3], L), from_lane<UNI>(q.g[4], L), from_lane<UNI>(q.g[5], L));
+    g2 = mk(from_lane<UNI>(q.g[6], L), from_lane<UNI>(q.g[7], L), from_lane<UNI>(q.g[8], L));
+    nn = mk(from_lane<UNI>(q.cone[0], L), from_lane<UNI>(q.cone[1], L), from_lane<UNI>(q.cone[2], L));
   } else if constexpr (KIND == KIND_EDGE) {
-    g1 = mk(__shfl(q.g[3], L, 64), __shfl(q.g[4], L, 64), __shfl(q.g[5], L, 64));
-    nn = mk(__shfl(q.pl[4][0], L, 64), __shfl(q.pl[4][1], L, 64), __shfl(q.pl[4][2], L, 64));
-    side = __shfl(q.side, L, 64);
+    g1 = mk(from_lane<UNI>(q.g[3], L), from_lane<UNI>(q.g[4], L), from_lane<UNI>(q.g[5], L));
+    nn = mk(from_lane<UNI>(q.pl[4][0], L), from_lane<UNI>(q.pl[4][1], L), from_lane<UNI>(q.pl[4][2], L));
+    side = from_lane<UNI>(q.side, L);
   } else {
-    nn = mk(__shfl(q.cone[0], L, 64), __shfl(q.cone[1], L, 64), __shfl(q.cone[2], L, 64));
-    side = __shfl(q.side, L, 64);
+    nn = mk(from_lane<UNI>(q.cone[0], L), from_lane<UNI>(q.cone[1], L), from_lane<UNI>(q.cone[2], L));
+    side = from_lane<UNI>(q.side, L);
   }
   if (!valid) return;
   const MeshDesc& G = P.md[mesh];
@@ -462,29 +476,29 @@ __device__ inline int wave_incl_sum(int v) {
 // the row coefficients of the polyhedron held by lane L, fetched by lane
 // permutation (with the row-axis slopes when each cell is tested on its own);
 // called by all lanes together
-template <int KIND>
+template <int KIND, bool UNI>
 __device__ inline Rows rows_of(const Rows& r, int L, bool per_cell) {
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
   Rows o;
 #pragma unroll
   for (int i = 0; i < NPL; i++) {
-    o.inv[i] = __shfl(r.inv[i], L, 64);
-    o.su[i] = __shfl(r.su[i], L, 64);
-    o.sv[i] = __shfl(r.sv[i], L, 64);
-    o.k[i] = __shfl(r.k[i], L, 64);
+    o.inv[i] = from_lane<UNI>(r.inv[i], L);
+    o.su[i] = from_lane<UNI>(r.su[i], L);
+    o.sv[i] = from_lane<UNI>(r.sv[i], L);
+    o.k[i] = from_lane<UNI>(r.k[i], L);
   }
   if (per_cell) {
 #pragma unroll
-    for (int i = 0; i < NPL; i++) o.sl[i] = __shfl(r.sl[i], L, 64);
+    for (int i = 0; i < NPL; i++) o.sl[i] = from_lane<UNI>(r.sl[i], L);
   }
-  o.nt = __shfl(r.nt, L, 64);
+  o.nt = from_lane<UNI>(r.nt, L);
   if constexpr (KIND == KIND_VERT) {
-    o.A[0] = __shfl(r.A[0], L, 64);
-    o.A[1] = __shfl(r.A[1], L, 64);
-    o.A[2] = __shfl(r.A[2], L, 64);
-    o.R2 = __shfl(r.R2, L, 64);
-    o.hf = __shfl(r.hf, L, 64);
-    o.ihf = __shfl(r.ihf, L, 64);
+    o.A[0] = from_lane<UNI>(r.A[0], L);
+    o.A[1] = from_lane<UNI>(r.A[1], L);
+    o.A[2] = from_lane<UNI>(r.A[2], L);
+    o.R2 = from_lane<UNI>(r.R2, L);
+    o.hf = from_lane<UNI>(r.hf, L);
+    o.ihf = from_lane<UNI>(r.ihf, L);
   }
   return o;
 }
@@ -511,7 +525,7 @@ __device__ inline bool cell_in(const Rows& o, int t, int du, int dv) {
 // coefficients, and queues its candidate cells in ring `qb` (this wavefront's
 // own) under the owner's lane number. Lanes with many rows thus no longer hold
 // up the others. Must be called by all lanes of the wavefront.
-template <int KIND>
+template <int KIND, bool UNI>
 __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Rows& r, int rows,
                                       unsigned long long* qb, unsigned& issued) {
   const int lane = threadIdx.x & 63;
@@ -522,18 +536,20 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
   for (int base = 0; base < total; base += 64) {
     const int g = base + lane;
     int lo = 0, hi = 63;  // the last lane whose rows start at or before g
+    if constexpr (!UNI) {
 #pragma unroll
-    for (int s = 0; s < 6; s++) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (__shfl(excl, mid, 64) <= g) lo = mid;
-      else hi = mid - 1;
+      for (int s = 0; s < 6; s++) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__shfl(excl, mid, 64) <= g) lo = mid;
+        else hi = mid - 1;
+      }
     }
-    const int L = lo;
-    const int rloc = g - __shfl(excl, L, 64), nuL = __shfl(q.nu, L, 64);
+    const int L = lo;  // with UNI lane 0 owns every row
+    const int rloc = UNI ? g : g - __shfl(excl, L, 64), nuL = from_lane<UNI>(q.nu, L);
     const int nud = nuL > 0 ? nuL : 1;  // past the last row L may hold no polyhedron
     const int dv = g < total ? rloc / nud : 0, du = g < total ? rloc - dv * nud : 0;
     int t = 0, t1 = -1;
-    const Rows o = rows_of<KIND>(r, L, P.per_cell);
+    const Rows o = rows_of<KIND, UNI>(r, L, P.per_cell);
     if (P.per_cell) {  // every cell of the row, each tested by itself below
       t = 0;
       t1 = o.nt - 1;
@@ -546,12 +562,12 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
     [[maybe_unused]] float cct = -2.f, chf = 0.f, ceps = 0.f;
     [[maybe_unused]] int cra = 0, cua = 0;
     if constexpr (KIND == KIND_VERT) {
-      cg = mk(__shfl(q.g[0], L, 64), __shfl(q.g[1], L, 64), __shfl(q.g[2], L, 64));
-      cax = mk(__shfl(q.cone[0], L, 64), __shfl(q.cone[1], L, 64), __shfl(q.cone[2], L, 64));
-      cct = __shfl(q.cone[3], L, 64);
-      chf = __shfl(r.hf, L, 64);
-      ceps = __shfl(r.eps, L, 64);
-      const int ax = __shfl(q.ra | (q.ua << 2), L, 64);
+      cg = mk(from_lane<UNI>(q.g[0], L), from_lane<UNI>(q.g[1], L), from_lane<UNI>(q.g[2], L));
+      cax = mk(from_lane<UNI>(q.cone[0], L), from_lane<UNI>(q.cone[1], L), from_lane<UNI>(q.cone[2], L));
+      cct = from_lane<UNI>(q.cone[3], L);
+      chf = from_lane<UNI>(r.hf, L);
+      ceps = from_lane<UNI>(r.eps, L);
+      const int ax = from_lane<UNI>(q.ra | (q.ua << 2), L);
       cra = ax & 3;
       cua = ax >> 2;
     }
@@ -578,7 +594,7 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const unsigned long long e = qb[(head + lane) & (QCAP - 1)];
-        finish_cand<KIND>(P, q, e, true, bc, issued);
+        finish_cand<KIND, UNI>(P, q, e, true, bc, issued);
         head += 64;
       }
     }
@@ -589,7 +605,7 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const bool valid = (uint32_t)lane < tail - head;
     const unsigned long long e = valid ? qb[(head + lane) & (QCAP - 1)] : 0ull;
-    finish_cand<KIND>(P, q, e, valid, bc, issued);
+    finish_cand<KIND, UNI>(P, q, e, valid, bc, issued);
   }
   // the ring is reused by the next call: finish its reads first
   __builtin_amdgcn_wave_barrier();
@@ -629,7 +645,7 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   unsigned issued = 0;
   Rows r = {};
   if (nc > 0 && !big) setup_rows<KIND>(q, P.md[q.mesh], r);
-  scan_rows_wave<KIND>(P, q, r, nc > 0 && !big ? rows : 0, s_q[threadIdx.x >> 6], issued);
+  scan_rows_wave<KIND, false>(P, q, r, nc > 0 && !big ? rows : 0, s_q[threadIdx.x >> 6], issued);
   add_issued(P, issued, 0);
 }
 
@@ -646,7 +662,7 @@ __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
     if (build_poly<KIND>(P, P.big_items[w], q) <= 0) continue;  // the same for every lane
     Rows r;
     setup_rows<KIND>(q, P.md[q.mesh], r);
-    scan_rows_wave<KIND>(P, q, r, lane == 0 ? q.nu * q.nv : 0, s_q, issued);  // lane 0 owns every row
+    scan_rows_wave<KIND, true>(P, q, r, lane == 0 ? q.nu * q.nv : 0, s_q, issued);  // lane 0 owns every row
   }
   add_issued(P, issued, 3);
 }

@@ -232,8 +232,11 @@ int csc_scan_convert_batched(const csc_features* f, void* workspace_d, size_t ws
  * barycentric weights of q on the feature's vertices, SDF = s |c - q| and
  * dSDF/dx_k = -s w_k (c - q) / |c - q| (the closest feature is held fixed);
  * grad_verts_d[k] += grad_sdf_d[c] * dSDF/dx_k. Cells at zero distance add
- * nothing. grad_verts_d: float32 [nv][3], accumulated (not cleared); the sum
- * order of the float atomics varies from run to run.
+ * nothing. grad_verts_d: float32 [nv][3], accumulated (not cleared). Terms
+ * are first summed per block in 64-bit fixed point (exactly, for terms within
+ * 2^-17 .. 4 times the block's first chunk's largest |grad_sdf|); those sums
+ * and the other terms reach grad_verts_d through float atomics, whose order
+ * varies from run to run.
  * n_band: number of band cells, or (with n_band_d) an upper bound on it.
  * n_band_d: NULL, or the device int64 written by csc_scan_convert; the count is
  * then read on the device, so no host synchronisation is needed in between.

@@ -201,7 +201,11 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
   int gexp = 0;
   (void)frexpf(gmax, &gexp);  // gmax < 2^gexp
   const int fx = 40 - gexp;
+  // the mesh of this thread's first cell; a thread past the end of the band
+  // (whose cells are never used) takes the last mesh, so that every descriptor
+  // and offset it reads exists
   int m = P.band_off ? find_segment(P.band_off, P.n_meshes + 1, c0 + threadIdx.x) : 0;
+  if (m > P.n_meshes - 1) m = P.n_meshes - 1;
   BwMesh M = load_mesh(P, m);
   for (int64_t base = c0; base < c1; base += BW_THREADS) {
     const int64_t i = base + threadIdx.x;

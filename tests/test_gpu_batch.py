@@ -48,6 +48,32 @@ def test_batch_equals_single_mesh_runs(graph_safe):
         assert_same_sums(g1, g2, scale, m)
 
 
+def test_batch_with_empty_bands():
+    """Meshes whose grid holds none of their band (moved far outside it) between
+    ordinary ones: their bricks, band and gradient are empty, and every other
+    mesh still equals its single-mesh run (empty offset segments in the brick
+    marking, the band offsets and the adjoint's walk over the meshes)."""
+    meshes, grids = small_batch(5)
+    far = [1, 3]
+    for m in far:
+        v, f = meshes[m]
+        meshes[m] = (v + np.float32(50.0), f)
+    print("[case] batch of", len(meshes), "with empty bands", far, flush=True)
+    B = P.Batch(meshes, grids)
+    B.step()
+    B.check()
+    for m, (v, f) in enumerate(meshes):
+        c2, s2, f2 = batch_band(B, m)
+        g2 = B.grad(m).cpu().numpy()
+        if m in far:
+            assert c2.size == 0 and not np.any(g2)
+            continue
+        c1, s1, f1, g1 = single(v, f, grids[m])
+        assert np.array_equal(c1, c2) and np.array_equal(s1, s2) and np.array_equal(f1, f2), m
+        scale = vertex_term_scale(f, oracle.OracleMesh(v, f).edges, v.shape[0], f1, 2.0 * s1)
+        assert_same_sums(g1, g2, scale, m)
+
+
 def test_full_batch_against_oracle(configs):
     name, meshes, grids = configs(4)
     B = P.Batch(meshes, grids, backward=False)

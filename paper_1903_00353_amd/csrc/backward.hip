@@ -190,7 +190,8 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
   // summed exactly in 64-bit integers (a slot gets fewer than 2^20 terms between
   // flushes: no overflow), in any order. Terms outside that window (tiny, much
   // larger than the first chunk's, or non-finite) are added to the gradient as
-  // floats, so the scale only decides speed, never the result.
+  // floats: the scale decides which terms are summed exactly and how fast, not
+  // whether the sum is right.
   float gmax = 0.f;
   if (c0 + threadIdx.x < c1) gmax = fmax_finite(0.f, P.gsdf[c0 + threadIdx.x]);
   gmax = wave_max(gmax);

@@ -67,8 +67,12 @@ extern "C" int csc_features_info(const csc_features* f, csc_feature_info* info) 
 
 extern "C" void csc_features_free(csc_features* f) {
   if (!f) return;
+  if (f->side) (void)hipStreamSynchronize(f->side);
   if (f->arena) (void)hipFree(f->arena);
   if (f->h_stats) (void)hipHostFree(f->h_stats);
+  if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
+  if (f->ev_join) (void)hipEventDestroy(f->ev_join);
+  if (f->side) (void)hipStreamDestroy(f->side);
   delete f;
 }
 

@@ -389,8 +389,8 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 enum {
   L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FN, L_FV, L_ECLS,
-  L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_STATS,
-  L_SORT, L_N
+  L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_BFLAG,
+  L_TSCAN2, L_STATS, L_SORT, L_N
 };
 
 struct Layout {
@@ -425,6 +425,8 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_FIRST] = sizeof(int32_t) * (size_t)(n_meshes + 1);
   sz[L_TA] = sz[L_TB] = sz[L_TC] = sizeof(int32_t) * (size_t)(big + 1);
   sz[L_TSCAN] = sizeof(int32_t) * (size_t)scan_tmp_ints(big + 1);
+  sz[L_BFLAG] = sizeof(int32_t) * (size_t)(nbt + 1);
+  sz[L_TSCAN2] = sizeof(int32_t) * (size_t)scan_tmp_ints(nbt + 1);
   sz[L_STATS] = sizeof(int64_t) * ST_COUNT;
   sz[L_SORT] = sort_bytes;
   Layout L;
@@ -556,6 +558,12 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
       return fail(fail_hip(he));
     }
   }
+  if (!F->side) {  // default priority, like every stream here
+    he = hipStreamCreateWithFlags(&F->side, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&F->ev_fork, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&F->ev_join, hipEventDisableTiming);
+    if (he != hipSuccess) return fail(fail_hip(he));
+  }
   char* A = F->arena;
   F->n_meshes = n_meshes;
   F->verts = verts_d;
@@ -591,6 +599,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->t_b = (int32_t*)(A + L.off[L_TB]);
   F->t_c = (int32_t*)(A + L.off[L_TC]);
   F->t_scan = (int32_t*)(A + L.off[L_TSCAN]);
+  F->brick_flag = (int32_t*)(A + L.off[L_BFLAG]);
+  F->t_scan2 = (int32_t*)(A + L.off[L_TSCAN2]);
   F->d_stats = (int64_t*)(A + L.off[L_STATS]);
   F->t_sort = (void*)(A + L.off[L_SORT]);
   F->t_sort_bytes = sort_bytes;
@@ -629,6 +639,21 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                                                F->tris_g, F->face_mesh, F->face_edges,
                                                                F->vert_mesh, F->d_stats);
   const int32_t* T = F->tris_g;
+  // Face normals with the band bricks near each face, the brick slots and lists:
+  // they need only the inputs, so they run on the side stream while the corner
+  // table, twins, classes and edges run here.
+  CK(hipEventRecord(F->ev_fork, s));
+  CK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
+  {
+    hipStream_t s2 = F->side;
+    k_fill_i32<<<grid_1d(tb, B), B, 0, s2>>>(F->brick_flag, tb, 0);
+    k_face_geom<<<grid_1d(tf, B), B, 0, s2>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, F->face_v,
+                                               F->brick_flag, F->d_stats);
+    CK(exclusive_scan(F->brick_flag, F->brick_index, tb, F->t_scan2, &F->d_stats[ST_NBRICKS], nullptr, s2));
+    k_brick_fix<<<grid_1d(tb, B), B, 0, s2>>>(F->brick_flag, F->brick_index, F->brick_list, F->brick_mesh,
+                                              F->brick_base, n_meshes, F->first_slot, F->d_stats, tb);
+    CK(hipEventRecord(F->ev_join, s2));
+  }
   // 2. vertex -> corner table: corners sorted by vertex (stable: each vertex's
   // corners in ascending order), then the segment starts
   CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, nullptr, F->vtx_corners, nh,
@@ -649,10 +674,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   // edges with their classes and extrusion sides
   k_edges<<<grid_1d(nh, B), B, 0, s>>>(verts_d, T, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->edges,
                                        F->face_edges, F->edge_cls, F->t_c);
-  // 4. face normals with the band bricks near each face; edge classes
-  k_fill_i32<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, tb, 0);
-  k_face_geom<<<grid_1d(tf, B), B, 0, s>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, F->face_v, F->t_b,
-                                            F->d_stats);
+  // 4. edge polyhedron queue and class statistics
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
   {
@@ -660,10 +682,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
     k_class_stats<<<grid_1d(items < 1024 * 256 ? items : 1024 * 256, 256), 256, 0, s>>>(F->edge_cls, ne, F->vbits,
                                                                                        tv, F->d_stats);
   }
-  // 5. band bricks
-  CK(exclusive_scan(F->t_b, F->brick_index, tb, F->t_scan, &F->d_stats[ST_NBRICKS], nullptr, s));
-  k_brick_fix<<<grid_1d(tb, B), B, 0, s>>>(F->t_b, F->brick_index, F->brick_list, F->brick_mesh, F->brick_base,
-                                           n_meshes, F->first_slot, F->d_stats, tb);
+  // 5. join the side stream
+  CK(hipStreamWaitEvent(s, F->ev_join, 0));
   CK(hipGetLastError());
 #undef CK
   F->built = true;

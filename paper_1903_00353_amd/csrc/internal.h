@@ -160,6 +160,12 @@ struct csc_features {
   size_t t_sort_bytes = 0;
   int64_t* d_stats = nullptr;       // [ST_COUNT] counters; ST_ERR holds the error bits
   int64_t* h_stats = nullptr;       // pinned host mirror [ST_COUNT]
+  // the build's brick marking runs on `side`, forked from and joined back into
+  // the caller's stream with the two events (capturable: a parallel branch)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int32_t* brick_flag = nullptr;    // [nbt + 1] brick marks of the build
+  int32_t* t_scan2 = nullptr;       // scan temporaries of the side branch
 
   bool built = false;               // device work queued for the current inputs
   bool synced = false;              // counts below read back since the last build

@@ -272,6 +272,9 @@ int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_b
  * every other stage one launch or the whole build). While enabled, every call records a pair
  * of events around each stage; csc_timing_read waits for the recorded events and
  * returns the accumulated milliseconds and call counts of the first n stages.
+ * A batch's scan otherwise runs the edge and vertex kinds on a second stream,
+ * beside the faces; while timing is enabled the kinds run one after another, so
+ * that each stage times one kernel running alone.
  * Process-wide; not meant for concurrent callers.
  */
 int csc_timing_enable(int on);

@@ -81,6 +81,9 @@ enum {
   TS_SCAN_FACE_BIG, TS_SCAN_EDGE_BIG, TS_SCAN_VERT_BIG, TS_FILL, N_STAGES
 };
 
+// whether stage timing is on (csc_timing_enable)
+bool stage_timing_on();
+
 // Records a pair of events around its scope on stream s when timing is enabled
 // and the stream is not being captured into a graph.
 class StageTimer {

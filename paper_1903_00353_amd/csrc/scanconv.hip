@@ -939,6 +939,8 @@ void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s) {
 // kind's passes (batch of 64: 1.875 -> 1.792 ms per step). One large mesh
 // fills the GPU with each kind alone, and there the overlap only adds
 // contention (1024^3 sphere: 3.43 -> 3.47 ms), so it stays on one stream.
+// With stage timing on, the kinds also run one after another, so that each
+// timed stage is one kernel running alone.
 void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, unsigned long long* counters,
                int32_t* big, hipStream_t s) {
   {
@@ -946,7 +948,7 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
     k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap);
     k_zero_i32<<<1, 64, 0, s>>>(big, 3);
   }
-  const bool fork = f->n_meshes > 1;
+  const bool fork = f->n_meshes > 1 && !stage_timing_on();
   hipStream_t s2 = fork ? f->side : s;
   if (fork) {
     (void)hipEventRecord(f->ev_fork, s);

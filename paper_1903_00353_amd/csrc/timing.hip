@@ -35,6 +35,11 @@ void drain_locked() {
 
 namespace csc {
 
+bool stage_timing_on() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_on;
+}
+
 StageTimer::StageTimer(int stage, hipStream_t s) : stage_(stage), s_(s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;

@@ -948,12 +948,11 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
     k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap);
     k_zero_i32<<<1, 64, 0, s>>>(big, 3);
   }
-  const bool fork = f->n_meshes > 1 && !stage_timing_on();
+  // a fork that cannot be set up leaves everything on the caller's stream
+  bool fork = f->n_meshes > 1 && !stage_timing_on() && f->side;
+  if (fork)
+    fork = hipEventRecord(f->ev_fork, s) == hipSuccess && hipStreamWaitEvent(f->side, f->ev_fork, 0) == hipSuccess;
   hipStream_t s2 = fork ? f->side : s;
-  if (fork) {
-    (void)hipEventRecord(f->ev_fork, s);
-    (void)hipStreamWaitEvent(s2, f->ev_fork, 0);
-  }
   ScanArgs A = scan_args(f, keys, cap);
   A.big_count = big;
   A.big_items = big + 4;
@@ -980,10 +979,8 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.counter = counters ? counters + 2 : nullptr;
   A.big_count = big + 2;
   launch_kind<KIND_VERT>(A, TS_SCAN_VERT, TS_SCAN_VERT_BIG, s2);
-  if (fork) {
-    (void)hipEventRecord(f->ev_join, s2);
-    (void)hipStreamWaitEvent(s, f->ev_join, 0);
-  }
+  if (fork && (hipEventRecord(f->ev_join, s2) != hipSuccess || hipStreamWaitEvent(s, f->ev_join, 0) != hipSuccess))
+    (void)hipStreamSynchronize(s2);  // no join on the device: finish the side branch from the host
 }
 
 int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d, int32_t* feat_d,

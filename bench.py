@@ -35,11 +35,17 @@ WORKLOADS = {
 }
 PEAK_HBM_GBS = 8000.0
 # stages timed around exactly one kernel launch, and that kernel
-KERNEL_SYMBOL = {"init_keys": "k_init_keys", "scan_faces": "k_scan_small<0>", "scan_edges": "k_scan_small<1>",
-                 "scan_vertices": "k_scan_small<2>", "scan_faces_big": "k_scan_big<0>",
-                 "scan_edges_big": "k_scan_big<1>", "scan_vertices_big": "k_scan_big<2>", "sign": "k_sign",
-                 "backward": "k_backward"}
+KERNEL_SYMBOL = {"init_keys": "k_init_keys", "scan_faces": "k_scan_small<0, false>",
+                 "scan_edges": "k_scan_small<1, false>", "scan_vertices": "k_scan_small<2, false>",
+                 "scan_faces_big": "k_scan_big<0, false, false>", "scan_edges_big": "k_scan_big<1, false, false>",
+                 "scan_vertices_big": "k_scan_big<2, false, false>", "sign": "k_sign", "backward": "k_backward"}
 SINGLE_KERNEL_STAGES = list(KERNEL_SYMBOL)
+# scan launches and their tags in csc_scan_record_atomics, with their index in the atomic counts
+SCAN_LAUNCHES = {"scan_faces": 0, "scan_edges": 1, "scan_vertices": 2, "scan_faces_big": 3, "scan_edges_big": 4,
+                 "scan_vertices_big": 5}
+# the launches of the forward pass (a5 scan conversion and a6 sign + compaction)
+FORWARD_STAGES = ["init_keys", "scan_faces", "scan_edges", "scan_vertices", "scan_faces_big", "scan_edges_big",
+                  "scan_vertices_big", "scan_wide", "brick_count", "sign"]
 
 
 def kernel_source_sha() -> str:
@@ -84,6 +90,110 @@ def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
     if stage == "backward":     # (sdf, id, cell, dL/dSDF) read, 3 floats added per weighted vertex
         return 16 * band_cells + 12 * vert_refs
     raise KeyError(stage)
+
+
+def popcount64(mask_np):
+    import numpy as np
+    return int(np.unpackbits(np.ascontiguousarray(mask_np).view(np.uint8)).sum())
+
+
+def atomic_rates(P, feats, ws, n_keys, nv, reps=10):
+    """Measured atomic peaks at the scan's own locality: the packed atomicMin
+    instructions of each scan launch are logged (one round per wavefront
+    instruction, with its lanes) and replayed by a kernel that does nothing
+    else, on a key array of the store's size; the replay of every launch
+    together gives the forward pass's rate. The replay reads 4 bytes of log per
+    lane; a read-only pass over the same log is timed beside it. Also the
+    scattered float atomicAdd rate (x, y, z of random vertices) that the
+    adjoint's flushes meet. HIP events on the stream the kernels run on."""
+    import torch
+    keys = torch.empty(max(1, n_keys), dtype=torch.int64, device=ws.device)
+    out = {}
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for stage, tag in list(SCAN_LAUNCHES.items()) + [("all", -1)]:
+        log, mask = P.csc_scan_record_atomics(feats, ws, tag)
+        n = popcount64(mask.cpu().numpy())
+        if n == 0:
+            continue
+        ms = timed(lambda: P.csc_atomic_replay(log, mask, keys, 0))
+        ms_read = timed(lambda: P.csc_atomic_replay(log, mask, keys, 1))
+        ms_wg = timed(lambda: P.csc_atomic_replay(log, mask, keys, 2))
+        ms_st = timed(lambda: P.csc_atomic_replay(log, mask, keys, 3))
+        out[stage] = {"atomics": n, "instructions": int(mask.numel()), "lanes_per_instruction": n / mask.numel(),
+                      "replay_ms": ms, "log_read_ms": ms_read, "workgroup_scope_ms": ms_wg, "plain_store_ms": ms_st,
+                      "rate_G_per_s": n / (ms * 1e-3) / 1e9}
+        del log, mask
+    g = torch.zeros(max(1, nv), 3, dtype=torch.float32, device=ws.device)
+    nadd = 1 << 23
+    ms = timed(lambda: P.csc_fadd_rate(g, nadd))
+    out["f32_atomicAdd_scattered"] = {"adds": 3 * nadd, "vertices": nv, "ms": ms,
+                                      "rate_G_per_s": 3 * nadd / (ms * 1e-3) / 1e9}
+    del keys, g
+    return out
+
+
+def rooflines(avg, per_step, atomics, rates, alg_bytes, fwd_bytes):
+    """Per single-kernel stage: T_roof = max(algorithmic bytes / 8 TB/s, atomics /
+    measured atomic rate of that launch) against its measured time; the dominant
+    (slowest) kernel's entry is the bench line's roofline. The forward pass (a5 +
+    a6 launches) gets the same bound from its total bytes and atomics against
+    the replay rate of all its launches together."""
+    per = {}
+    for st in SINGLE_KERNEL_STAGES:
+        t = avg.get(st, 0.0)
+        if t <= 0:
+            continue
+        b = alg_bytes(st)
+        ent = {"ms": t, "algorithmic_bytes": b, "hbm_GBs": b / (t * 1e-3) / 1e9}
+        ent["hbm_frac"] = ent["hbm_GBs"] / PEAK_HBM_GBS
+        if st in SCAN_LAUNCHES and st in rates:
+            a = atomics[SCAN_LAUNCHES[st]]
+            ent["atomics"] = a
+            ent["atomic_G_per_s"] = a / (t * 1e-3) / 1e9
+            ent["atomic_peak_G_per_s"] = rates[st]["rate_G_per_s"]
+            ent["atomic_frac"] = ent["atomic_G_per_s"] / ent["atomic_peak_G_per_s"]
+        ent["frac"] = max(ent["hbm_frac"], ent.get("atomic_frac", 0.0))
+        ent["bound"] = "atomic" if ent.get("atomic_frac", 0.0) > ent["hbm_frac"] else "hbm"
+        per[st] = ent
+    dom = max(per, key=lambda k: per[k]["ms"])
+    d = per[dom]
+    if d["bound"] == "atomic":
+        main = {"bound": "atomic", "achieved": d["atomic_G_per_s"], "peak": d["atomic_peak_G_per_s"],
+                "unit": "G atomics/s"}
+    else:
+        main = {"bound": "hbm", "achieved": d["hbm_GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    main.update({"kernel": KERNEL_SYMBOL[dom], "frac": d["frac"], "avg_ms": d["ms"],
+                 "algorithmic_bytes": d["algorithmic_bytes"], "hbm_frac": d["hbm_frac"],
+                 "atomic_frac": d.get("atomic_frac")})
+    t_fwd = sum(per_step.get(st, 0.0) for st in FORWARD_STAGES)
+    a_all = sum(atomics)
+    fwd = {"ms": t_fwd, "algorithmic_bytes": fwd_bytes, "atomics": a_all,
+           "t_hbm_ms": fwd_bytes / (PEAK_HBM_GBS * 1e9) * 1e3}
+    if "all" in rates:
+        fwd["atomic_peak_G_per_s"] = rates["all"]["rate_G_per_s"]
+        fwd["t_atomic_ms"] = a_all / (rates["all"]["rate_G_per_s"] * 1e9) * 1e3
+    fwd["t_roof_ms"] = max(fwd["t_hbm_ms"], fwd.get("t_atomic_ms", 0.0))
+    fwd["frac"] = fwd["t_roof_ms"] / t_fwd if t_fwd > 0 else None
+    fwd["bound"] = "atomic" if fwd.get("t_atomic_ms", 0.0) > fwd["t_hbm_ms"] else "hbm"
+    return main, per, dom, fwd
+
+
+def forward_bytes(nv, nf, ne, atomics, band_cells):
+    """Algorithmic bytes of one forward pass: the mesh (12 B per vertex, 12 B per
+    triangle, 16 B per edge record), 8 B per packed atomicMin, the key read by
+    the sign pass and the band written (SDF and id), 8 B each per band cell."""
+    return 12 * nv + 12 * nf + 16 * ne + 8 * sum(atomics) + 8 * band_cells + 8 * band_cells
 
 
 def cpu_baseline(v, f, grid, budget_s=15.0):
@@ -133,7 +243,8 @@ def timed_steps(fn, steps):
 
 def stage_averages(fn, steps):
     """Mean ms per launch of every library stage over `steps` eager calls of fn
-    (the library's own HIP events on the stream each kernel is launched on)."""
+    (the library's own HIP events on the stream each kernel is launched on), the
+    wall-clock ms per call, and each stage's ms per call of fn."""
     import torch
 
     import paper_1903_00353_amd as P
@@ -147,7 +258,8 @@ def stage_averages(fn, steps):
     t1 = time.perf_counter()
     P.csc_timing_enable(False)
     stages = P.csc_timing_read()
-    return {k: (ms / c if c else 0.0) for k, (ms, c) in stages.items()}, (t1 - t0) * 1e3 / steps
+    return ({k: (ms / c if c else 0.0) for k, (ms, c) in stages.items()}, (t1 - t0) * 1e3 / steps,
+            {k: ms / steps for k, (ms, c) in stages.items()})
 
 
 def parse_rows(text):
@@ -209,12 +321,16 @@ def bench_batch(args):
     # the same step launched eagerly, with the library's per-stage events (roofline)
     for _ in range(max(1, args.warmup)):
         B.step()
-    avg, ms_eager = stage_averages(B.step, args.steps)
-    dom = max(SINGLE_KERNEL_STAGES, key=lambda k: avg[k])
-    alg = batch_algorithmic_bytes(dom, int(info["n_faces"]), int(info["n_vertices"]),
-                                  int(info["n_edge_polyhedra"]), int(info["n_vertex_polyhedra"]), atomics, M,
-                                  vert_refs, int(info["n_bricks"]))
-    achieved = alg / (avg[dom] * 1e-3) / 1e9
+    avg, ms_eager, per_step = stage_averages(B.step, args.steps)
+    rates = atomic_rates(P, B.f, B.workspace, int(info["n_bricks"]) * 512, int(info["n_vertices"]))
+    NF, NV = int(info["n_faces"]), int(info["n_vertices"])
+    main, per, dom, fwd = rooflines(
+        avg, per_step, atomics, rates,
+        lambda st: batch_algorithmic_bytes(st, NF, NV, int(info["n_edge_polyhedra"]), int(info["n_vertex_polyhedra"]),
+                                           atomics, M, vert_refs, int(info["n_bricks"])),
+        forward_bytes(NV, NF, int(info["n_edges"]), atomics, M))
+    main["traffic"] = load_traffic("batch64", dom)
+    main["measured_on"] = "eager batched steps, scan kinds one after another"
     res = {
         "metric": METRIC,
         "value": M / (ms_graph * 1e-3),
@@ -231,9 +347,10 @@ def bench_batch(args):
         "config": {"workload": f"batch64: {desc}", "meshes": len(meshes), "faces": int(info["n_faces"]),
                    "vertices": int(info["n_vertices"]), "grids": [int(g.n[0]) for g in grids], "band_cells": 3.0,
                    "band_size": M, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("batch64", dom),
-                     "algorithmic_bytes": alg, "avg_ms": avg[dom], "measured_on": "eager batched steps"},
+        "roofline": main,
+        "roofline_forward": fwd,
+        "roofline_kernels": per,
+        "atomic_peaks": rates,
         "step_ms": {"median": med_graph, "min": min_graph, "launch": "eager" if args.no_graph else "graph replay"},
         "batched_eager": {"value": M / (ms_eager * 1e-3), "ms_per_step": ms_eager},
         "schedule": {"small_rows": list(schedule)},
@@ -286,7 +403,7 @@ def bench_batch(args):
     B2 = P.Batch(meshes, grids, options=P.make_options(small_rows=schedule, scan_mode=1), device=dev, backward=False,
                  graph_safe=True)
     B2.step()
-    avg2, ms2 = stage_averages(B2.step, max(3, args.steps // 4))
+    avg2, ms2, _ = stage_averages(B2.step, max(3, args.steps // 4))
     res["ablation_per_cell_scan"] = {"fwd_ms": ms2, "fwd_ms_row_intervals": ms_fwd,
                                      "stages_ms": {k: round(v, 4) for k, v in avg2.items() if k.startswith("scan_")}}
     del B2
@@ -410,10 +527,12 @@ def bench_single(args):
     for _ in range(args.warmup):
         step()
     ms_step, med_step, min_step = timed_steps(step, args.steps)
-    avg, _ = stage_averages(step, args.steps)
-    dom = max(SINGLE_KERNEL_STAGES, key=lambda k: avg[k])
-    alg = algorithmic_bytes(dom, info, atomics, M, vert_refs, verts.shape[0])
-    achieved = alg / (avg[dom] * 1e-3) / 1e9
+    avg, _, per_step = stage_averages(step, args.steps)
+    rates = atomic_rates(P, feats, ws, int(info["n_bricks"]) * 512, int(verts.shape[0]))
+    main, per, dom, fwd = rooflines(avg, per_step, atomics, rates,
+                                    lambda st: algorithmic_bytes(st, info, atomics, M, vert_refs, verts.shape[0]),
+                                    forward_bytes(int(verts.shape[0]), F, E, atomics, M))
+    main["traffic"] = load_traffic(args.workload, dom)
     res = {
         "metric": METRIC,
         "value": M / (ms_step * 1e-3),
@@ -429,9 +548,10 @@ def bench_single(args):
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "faces": F, "vertices": int(verts.shape[0]),
                    "grid": list(g.n), "band_cells": g.band, "band_size": M, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic(args.workload, dom),
-                     "algorithmic_bytes": alg, "avg_ms": avg[dom]},
+        "roofline": main,
+        "roofline_forward": fwd,
+        "roofline_kernels": per,
+        "atomic_peaks": rates,
         "step_ms": {"median": med_step, "min": min_step},
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
         "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
@@ -484,7 +604,7 @@ def bench_per_cell(P, verts, tris, g, schedule, ws, out, reps):
         P.csc_scan_convert(f1, ws, out, sync_count=False)
 
     fwd()
-    avg, ms = stage_averages(fwd, reps)
+    avg, ms, _ = stage_averages(fwd, reps)
     f1.free()
     return {"fwd_ms": ms, "stages_ms": {k: round(v, 4) for k, v in avg.items() if k.startswith("scan_")}}
 
@@ -525,7 +645,7 @@ def bench_interior_fill(P, feats, ws, out, g, reps):
     rep()
     torch.cuda.synchronize()
     interior = int((dense == float("-inf")).sum().item())
-    avg, _ = stage_averages(rep, reps)
+    avg, _, _ = stage_averages(rep, reps)
     ms = avg["interior_fill"]
     nbytes = 4 * n + 4 * interior
     del dense

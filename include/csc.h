@@ -79,6 +79,15 @@ typedef struct csc_options {
                                half-spaces at once; 1: every cell of the box is tested by itself
                                (Alg. 2 as printed), an ablation that costs more and gives the same
                                field up to ties between features */
+  float absorb_cells;       /* nearly flat features (Section 3.1: flat ones need no extrusion): an edge
+                               whose face normals differ by theta needs no wedge of its own once its two
+                               face prisms (Section 8.1) take side slack band_cells * sin(theta), and a
+                               vertex with cone aperture theta none once its faces take
+                               band_cells * sin(2 theta); the distances stay exact (a face prism computes
+                               the exact distance to its triangle). Features whose slack is at most
+                               this many cells are absorbed that way. 0 = default (0.05); negative: every
+                               non-flat edge and vertex keeps its own polyhedron, as in Section 8; at most
+                               0.24. Only the speed depends on it. */
 } csc_options;
 
 typedef struct csc_features csc_features; /* opaque, library-owned, device resident */
@@ -91,6 +100,8 @@ typedef struct csc_feature_info {
   int64_t vertices_convex, vertices_concave, vertices_flat, vertices_saddle, vertices_ruff;
   int64_t n_bricks;                               /* allocated 8^3-cell bricks of the band store */
   int64_t max_band_cells;                         /* upper bound of the band size (n_bricks * 512) */
+  int64_t edges_absorbed, vertices_absorbed;      /* nearly flat features handed to their faces
+                                                     (csc_options.absorb_cells) */
 } csc_feature_info;
 
 /*
@@ -154,6 +165,11 @@ int csc_features_info(const csc_features* f, csc_feature_info* info);
  * bricks; the outputs must then have 512 entries per brick it holds. */
 int csc_scan_convert_workspace(const csc_features* f, size_t* bytes, int64_t* max_band_cells);
 
+/* The same for a band store of n_bricks bricks (at most all bricks of the
+ * grids): room for bricks that later builds with moved vertices may add (a
+ * graph replayed on updated positions, for example). */
+int csc_scan_convert_workspace_for(const csc_features* f, int64_t n_bricks, size_t* bytes, int64_t* max_band_cells);
+
 /*
  * Scan-convert every polyhedron (Section 5, Alg. 2: inclusion by the half-space
  * test with slack, cones and hemispheres by their discriminant, Eq. 10), compute
@@ -206,11 +222,12 @@ int csc_weld_soup(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris
  * scan on the same stream). Along each z column an unset cell takes the side
  * (sign) of the nearest band cell before it in the column, or of the first one
  * after it; a column with no band cell stays +infinity. Exact for a closed
- * surface when band_cells >= 1/2 (a column cannot cross the surface between two
- * cell centres without passing a band cell); surfaces cut by the grid boundary
- * are handled as long as every z column that meets the solid meets the band.
+ * surface when band_cells > 1: where a column crosses the surface between two
+ * neighbouring cell centres, both lie within one cell of the crossing and so
+ * are band cells, each with its own side. Surfaces cut by the grid boundary are
+ * handled as long as every z column that meets the solid meets the band.
  * Single-mesh handles only. Errors: INVALID_ARG (null, not built, batched
- * handle), HIP_ERROR.
+ * handle, band_cells <= 1), HIP_ERROR.
  */
 int csc_interior_fill(const csc_features* f, float* dense_d, void* stream);
 
@@ -264,12 +281,45 @@ int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_b
                            void* stream);
 
 /*
+ * Diagnostics for the atomic roofline. csc_scan_record_atomics runs the key
+ * initialisation and the scan launches (as csc_scan_convert_count does) and logs
+ * every packed atomicMin instruction of one launch (launch: 0-2 the
+ * one-thread-per-polyhedron launch of faces, edges, vertices; 3-5 their overflow
+ * launches; 6-8 their wide launches; -1 every launch) as one round: the key
+ * indices of the issuing lanes at log_d[64 r + lane] (uint32, device,
+ * 64 * max_rounds entries, lanes that do not issue left unwritten) and the mask
+ * of issuing lanes at mask_d[r] (device, max_rounds entries). *rounds receives
+ * the number of rounds issued, also those past max_rounds, which are not logged
+ * (max_rounds 0 only counts them; the log pointers may then be NULL).
+ * Synchronises `stream`. The launches run on one stream.
+ * csc_atomic_replay issues the logged atomicMin instructions again, each round
+ * as one instruction of one wavefront with the same lanes, and nothing else
+ * (mode 0), or only reads the log (mode 1), or issues them at workgroup scope
+ * (mode 2: in the issuing XCD's L2 only, so the values are meaningless; a rate
+ * measurement) or as plain stores (mode 3): keys_d is any device array of n_keys
+ * uint64 (indices at or past n_keys are skipped); rounds must not exceed the
+ * rounds logged. csc_fadd_rate queues n float atomicAdds of 1 to the x, y and z
+ * of pseudo-random vertices of grad_d (float32 [nv][3], device): the scattered
+ * float-atomic rate the adjoint's flushes meet. Both queue one launch on
+ * `stream` and return at once. Errors: INVALID_ARG, WORKSPACE_TOO_SMALL,
+ * HIP_ERROR.
+ */
+int csc_scan_record_atomics(const csc_features* f, void* workspace_d, size_t ws_bytes, int32_t launch,
+                            uint32_t* log_d, unsigned long long* mask_d, int64_t max_rounds, int64_t* rounds,
+                            void* stream);
+int csc_atomic_replay(const uint32_t* log_d, const unsigned long long* mask_d, int64_t rounds,
+                      unsigned long long* keys_d, int64_t n_keys, int32_t mode, void* stream);
+int csc_fadd_rate(float* grad_d, int64_t nv, int64_t n, void* stream);
+
+/*
  * Per-stage timing with HIP events recorded on the stream of each call (stages:
  * 0 build_features, 1 init_keys, 2 scan_faces, 3 scan_edges, 4 scan_vertices,
  * 5 brick_count, 6 sign, 7 backward, 8 scan_faces_big, 9 scan_edges_big,
- * 10 scan_vertices_big, 11 interior_fill; stages 2-4 time the one-thread-per-polyhedron launch of
- * each kind and 8-10 the wave-per-polyhedron launch over its overflow list,
- * every other stage one launch or the whole build). While enabled, every call records a pair
+ * 10 scan_vertices_big, 11 interior_fill, 12 scan_wide; stages 2-4 time the
+ * one-thread-per-polyhedron launch of each kind, 8-10 the wave-per-polyhedron
+ * launch over its overflow list, 12 the three launches (one per kind) over the
+ * polyhedra whose box exceeds 32 cells along an axis, whose distances are taken
+ * in FP64; every other stage one launch or the whole build). While enabled, every call records a pair
  * of events around each stage; csc_timing_read waits for the recorded events and
  * returns the accumulated milliseconds and call counts of the first n stages.
  * A batch's scan otherwise runs the edge and vertex kinds on a second stream,

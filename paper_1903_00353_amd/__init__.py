@@ -44,7 +44,7 @@ class csc_grid(C.Structure):
 class csc_options(C.Structure):
     _fields_ = [("eps_rel", C.c_float), ("ruff_mode", C.c_int32), ("saddle_mode", C.c_int32),
                 ("force_both_sides", C.c_int32), ("small_rows", C.c_int32 * 3),
-                ("scan_mode", C.c_int32)]
+                ("scan_mode", C.c_int32), ("absorb_cells", C.c_float)]
 
 
 class csc_feature_info(C.Structure):
@@ -52,7 +52,7 @@ class csc_feature_info(C.Structure):
         "n_vertices", "n_faces", "n_edges", "n_edge_polyhedra", "n_vertex_polyhedra",
         "edges_convex", "edges_concave", "edges_flat", "edges_unknown",
         "vertices_convex", "vertices_concave", "vertices_flat", "vertices_saddle", "vertices_ruff",
-        "n_bricks", "max_band_cells")]
+        "n_bricks", "max_band_cells", "edges_absorbed", "vertices_absorbed")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -63,10 +63,11 @@ EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspac
            "csc_classify_edge", "csc_classify_vertex", "csc_scan_convert_count", "csc_timing_enable",
            "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name", "csc_build_features_batched",
            "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched", "csc_interior_fill",
-           "csc_weld_soup"]
+           "csc_weld_soup", "csc_scan_record_atomics", "csc_atomic_replay", "csc_fadd_rate",
+           "csc_scan_convert_workspace_for"]
 CSC_BUILD_NO_SYNC = 1
 CSC_BUILD_GRAPH_SAFE = 2
-N_STAGES = 12
+N_STAGES = 13
 
 _lib = None
 
@@ -87,6 +88,8 @@ def lib():
     L.csc_features_info.argtypes = [P, C.POINTER(csc_feature_info)]
     L.csc_scan_convert_workspace.restype = C.c_int
     L.csc_scan_convert_workspace.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]
+    L.csc_scan_convert_workspace_for.restype = C.c_int
+    L.csc_scan_convert_workspace_for.argtypes = [P, C.c_int64, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]
     L.csc_scan_convert.restype = C.c_int
     L.csc_scan_convert.argtypes = [P, P, C.c_size_t, P, P, P, P, P, P]
     L.csc_sdf_backward.restype = C.c_int
@@ -114,6 +117,12 @@ def lib():
     L.csc_scan_convert_batched.argtypes = [P, P, C.c_size_t, P, P, P, P, P]
     L.csc_sdf_backward_batched.restype = C.c_int
     L.csc_sdf_backward_batched.argtypes = [P, P, P, P, C.c_int64, P, P, P, P]
+    L.csc_scan_record_atomics.restype = C.c_int
+    L.csc_scan_record_atomics.argtypes = [P, P, C.c_size_t, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64), P]
+    L.csc_atomic_replay.restype = C.c_int
+    L.csc_atomic_replay.argtypes = [P, P, C.c_int64, P, C.c_int64, C.c_int32, P]
+    L.csc_fadd_rate.restype = C.c_int
+    L.csc_fadd_rate.argtypes = [P, C.c_int64, C.c_int64, P]
     L.csc_features_free.restype = None
     L.csc_features_free.argtypes = [P]
     L.csc_error_string.restype = C.c_char_p
@@ -149,11 +158,14 @@ def make_grid(grid) -> csc_grid:
 
 
 def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0, small_rows=(0, 0, 0),
-                 scan_mode=0) -> csc_options:
+                 scan_mode=0, absorb_cells=0.0) -> csc_options:
+    """absorb_cells: 0 the library's default, negative to give every non-flat
+    feature its own polyhedron."""
     o = csc_options(float(eps_rel), int(ruff_mode), int(saddle_mode), int(force_both_sides))
     for k in range(3):
         o.small_rows[k] = int(small_rows[k])
     o.scan_mode = int(scan_mode)
+    o.absorb_cells = float(absorb_cells)
     return o
 
 
@@ -234,6 +246,13 @@ def csc_scan_convert_workspace(f: Features):
     return int(nbytes.value), int(mx.value)
 
 
+def csc_scan_convert_workspace_for(f: Features, n_bricks: int):
+    nbytes, mx = C.c_size_t(), C.c_int64()
+    _check(lib().csc_scan_convert_workspace_for(f.handle, int(n_bricks), C.byref(nbytes), C.byref(mx)),
+           "csc_scan_convert_workspace_for")
+    return int(nbytes.value), int(mx.value)
+
+
 @dataclasses.dataclass
 class Band:
     sdf: "object"      # float32 [M]
@@ -292,6 +311,36 @@ def csc_scan_convert_count(f: Features, workspace=None, stream=None):
     _check(lib().csc_scan_convert_count(f.handle, _ptr(workspace), workspace.numel(), counts, _stream(stream)),
            "csc_scan_convert_count")
     return [int(x) for x in counts]
+
+
+def csc_scan_record_atomics(f: Features, workspace, launch: int = 0, stream=None):
+    """Log the packed atomicMin instructions of one scan launch (diagnostic;
+    synchronises): returns (log uint32 [rounds*64], mask int64 [rounds]) device
+    tensors, one round per wavefront instruction."""
+    import torch
+    rounds = C.c_int64()
+    _check(lib().csc_scan_record_atomics(f.handle, _ptr(workspace), workspace.numel(), int(launch), None, None, 0,
+                                         C.byref(rounds), _stream(stream)), "csc_scan_record_atomics")
+    n = int(rounds.value)
+    log = torch.empty(max(1, 64 * n), dtype=torch.int32, device=workspace.device)
+    mask = torch.zeros(max(1, n), dtype=torch.int64, device=workspace.device)
+    got = C.c_int64()
+    _check(lib().csc_scan_record_atomics(f.handle, _ptr(workspace), workspace.numel(), int(launch), _ptr(log),
+                                         _ptr(mask), n, C.byref(got), _stream(stream)), "csc_scan_record_atomics")
+    if int(got.value) != n:
+        raise RuntimeError(f"csc_scan_record_atomics: {got.value} rounds on the second run, {n} on the first")
+    return log[: 64 * n], mask[:n]
+
+
+def csc_atomic_replay(log, mask, keys, mode: int = 0, stream=None):
+    """Queue the replay of a logged atomic stream on ``keys`` (uint64-sized tensor)."""
+    _check(lib().csc_atomic_replay(_ptr(log), _ptr(mask), int(mask.numel()), _ptr(keys), int(keys.numel()), int(mode),
+                                   _stream(stream)), "csc_atomic_replay")
+
+
+def csc_fadd_rate(grad, n: int, stream=None):
+    """Queue n scattered float atomicAdds (x, y, z of random vertices) into grad [nv, 3]."""
+    _check(lib().csc_fadd_rate(_ptr(grad), int(grad.shape[0]), int(n), _stream(stream)), "csc_fadd_rate")
 
 
 def csc_timing_enable(on: bool = True):
@@ -367,9 +416,15 @@ class Batch:
     After ``Batch(...)`` (one synchronised build that sizes every buffer), each
     ``step()`` runs build + scan conversion (+ adjoint of sum SDF^2) without any
     host synchronisation or allocation, so it can be captured in a graph
-    (``capture()``) and replayed (``replay()``)."""
+    (``capture()``) and replayed (``replay()``).
 
-    def __init__(self, meshes, grids, options=None, device="cuda", backward=True, graph_safe=True):
+    The band store holds ``headroom`` times the bricks of that first build (at
+    most every brick of the grids), so that steps on moved vertices that reach
+    new bricks still fit. Bricks past that capacity are dropped and flagged:
+    ``check()`` (or ``overflowed()``) after a step or replay whose vertices moved
+    tells whether that happened."""
+
+    def __init__(self, meshes, grids, options=None, device="cuda", backward=True, graph_safe=True, headroom=1.25):
         import torch
         self.grids = list(grids)
         self.nv = [int(m[0].shape[0]) for m in meshes]
@@ -381,7 +436,8 @@ class Batch:
         self.flags = CSC_BUILD_GRAPH_SAFE if graph_safe else 0
         self.f = csc_build_features_batched(self.verts, self.tris, self.nv, self.nf, self.grids, options,
                                             flags=self.flags)
-        nbytes, mx = csc_scan_convert_workspace(self.f)
+        nb = int(self.f.info()["n_bricks"])
+        nbytes, mx = csc_scan_convert_workspace_for(self.f, int(nb * float(headroom)) + 1)
         self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
         self.out = (torch.empty(max(mx, 1), dtype=torch.float32, device=device),
                     torch.empty(max(mx, 1), dtype=torch.int32, device=device),
@@ -417,8 +473,19 @@ class Batch:
         self.graph.replay()
 
     def check(self):
-        """Synchronise and raise if the last build or scan reported an error."""
+        """Synchronise and raise if the last build or scan reported an error
+        (CSC_WORKSPACE_TOO_SMALL: bricks past the store's capacity were dropped)."""
         csc_features_sync(self.f)
+
+    def overflowed(self) -> bool:
+        """Synchronise; True if the last step needed more bricks than the store holds."""
+        try:
+            csc_features_sync(self.f)
+        except CscError as e:
+            if e.code == 8:
+                return True
+            raise
+        return False
 
     def band(self, m):
         """(sdf, feat, cell) tensors of mesh m (synchronises to read the offsets)."""

@@ -128,4 +128,5 @@ def tune_single(verts, tris, grid, options=None, candidates=CANDIDATES, reps=3, 
 
 def _with_rows(opt, rows):
     import paper_1903_00353_amd as P
-    return P.make_options(opt.eps_rel, opt.ruff_mode, opt.saddle_mode, opt.force_both_sides, rows, opt.scan_mode)
+    return P.make_options(opt.eps_rel, opt.ruff_mode, opt.saddle_mode, opt.force_both_sides, rows, opt.scan_mode,
+                          opt.absorb_cells)

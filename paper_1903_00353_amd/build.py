@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libcsc.so")
-SOURCES = ["scan.hip", "sort.hip", "build.hip", "scanconv.hip", "backward.hip", "fill.hip", "weld.hip", "api.hip", "timing.hip"]
+SOURCES = ["scan.hip", "sort.hip", "build.hip", "scanconv.hip", "backward.hip", "fill.hip", "weld.hip", "api.hip", "timing.hip",
+           "diag.hip"]
 
 
 def hipcc() -> str:

@@ -6,6 +6,7 @@
 // Each band cell scatters grad_sdf(c) * dSDF/dx_k into its 1-3 vertices.
 #include "geometry.h"
 #include "internal.h"
+#include "wave.h"
 
 namespace csc {
 
@@ -86,21 +87,6 @@ __device__ inline int div_floor(int a, int d, double inv) {
   q += r >= d ? 1 : 0;
   q -= r < 0 ? 1 : 0;
   return q;
-}
-
-// DPP lane moves (gfx9 encodings): lane l reads lane l + 1 (wave_shl:1), l - 1
-// (wave_shr:1), l - k within its row of 16 (row_shr:k), or lane 15 / 31 (the last
-// of the row before, row_bcast). Lanes without a source keep `id`.
-constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
-constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
-
-template <int CTRL, int ROWS = 0xf>
-__device__ inline int dpp_i(int id, int x) {
-  return __builtin_amdgcn_update_dpp(id, x, CTRL, ROWS, 0xf, false);
-}
-template <int CTRL, int ROWS = 0xf>
-__device__ inline float dpp_f(float id, float x) {
-  return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(id), __float_as_int(x)));
 }
 
 // one step of the segmented inclusive scan over the lanes: add the partial sums

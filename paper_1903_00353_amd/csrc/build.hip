@@ -105,6 +105,46 @@ __global__ void k_offsets(const uint32_t* __restrict__ key, int64_t nh, int64_t 
     for (int64_t v = k + 1; v <= nv; v++) off[v] = (int32_t)nh;
 }
 
+// Absorbing nearly flat features into the face prisms. A cell whose closest
+// point q lies inside edge e (faces f1, f2 with unit normals n1, n2 at angle
+// theta) sees q along a unit direction u perpendicular to e within theta of n1
+// (or of -n1, concave side), so its projection onto f1's plane lies within
+// r sin(theta) <= band h sin(theta) of q, a point of f1: it is inside f1's prism
+// once the prism's side planes are moved out by that much, and there its exact
+// distance to f1 is its distance to e. Likewise a cell whose closest point is
+// vertex v sees it along a direction within theta_v (the cone aperture, every
+// incident normal within theta_v of the pseudonormal N) of +N or -N: every
+// tangent direction of the fan lies within theta_v of the plane normal to N,
+// and q = v minimises the distance only if u has no positive component along
+// any of them. Such a u is within 2 theta_v of +-n_f for every incident face,
+// so the cell is inside the prism of f with slack band h sin(2 theta_v). When
+// that slack is at most `absorb` cells the feature gets no polyhedron of its
+// own and every face holding it takes the slack (rounded up, in 1/1024 cells).
+// Flat features (theta = 0) already get none. Ruff vertices and hemispheres,
+// and edges of unknown class, keep their polyhedra.
+constexpr float SLACK_UNIT = 1.f / 1024.f;  // cells per step of the stored slack
+
+__device__ inline uint8_t slack_code(double cells, float absorb) {
+  if (!(cells <= (double)absorb)) return 0;
+  const double q = ceil(cells * 1024.0) + 1.0;  // one step more: never below the bound
+  return (uint8_t)(q < 255.0 ? q : 255.0);
+}
+
+__device__ inline uint8_t edge_slack(d3 u, d3 w, d3 c1, d3 c2, float band, float absorb) {
+  const d3 n1 = cross(w - u, c1 - u), n2 = cross(u - w, c2 - w);
+  const double l = len(n1) * len(n2);
+  if (!(l > 0) || !(dot(n1, n2) > 0)) return 0;  // theta >= 90 degrees
+  return slack_code((double)band * len(cross(n1, n2)) / l, absorb);
+}
+
+__device__ inline uint8_t vertex_slack(const VertexClass& cl, float band, float absorb) {
+  if (!(cl.bits & (V_POS | V_NEG)) || (cl.bits & (V_POS_HEMI | V_NEG_HEMI | V_RUFF))) return 0;
+  const double c = cl.cos_t;
+  if (!(c > 0.7071067811865476) || c > 1.0) return 0;  // 2 theta up to 90 degrees
+  const double sn = sqrt(fmax(0.0, 1.0 - c * c));
+  return slack_code((double)band * 2.0 * sn * c, absorb);  // band * sin(2 theta)
+}
+
 constexpr int VK_THREADS = 128;
 constexpr int VK_MAXD = 12;  // fans up to this degree are staged in LDS (18 KB per block: 4 wavefronts per SIMD)
 
@@ -119,8 +159,10 @@ constexpr int VK_MAXD = 12;  // fans up to this degree are staged in LDS (18 KB 
 __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__ V, const int32_t* __restrict__ T,
                                                       int64_t nv, const int32_t* __restrict__ off,
                                                       const int32_t* __restrict__ vc, int ruff_mode, int saddle_mode,
-                                                      int force_both, int32_t* twin, float4* vinfo, uint32_t* vbits,
-                                                      int32_t* count, int64_t* stats) {
+                                                      int force_both, const int32_t* __restrict__ vert_mesh,
+                                                      const MeshDesc* __restrict__ md, float absorb, int32_t* twin,
+                                                      float4* vinfo, uint32_t* vbits, int32_t* count,
+                                                      uint8_t* fslack, int64_t* stats) {
   __shared__ int32_t s_c[VK_MAXD][VK_THREADS], s_n[VK_MAXD][VK_THREADS], s_p[VK_MAXD][VK_THREADS];
   const int t = threadIdx.x;
   const int64_t v = blockIdx.x * (int64_t)VK_THREADS + t;
@@ -165,6 +207,11 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
   }
   VertexClass cl = vt.finish(ruff_mode, saddle_mode, force_both);
   if (d == 0) cl.bits = 0;  // isolated vertex: no feature
+  // a nearly flat vertex hands its region to the prisms of its faces (side slack
+  // band * sin(2 theta), theta the cone aperture): see absorbed_slack
+  const uint8_t q = absorb > 0.f && !force_both ? vertex_slack(cl, md[vert_mesh[v]].band, absorb) : 0;
+  if (q) cl.bits = (cl.bits & ~(V_POS | V_NEG)) | V_ABSORBED;
+  for (int k = 0; k < d; k++) fslack[2 * (int64_t)C_(k) + 1] = q;
   float cf = (float)cl.cos_t;
   if ((double)cf > cl.cos_t) cf = nextafterf(cf, -2.f);  // the stored cone contains the exact one
   vinfo[v] = make_float4((float)cl.axis.x, (float)cl.axis.y, (float)cl.axis.z, cf);
@@ -182,26 +229,37 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
 // beforehand, so edges no half-edge produced stay unclassified and empty.)
 __global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nh, int64_t ne,
                         const int32_t* __restrict__ twin, const int32_t* __restrict__ eid, int force_both,
-                        int4* edges, int32_t* face_edges, uint8_t* cls, int32_t* count) {
+                        const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float absorb,
+                        int4* edges, int32_t* face_edges, uint8_t* cls, int32_t* count, uint8_t* fslack) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (h >= nh) return;
   int32_t u = T[h], w = T[next_corner((int32_t)h)];
   int32_t t = twin[h];
+  if (u >= w && t < 0) fslack[2 * h] = 0;  // no owner writes this side
   if (u < w) {
     int32_t e = eid[h];
     face_edges[h] = e < ne ? e : -1;
     if (e >= ne) return;
     edges[e] = make_int4(u, w, (int)(h / 3), t >= 0 ? t / 3 : -1);
     int c = 0, sides = 0;
+    uint8_t q = 0;
     if (t >= 0) {
       const int32_t c1 = T[prev_corner((int32_t)h)], c2 = T[prev_corner(t)];
-      c = classify_edge(vload_f(V, u), vload_f(V, w), vload_f(V, c1), vload_f(V, c2));
+      const f3 fu = vload_f(V, u), fw = vload_f(V, w), f1 = vload_f(V, c1), f2 = vload_f(V, c2);
+      c = classify_edge(fu, fw, f1, f2);
       if (c == EDGE_CONVEX) sides = 1;
       else if (c == EDGE_CONCAVE) sides = 2;
       else if (c == EDGE_UNKNOWN) sides = 3;
       if (force_both) sides = 3;
+      // a nearly flat edge hands its wedge to its two face prisms
+      if (absorb > 0.f && !force_both && (c == EDGE_CONVEX || c == EDGE_CONCAVE)) {
+        q = edge_slack(tod(fu), tod(fw), tod(f1), tod(f2), md[face_mesh[h / 3]].band, absorb);
+        if (q) sides = 0;
+      }
+      fslack[2 * (int64_t)t] = q;
     }
-    cls[e] = (uint8_t)(c | (sides << 2));
+    fslack[2 * h] = q;
+    cls[e] = (uint8_t)(c | (sides << 2) | (q ? EDGE_ABSORBED : 0));
     count[e] = __popc(sides);
   } else {
     int32_t e = t >= 0 ? eid[t] : -1;
@@ -276,22 +334,24 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
       }
 }
 
-// class statistics: each thread counts 16 edge-class bytes and 4 vertex words per
+// class statistics (and absorbed features): each thread counts 16 edge-class bytes and 4 vertex words per
 // 16-byte load (both arrays start 256-byte aligned), one LDS histogram per
 // block, one global add per bin and block
-__device__ inline void count_edge_class(int c, int (&loc)[9]) {
+__device__ inline void count_edge_class(int c, int (&loc)[11]) {
+  loc[9] += (c & EDGE_ABSORBED) != 0;
   c &= 3;
   loc[0] += c == EDGE_CONVEX;
   loc[1] += c == EDGE_CONCAVE;
   loc[2] += c == EDGE_FLAT;
   loc[3] += c == EDGE_UNKNOWN;
 }
-__device__ inline void count_vertex_class(uint32_t b, int (&loc)[9]) {
+__device__ inline void count_vertex_class(uint32_t b, int (&loc)[11]) {
   loc[4] += (b & V_CONVEX) != 0;
   loc[5] += (b & V_CONCAVE) != 0;
   loc[6] += (b & V_FLAT) != 0;
   loc[7] += (b & V_SADDLE) != 0;
   loc[8] += (b & V_RUFF) != 0;
+  loc[10] += (b & V_ABSORBED) != 0;
 }
 
 __global__ __launch_bounds__(256) void k_class_stats(const uint8_t* __restrict__ ecls, int64_t ne,
@@ -300,7 +360,7 @@ __global__ __launch_bounds__(256) void k_class_stats(const uint8_t* __restrict__
   if (threadIdx.x < 16) h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
-  int loc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int loc[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const uint4* e16 = reinterpret_cast<const uint4*>(ecls);
   for (int64_t i = t0; i < ne / 16; i += stride) {
     const uint4 x = e16[i];
@@ -321,15 +381,15 @@ __global__ __launch_bounds__(256) void k_class_stats(const uint8_t* __restrict__
   }
   for (int64_t i = nv / 4 * 4 + t0; i < nv; i += stride) count_vertex_class(vbits[i], loc);
 #pragma unroll
-  for (int k = 0; k < 9; k++) {
+  for (int k = 0; k < 11; k++) {
     int x = loc[k];
     for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
     if ((threadIdx.x & 63) == 0 && x) atomicAdd(&h[k], x);
   }
   __syncthreads();
-  const int map[9] = {ST_E_CONVEX, ST_E_CONCAVE, ST_E_FLAT, ST_E_UNKNOWN, ST_V_CONVEX,
-                      ST_V_CONCAVE, ST_V_FLAT,   ST_V_SADDLE, ST_V_RUFF};
-  if (threadIdx.x < 9 && h[threadIdx.x])
+  const int map[11] = {ST_E_CONVEX, ST_E_CONCAVE, ST_E_FLAT, ST_E_UNKNOWN, ST_V_CONVEX, ST_V_CONCAVE,
+                       ST_V_FLAT,   ST_V_SADDLE,  ST_V_RUFF, ST_E_ABSORBED, ST_V_ABSORBED};
+  if (threadIdx.x < 11 && h[threadIdx.x])
     atomicAdd((unsigned long long*)&stats[map[threadIdx.x]], (unsigned long long)h[threadIdx.x]);
 }
 
@@ -390,7 +450,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 enum {
   L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FN, L_FV, L_ECLS,
   L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_BFLAG,
-  L_TSCAN2, L_STATS, L_SORT, L_N
+  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_N
 };
 
 struct Layout {
@@ -429,6 +489,7 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_TSCAN2] = sizeof(int32_t) * (size_t)scan_tmp_ints(nbt + 1);
   sz[L_STATS] = sizeof(int64_t) * ST_COUNT;
   sz[L_SORT] = sort_bytes;
+  sz[L_FSLACK] = (size_t)(6 * nf + 8);
   Layout L;
   size_t o = 0;
   for (int i = 0; i < L_N; i++) {
@@ -464,8 +525,11 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                const csc_grid* grids, int32_t n_meshes, const csc_options* opt, int32_t flags, void* stream,
                csc_features** out) {
   if (!verts_d || !tris_d || !nv || !nf || !grids || !out || n_meshes <= 0) return CSC_INVALID_ARG;
-  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}};
+  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}, 0, 0.f};
   if (opt) o = *opt;
+  if (!(o.absorb_cells <= 0.24f) || o.absorb_cells != o.absorb_cells) return CSC_INVALID_ARG;
+  // 0: the default; negative: every non-flat feature keeps its own polyhedron
+  if (o.absorb_cells == 0.f) o.absorb_cells = 0.05f;
   if (!(o.eps_rel >= 0) || !(o.eps_rel < 0.5f) || o.ruff_mode < 0 || o.ruff_mode > 1 || o.scan_mode < 0 || o.scan_mode > 1 || o.saddle_mode < 0 ||
       o.saddle_mode > 2)
     return CSC_INVALID_ARG;
@@ -604,6 +668,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->d_stats = (int64_t*)(A + L.off[L_STATS]);
   F->t_sort = (void*)(A + L.off[L_SORT]);
   F->t_sort_bytes = sort_bytes;
+  F->fslack = (uint8_t*)(A + L.off[L_FSLACK]);
   F->built = F->synced = false;
 
 #define CK(x)                                        \
@@ -660,9 +725,11 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                 sort_bits, s));
   k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, tv, F->vtx_off);
   // 3. per vertex: twins, pseudonormal, class, cone; then edge numbering
+  const float absorb = o.absorb_cells > 0.f ? o.absorb_cells : 0.f;
   k_vertex<<<grid_1d(tv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, T, tv, F->vtx_off, F->vtx_corners, o.ruff_mode,
-                                                        o.saddle_mode, o.force_both_sides, F->t_a, F->vinfo,
-                                                        F->vbits, F->t_c, F->d_stats);
+                                                        o.saddle_mode, o.force_both_sides, F->vert_mesh, F->d_mesh,
+                                                        absorb, F->t_a, F->vinfo, F->vbits, F->t_c, F->fslack,
+                                                        F->d_stats);
   CK(exclusive_scan(F->t_c, F->t_c, tv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
   k_vertex_queue<<<grid_1d(tv, B), B, 0, s>>>(F->vbits, tv, F->t_c, F->vpoly);
   {
@@ -672,8 +739,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   }
   CK(exclusive_scan(F->face_edges, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
   // edges with their classes and extrusion sides
-  k_edges<<<grid_1d(nh, B), B, 0, s>>>(verts_d, T, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->edges,
-                                       F->face_edges, F->edge_cls, F->t_c);
+  k_edges<<<grid_1d(nh, B), B, 0, s>>>(verts_d, T, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->face_mesh,
+                                       F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_c, F->fslack);
   // 4. edge polyhedron queue and class statistics
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
@@ -724,6 +791,8 @@ extern "C" int csc_features_sync(csc_features* F, void* stream) {
   I.vertices_flat = st[ST_V_FLAT];
   I.vertices_saddle = st[ST_V_SADDLE];
   I.vertices_ruff = st[ST_V_RUFF];
+  I.edges_absorbed = st[ST_E_ABSORBED];
+  I.vertices_absorbed = st[ST_V_ABSORBED];
   I.n_bricks = F->n_bricks;
   I.max_band_cells = F->n_bricks * BRICK_CELLS;
   F->synced = true;

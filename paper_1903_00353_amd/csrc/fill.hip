@@ -4,12 +4,15 @@
 // Sweeping along one grid axis and giving the unset cells inside the solid the
 // value -infinity removes it.
 //
-// Along a column of cell centres no step can cross the surface without a cell
-// within half a cell of the crossing, and such a cell is a band cell whenever
-// band_cells >= 1/2. Every run of unset cells therefore lies on the side of the
-// band cells next to it: the one before it in the column, or, for the cells
-// before the column's first band cell, the one after. A column without band
-// cells does not meet the surface and is taken as outside.
+// Where a step between two neighbouring cell centres of a column crosses the
+// surface, both cells lie within one cell of the crossing, so both are band
+// cells whenever band_cells > 1 (the band is strict: d < band_cells * h). Every
+// run of unset cells therefore lies on the side of the band cells next to it:
+// the one before it in the column, or, for the cells before the column's first
+// band cell, the one after. A column without band cells does not meet the
+// surface and is taken as outside. With band_cells <= 1 only the nearer cell of
+// such a step is sure to be in the band, and the farther one, on the other
+// side, would inherit the wrong side: the call rejects those bands.
 #include "internal.h"
 
 namespace csc {
@@ -51,6 +54,7 @@ using namespace csc;
 extern "C" int csc_interior_fill(const csc_features* f, float* dense_d, void* stream) {
   if (!f || !f->built || !dense_d || f->n_meshes != 1 || f->mesh.empty()) return CSC_INVALID_ARG;
   const MeshDesc& G = f->mesh[0];
+  if (!(G.band > 1.f)) return CSC_INVALID_ARG;
   const int64_t cols = (int64_t)G.n[0] * G.n[1];
   hipStream_t s = (hipStream_t)stream;
   StageTimer t(TS_FILL, s);

@@ -119,6 +119,7 @@ __host__ __device__ inline int orient3d_sign(f3 a, f3 b, f3 c, f3 d) {
 // plane (Section 3.1: convex edges only need the outward extrusion, concave ones
 // the inward one, flat ones none; Section 8.2).
 enum { EDGE_FLAT = 0, EDGE_CONVEX = 1, EDGE_CONCAVE = 2, EDGE_UNKNOWN = 3 };
+constexpr int EDGE_ABSORBED = 16;  // class byte: bits 0-1 class, 2-3 extruded sides, 4 absorbed by its faces
 __host__ __device__ inline int classify_edge(f3 a, f3 b, f3 c1, f3 c2) {
   int s = orient3d_sign(a, b, c1, c2);
   if (s == 2) return EDGE_UNKNOWN;
@@ -131,7 +132,8 @@ enum : uint32_t {
   V_NEG = 2u,        // extrusion on the inward side
   V_POS_HEMI = 4u,   // outward extrusion is a hemisphere (else a cone)
   V_NEG_HEMI = 8u,   // inward extrusion is a hemisphere
-  V_CONVEX = 16u, V_CONCAVE = 32u, V_FLAT = 64u, V_SADDLE = 128u, V_RUFF = 256u
+  V_CONVEX = 16u, V_CONCAVE = 32u, V_FLAT = 64u, V_SADDLE = 128u, V_RUFF = 256u,
+  V_ABSORBED = 512u  // nearly flat: its region handed to the prisms of its faces
 };
 
 struct VertexClass {
@@ -219,47 +221,60 @@ struct VertexTest {
 // Closest point of the closed triangle (a, b, c) to p by the Voronoi-region tests
 // of Ericson, Real-Time Collision Detection (2005), section 5.1.5. Returns the
 // region: 0 face, 1..3 local edge j-1 (corner j-1 to corner j mod 3), 4..6
-// corner j-4; writes the barycentric weights of q.
-__host__ __device__ inline int closest_triangle(f3 p, f3 a, f3 b, f3 c, f3& q, float w[3]) {
-  f3 ab = b - a, ac = c - a, ap = p - a;
-  float d1 = dot(ab, ap), d2 = dot(ac, ap);
-  if (d1 <= 0.f && d2 <= 0.f) { w[0] = 1; w[1] = 0; w[2] = 0; q = a; return 4; }
-  f3 bp = p - b;
-  float d3v = dot(ab, bp), d4 = dot(ac, bp);
-  if (d3v >= 0.f && d4 <= d3v) { w[0] = 0; w[1] = 1; w[2] = 0; q = b; return 5; }
-  float vc = d1 * d4 - d3v * d2;
-  if (vc <= 0.f && d1 >= 0.f && d3v <= 0.f) {
-    float t = d1 / (d1 - d3v);
-    w[0] = 1.f - t; w[1] = t; w[2] = 0; q = a + ab * t; return 1;
+// corner j-4; writes the barycentric weights of q. V3 / S: f3 / float on the
+// scan path, d3 / double where the operands span many cells.
+template <typename V3, typename S>
+__host__ __device__ inline int closest_triangle_t(V3 p, V3 a, V3 b, V3 c, V3& q, S w[3]) {
+  const S zero = 0, one = 1;
+  V3 ab = b - a, ac = c - a, ap = p - a;
+  S d1 = dot(ab, ap), d2 = dot(ac, ap);
+  if (d1 <= zero && d2 <= zero) { w[0] = one; w[1] = zero; w[2] = zero; q = a; return 4; }
+  V3 bp = p - b;
+  S d3v = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3v >= zero && d4 <= d3v) { w[0] = zero; w[1] = one; w[2] = zero; q = b; return 5; }
+  S vc = d1 * d4 - d3v * d2;
+  if (vc <= zero && d1 >= zero && d3v <= zero) {
+    S t = d1 / (d1 - d3v);
+    w[0] = one - t; w[1] = t; w[2] = zero; q = a + ab * t; return 1;
   }
-  f3 cp = p - c;
-  float d5 = dot(ab, cp), d6 = dot(ac, cp);
-  if (d6 >= 0.f && d5 <= d6) { w[0] = 0; w[1] = 0; w[2] = 1; q = c; return 6; }
-  float vb = d5 * d2 - d1 * d6;
-  if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
-    float t = d2 / (d2 - d6);
-    w[0] = 1.f - t; w[1] = 0; w[2] = t; q = a + ac * t; return 3;
+  V3 cp = p - c;
+  S d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= zero && d5 <= d6) { w[0] = zero; w[1] = zero; w[2] = one; q = c; return 6; }
+  S vb = d5 * d2 - d1 * d6;
+  if (vb <= zero && d2 >= zero && d6 <= zero) {
+    S t = d2 / (d2 - d6);
+    w[0] = one - t; w[1] = zero; w[2] = t; q = a + ac * t; return 3;
   }
-  float va = d3v * d6 - d5 * d4;
-  if (va <= 0.f && (d4 - d3v) >= 0.f && (d5 - d6) >= 0.f) {
-    float t = (d4 - d3v) / ((d4 - d3v) + (d5 - d6));
-    w[0] = 0; w[1] = 1.f - t; w[2] = t; q = b + (c - b) * t; return 2;
+  S va = d3v * d6 - d5 * d4;
+  if (va <= zero && (d4 - d3v) >= zero && (d5 - d6) >= zero) {
+    S t = (d4 - d3v) / ((d4 - d3v) + (d5 - d6));
+    w[0] = zero; w[1] = one - t; w[2] = t; q = b + (c - b) * t; return 2;
   }
-  float den = 1.f / (va + vb + vc);
-  float v = vb * den, ww = vc * den;
-  w[0] = 1.f - v - ww; w[1] = v; w[2] = ww;
+  S den = one / (va + vb + vc);
+  S v = vb * den, ww = vc * den;
+  w[0] = one - v - ww; w[1] = v; w[2] = ww;
   q = a + ab * v + ac * ww;
   return 0;
 }
 
+__host__ __device__ inline int closest_triangle(f3 p, f3 a, f3 b, f3 c, f3& q, float w[3]) {
+  return closest_triangle_t<f3, float>(p, a, b, c, q, w);
+}
+
 // Closest point of the closed segment [a, b]; t is the weight of b.
-__host__ __device__ inline f3 closest_segment(f3 p, f3 a, f3 b, float& t) {
-  f3 ab = b - a;
-  float den = dot(ab, ab);
-  float s = den > 0.f ? dot(p - a, ab) / den : 0.f;
-  s = s < 0.f ? 0.f : (s > 1.f ? 1.f : s);
+template <typename V3, typename S>
+__host__ __device__ inline V3 closest_segment_t(V3 p, V3 a, V3 b, S& t) {
+  const S zero = 0, one = 1;
+  V3 ab = b - a;
+  S den = dot(ab, ab);
+  S s = den > zero ? dot(p - a, ab) / den : zero;
+  s = s < zero ? zero : (s > one ? one : s);
   t = s;
   return a + ab * s;
+}
+
+__host__ __device__ inline f3 closest_segment(f3 p, f3 a, f3 b, float& t) {
+  return closest_segment_t<f3, float>(p, a, b, t);
 }
 
 __host__ __device__ inline float norm3(f3 a) { return sqrtf(dot(a, a)); }

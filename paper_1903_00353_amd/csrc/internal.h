@@ -24,7 +24,7 @@ enum {
   ST_NE = 0, ST_NEPOLY, ST_NVPOLY, ST_NBRICKS,
   ST_E_CONVEX, ST_E_CONCAVE, ST_E_FLAT, ST_E_UNKNOWN,
   ST_V_CONVEX, ST_V_CONCAVE, ST_V_FLAT, ST_V_SADDLE, ST_V_RUFF,
-  ST_ERR, ST_COUNT = 16
+  ST_ERR, ST_E_ABSORBED, ST_V_ABSORBED, ST_COUNT = 16
 };
 
 // One mesh of a batch: its grid, band and slice of the concatenated arrays.
@@ -78,7 +78,7 @@ int check_device();          // CSC_OK or CSC_UNSUPPORTED_DEVICE / CSC_HIP_ERROR
 // timed stages (csc_timing_*)
 enum {
   TS_BUILD = 0, TS_INIT, TS_SCAN_FACE, TS_SCAN_EDGE, TS_SCAN_VERT, TS_COUNT, TS_SIGN, TS_BACKWARD,
-  TS_SCAN_FACE_BIG, TS_SCAN_EDGE_BIG, TS_SCAN_VERT_BIG, TS_FILL, N_STAGES
+  TS_SCAN_FACE_BIG, TS_SCAN_EDGE_BIG, TS_SCAN_VERT_BIG, TS_FILL, TS_SCAN_WIDE, N_STAGES
 };
 
 // whether stage timing is on (csc_timing_enable)
@@ -169,6 +169,8 @@ struct csc_features {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t* brick_flag = nullptr;    // [nbt + 1] brick marks of the build
   int32_t* t_scan2 = nullptr;       // scan temporaries of the side branch
+  uint8_t* fslack = nullptr;        // [nf][3][2] per face side: slack of the edge, of the corner's vertex
+                                    // (absorbed features, in 1/1024 cells)
 
   bool built = false;               // device work queued for the current inputs
   bool synced = false;              // counts below read back since the last build

@@ -17,6 +17,7 @@
 // device, so the whole sequence runs without host synchronisation.
 #include "geometry.h"
 #include "internal.h"
+#include "wave.h"
 
 namespace csc {
 
@@ -28,6 +29,8 @@ struct ScanArgs {
   const float* fv;             // corner positions in face order [nf][9]
   const float4* fn;
   const int4* edges;
+  const int32_t* face_edges;   // [nf][3] edge of each face side (wide faces: boundary signs)
+  const uint8_t* fslack;       // [nf][3][2] side slack of absorbed edges and vertices (1/1024 cells)
   const uint8_t* ecls;
   const float4* vinfo;
   const uint32_t* vbits;
@@ -39,13 +42,25 @@ struct ScanArgs {
   const int32_t* brick_index;
   unsigned long long* keys;
   unsigned long long* counter;  // optional: number of atomicMin issued (diagnostics)
-  int32_t* big_items;           // overflow list of polyhedra with many rows
-  int32_t* big_count;
+  // overflow list: polyhedra of this kind (item indices) with more than small_rows
+  // rows from the front, wide ones from the back; their rows are cut into
+  // chunks of OV_CHUNK, numbered in list order (ov_chunk0: an entry's first)
+  int32_t* ov_items;
+  int32_t* ov_chunk0;
+  unsigned long long* ov_ctr;   // [0] front: entries << 36 | chunks, [1] back (wide) the same
+  int64_t ov_cap;               // entries the two ends share
   int64_t* stats;               // error word (brick capacity overflow)
   int64_t cap;                  // bricks the key store holds
   int64_t nf, ne, n_items;      // totals; n_items = launch bound
   int32_t small_rows;           // more rows: one wavefront per polyhedron
   int32_t per_cell;             // 1: test every box cell by itself (Alg. 2) instead of row intervals
+  // diagnostics (null in normal runs): every packed atomicMin instruction of this
+  // launch logged as one round, its lanes' key indices at log[64 r + lane] and
+  // the mask of issuing lanes at log_mask[r]
+  uint32_t* log;
+  unsigned long long* log_mask;
+  unsigned* log_rounds;
+  int64_t log_cap;              // rounds the log holds (later rounds are counted only)
 };
 
 // Packed key of a candidate: float bits of |d| in the high word; the low word
@@ -71,7 +86,15 @@ struct Poly {
   int nt, nu, nv;   // cells along ra, ua, va (resolved once: no runtime-indexed arrays)
   int id;           // global feature id
   int mesh;
+  int wide;         // box longer than WIDE_CELLS along some axis: distances in FP64
 };
+
+// Local-frame FP32 distances carry a rounding error of about 1e-7 cells per cell
+// of box extent (the feature points lie that far from the anchor); up to 32
+// cells that stays near 3e-6 h, well inside the 1e-5 h tolerance. Polyhedra
+// with a longer box go to the overflow pass, which computes their distances in
+// FP64 from the feature's own coordinates and the cell centre.
+constexpr int WIDE_CELLS = 32;
 
 __device__ inline d3 vload_d(const float* V, int64_t i) {
   return mkd((double)V[3 * i], (double)V[3 * i + 1], (double)V[3 * i + 2]);
@@ -133,16 +156,22 @@ __device__ inline void set_plane(Poly& q, int i, f3 m, f3 through) {
 }
 
 // Face prism (Section 8.1): three inward side planes through the edges and the two
-// caps |n . (x - a)| <= band*h (both the outward and inward prism at once).
+// caps |n . (x - a)| <= band*h (both the outward and inward prism at once). The
+// side planes move out by the largest slack of the absorbed edges and vertices
+// of the face (the regions of those nearly flat features lie within it).
 __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f, Poly& q) {
   const float* fv = P.fv + 9 * f;
   d3 a = mkd(fv[0], fv[1], fv[2]), b = mkd(fv[3], fv[4], fv[5]), c = mkd(fv[6], fv[7], fv[8]);
   float4 nn = P.fn[f];
   d3 n = mkd(nn.x, nn.y, nn.z);
+  const uint8_t* sl = P.fslack + 6 * f;
+  const uint32_t sq = max(max(max((uint32_t)sl[0], (uint32_t)sl[1]), max((uint32_t)sl[2], (uint32_t)sl[3])),
+                          max((uint32_t)sl[4], (uint32_t)sl[5]));
+  const float slack = (float)sq * (1.f / 1024.f) * G.hf;  // absorbed features' slack, length units
   double lo[3], hi[3];
   const double A3[3] = {a.x, a.y, a.z}, B3[3] = {b.x, b.y, b.z}, C3[3] = {c.x, c.y, c.z}, N3[3] = {n.x, n.y, n.z};
   for (int k = 0; k < 3; k++) {
-    double r = G.whd * fabs(N3[k]) + G.epsd;
+    double r = G.whd * fabs(N3[k]) + G.epsd + (double)slack;
     lo[k] = fmin(A3[k], fmin(B3[k], C3[k])) - r;
     hi[k] = fmax(A3[k], fmax(B3[k], C3[k])) + r;
   }
@@ -153,6 +182,7 @@ __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f
   for (int j = 0; j < 3; j++) {
     f3 m = cross(nf, W[(j + 1) % 3] - W[j]);
     set_plane(q, j, m * __builtin_amdgcn_rsqf(dot(m, m)), W[j]);
+    q.pl[j][3] += slack;
   }
   float na = dot(nf, A);
   q.pl[3][0] = -nf.x; q.pl[3][1] = -nf.y; q.pl[3][2] = -nf.z; q.pl[3][3] = na + G.whf;
@@ -274,18 +304,21 @@ __device__ inline int build_vertex(const ScanArgs& P, const MeshDesc& G, int32_t
 
 template <int KIND>
 __device__ inline int build_poly(const ScanArgs& P, int64_t item, Poly& q) {
+  int nc;
   if constexpr (KIND == KIND_FACE) {
     q.mesh = P.face_mesh[item];
-    return build_face(P, P.md[q.mesh], item, q);
+    nc = build_face(P, P.md[q.mesh], item, q);
   } else if constexpr (KIND == KIND_EDGE) {
     const int32_t ent = P.items[item];
     q.mesh = P.face_mesh[P.edges[ent >> 1].z];
-    return build_edge(P, P.md[q.mesh], ent, q);
+    nc = build_edge(P, P.md[q.mesh], ent, q);
   } else {
     const int32_t ent = P.items[item];
     q.mesh = P.vert_mesh[ent >> 1];
-    return build_vertex(P, P.md[q.mesh], ent, q);
+    nc = build_vertex(P, P.md[q.mesh], ent, q);
   }
+  q.wide = nc > 0 && max(q.dim.x, max(q.dim.y, q.dim.z)) > WIDE_CELLS;
+  return nc;
 }
 
 __device__ inline int lanes_below(unsigned long long m) {
@@ -308,16 +341,19 @@ struct Rows {
   int nt;           // cells along the row
 };
 
-template <int KIND>
+template <int KIND, bool WIDE>
 __device__ inline void setup_rows(const Poly& q, const MeshDesc& G, Rows& r) {
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
+  // a wide polyhedron's planes are rounded at the size of its box: its slack
+  // grows by 1e-6 h per cell of extent (several times that rounding)
+  const float eps = WIDE ? G.eps + 1e-6f * G.hf * (float)max(q.dim.x, max(q.dim.y, q.dim.z)) : G.eps;
 #pragma unroll
   for (int i = 0; i < NPL; i++) {
     r.sl[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.ra) * G.hf;
     r.inv[i] = fabsf(r.sl[i]) > 1e-20f ? __builtin_amdgcn_rcpf(r.sl[i]) : 0.f;
     r.su[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.ua) * G.hf;
     r.sv[i] = pick3(q.pl[i][0], q.pl[i][1], q.pl[i][2], q.va) * G.hf;
-    r.k[i] = q.pl[i][3] + G.eps;
+    r.k[i] = q.pl[i][3] + eps;
   }
   r.A[0] = pick3(q.g[0], q.g[1], q.g[2], q.ra);
   r.A[1] = pick3(q.g[0], q.g[1], q.g[2], q.ua);
@@ -325,7 +361,7 @@ __device__ inline void setup_rows(const Poly& q, const MeshDesc& G, Rows& r) {
   r.R2 = (G.whf + G.eps) * (G.whf + G.eps);
   r.hf = G.hf;
   r.ihf = (float)G.inv_h;
-  r.eps = G.eps;
+  r.eps = eps;
   r.nt = q.nt;
 }
 
@@ -335,13 +371,17 @@ __device__ inline bool row_range(const Rows& r, int du, int dv, int& t0, int& t1
   const float hf = r.hf;
   constexpr int NPL = KIND == KIND_VERT ? 1 : 5;
   float lo = 0.f, hi = (float)(r.nt - 1);
+  bool dead = false;  // a plane parallel to the row with the row outside it
+  // selects, not branches: every lane takes the same instructions
 #pragma unroll
   for (int i = 0; i < NPL; i++) {
     const float v = r.su[i] * du + r.sv[i] * dv + r.k[i];
-    if (r.inv[i] > 0.f) lo = fmaxf(lo, -v * r.inv[i]);
-    else if (r.inv[i] < 0.f) hi = fminf(hi, -v * r.inv[i]);
-    else if (v < 0.f) return false;
+    const float x = -v * r.inv[i];
+    lo = fmaxf(lo, r.inv[i] > 0.f ? x : -__builtin_inff());
+    hi = fminf(hi, r.inv[i] < 0.f ? x : __builtin_inff());
+    dead = dead || (r.inv[i] == 0.f && v < 0.f);
   }
+  if (dead) return false;
   if constexpr (KIND == KIND_VERT) {  // the ball |p - v| < band*h (+ slack)
     const float qu = du * hf - r.A[1], qv = dv * hf - r.A[2];
     const float disc = r.R2 - qu * qu - qv * qv;
@@ -390,9 +430,81 @@ __device__ inline T from_lane(T x, int L) {
   else return __shfl(x, L, 64);
 }
 
+// Distance and sign code of cell (i, j, k) to the feature of a wide polyhedron
+// (global id), in FP64 relative to the cell centre: the feature's corners are
+// read again from the face and vertex arrays. The sign is always decided here,
+// with the pseudonormal of the feature holding the closest point (Section
+// 4.1.3), so that it stays right next to the surface however far the corners
+// lie. False when the cell lies outside the band.
+template <int KIND>
+__device__ inline bool dist_wide(const ScanArgs& P, const MeshDesc& G, int id, int i, int j, int k, float& d,
+                                 uint32_t& code) {
+  const d3 c = mkd(G.origin[0] + (i + 0.5) * G.h, G.origin[1] + (j + 0.5) * G.h, G.origin[2] + (k + 0.5) * G.h);
+  const d3 o = mkd(0.0, 0.0, 0.0);
+  double dd;
+  if constexpr (KIND == KIND_FACE) {
+    const float* fv = P.fv + 9 * (int64_t)id;
+    d3 qq;
+    double w[3];
+    const int region = closest_triangle_t<d3, double>(o, mkd(fv[0], fv[1], fv[2]) - c, mkd(fv[3], fv[4], fv[5]) - c,
+                                                      mkd(fv[6], fv[7], fv[8]) - c, qq, w);
+    dd = len(qq);
+    float4 n4;
+    if (region == 0) {
+      n4 = P.fn[id];
+    } else if (region <= 3) {
+      const int4 E = P.edges[P.face_edges[3 * (int64_t)id + region - 1]];
+      const float4 f1 = P.fn[E.z], f2 = P.fn[E.w];
+      n4 = make_float4(f1.x + f2.x, f1.y + f2.y, f1.z + f2.z, 0.f);
+    } else {
+      n4 = P.vinfo[P.T[3 * (int64_t)id + region - 4]];
+    }
+    // (c - q) . N >= 0: outside
+    code = dot(qq, mkd(n4.x, n4.y, n4.z)) <= 0.0 ? SIGN_POS : SIGN_NEG;
+  } else if constexpr (KIND == KIND_EDGE) {
+    const int4 E = P.edges[id - P.nf];
+    double tt;
+    const d3 qq = closest_segment_t<d3, double>(o, vload_d(P.V, E.x) - c, vload_d(P.V, E.y) - c, tt);
+    dd = len(qq);
+    d3 N;
+    if (tt <= 0.0 || tt >= 1.0) {
+      const float4 vi = P.vinfo[tt <= 0.0 ? E.x : E.y];
+      N = mkd(vi.x, vi.y, vi.z);
+    } else {
+      const float4 f1 = P.fn[E.z], f2 = P.fn[E.w];
+      N = mkd((double)f1.x + f2.x, (double)f1.y + f2.y, (double)f1.z + f2.z);
+    }
+    code = dot(qq, N) <= 0.0 ? SIGN_POS : SIGN_NEG;
+  } else {
+    const int64_t v = id - P.nf - P.ne;
+    const d3 qq = vload_d(P.V, v) - c;
+    dd = len(qq);
+    const float4 vi = P.vinfo[v];
+    code = dot(qq, mkd(vi.x, vi.y, vi.z)) <= 0.0 ? SIGN_POS : SIGN_NEG;
+  }
+  d = (float)dd;
+  return dd < G.whd;
+}
+
+// diagnostics: the lanes about to issue one atomicMin instruction record it as a
+// round of the log (index and lane mask)
+__device__ inline void log_atomic(const ScanArgs& P, uint32_t at) {
+  const unsigned long long m = __ballot(true);
+  const int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
+  unsigned r = 0;
+  if (lane == leader) r = atomicAdd(P.log_rounds, 1u);
+  r = __shfl(r, leader, 64);
+  if ((int64_t)r < P.log_cap) {
+    P.log[(int64_t)r * 64 + lane] = at;
+    if (lane == leader) P.log_mask[r] = m;
+  }
+}
+
 // exact distance of one queued candidate and its packed atomic minimum; called by
-// all lanes of the wavefront together (lane permutations), `valid` per lane
-template <int KIND, bool UNI>
+// all lanes of the wavefront together (lane permutations), `valid` per lane.
+// WIDE (overflow pass only): the distance in FP64 (dist_wide). LOG: record the
+// atomic instruction (diagnostic instantiation).
+template <int KIND, bool UNI, bool WIDE, bool LOG>
 __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned long long ent, bool valid,
                                    BrickCache& bc, unsigned& issued) {
   const int L = valid ? (int)(ent >> 48) : 0;
@@ -421,10 +533,14 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
   const int di = ra == 0 ? t : (ua == 0 ? du : dv);
   const int dj = ra == 1 ? t : (ua == 1 ? du : dv);
   const int dk = ra == 2 ? t : (ua == 2 ? du : dv);
-  const float hf = G.hf;
-  const f3 p = mk(di * hf, dj * hf, dk * hf);
+  const int i = ax + di, j = ay + dj, k = az + dk;
   float d;
   uint32_t code;
+  if constexpr (WIDE) {
+    if (!dist_wide<KIND>(P, G, id, i, j, k, d, code)) return;
+  } else {
+  const float hf = G.hf;
+  const f3 p = mk(di * hf, dj * hf, dk * hf);
   if constexpr (KIND == KIND_FACE) {
     f3 qq;
     float w[3];
@@ -446,7 +562,7 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
     code = dot(rr, nn) * side >= 0.f ? SIGN_POS : SIGN_NEG;
   }
   if (!(d < G.whf)) return;
-  const int i = ax + di, j = ay + dj, k = az + dk;
+  }
   const int64_t bl = brick_pos(G, i >> 3, j >> 3, k >> 3);
   if (bl != bc.bl) {
     bc.bl = bl;
@@ -455,23 +571,15 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
   const int32_t slot = bc.slot;
   if (slot >= 0 && slot < P.cap) {
     const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (code << 30) | (uint32_t)id;
-    atomicMin(&P.keys[(int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)], key);
+    const int64_t at = (int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
+    if constexpr (LOG) log_atomic(P, (uint32_t)at);
+    atomicMin(&P.keys[at], key);
     issued++;
   } else if (slot >= P.cap) {
     atomicOr((uint32_t*)&P.stats[ST_ERR], ERR_OVERFLOW);
   }
 }
 
-// inclusive prefix sum over the lanes of a wavefront
-__device__ inline int wave_incl_sum(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
-  }
-  return v;
-}
 
 // the row coefficients of the polyhedron held by lane L, fetched by lane
 // permutation (with the row-axis slopes when each cell is tested on its own);
@@ -525,12 +633,12 @@ __device__ inline bool cell_in(const Rows& o, int t, int du, int dv) {
 // coefficients, and queues its candidate cells in ring `qb` (this wavefront's
 // own) under the owner's lane number. Lanes with many rows thus no longer hold
 // up the others. Must be called by all lanes of the wavefront.
-template <int KIND, bool UNI>
-__device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Rows& r, int rows,
+template <int KIND, bool UNI, bool WIDE, bool LOG>
+__device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Rows& r, int rows, int row0,
                                       unsigned long long* qb, unsigned& issued) {
   const int lane = threadIdx.x & 63;
-  const int incl = wave_incl_sum(rows), excl = incl - rows;
-  const int total = __shfl(incl, 63, 64);
+  const int incl = wave_prefix_sum(rows), excl = incl - rows;
+  const int total = __builtin_amdgcn_readlane(incl, 63);
   uint32_t head = 0, tail = 0;  // the same in every lane
   BrickCache bc;
   for (int base = 0; base < total; base += 64) {
@@ -545,7 +653,7 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
       }
     }
     const int L = lo;  // with UNI lane 0 owns every row
-    const int rloc = UNI ? g : g - __shfl(excl, L, 64), nuL = from_lane<UNI>(q.nu, L);
+    const int rloc = UNI ? row0 + g : g - __shfl(excl, L, 64), nuL = from_lane<UNI>(q.nu, L);
     const int nud = nuL > 0 ? nuL : 1;  // past the last row L may hold no polyhedron
     const int dv = g < total ? rloc / nud : 0, du = g < total ? rloc - dv * nud : 0;
     int t = 0, t1 = -1;
@@ -594,7 +702,7 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const unsigned long long e = qb[(head + lane) & (QCAP - 1)];
-        finish_cand<KIND, UNI>(P, q, e, true, bc, issued);
+        finish_cand<KIND, UNI, WIDE, LOG>(P, q, e, true, bc, issued);
         head += 64;
       }
     }
@@ -605,9 +713,149 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const bool valid = (uint32_t)lane < tail - head;
     const unsigned long long e = valid ? qb[(head + lane) & (QCAP - 1)] : 0ull;
-    finish_cand<KIND, UNI>(P, q, e, valid, bc, issued);
+    finish_cand<KIND, UNI, WIDE, LOG>(P, q, e, valid, bc, issued);
   }
   // the ring is reused by the next call: finish its reads first
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The row coefficients of every lane's polyhedron, staged in LDS for the
+// one-polyhedron-per-lane pass so that the lane taking a row reads its owner's
+// with a few 16-byte loads: faces and edges inv, su, sv, k, sl of their five
+// planes, then nt, the owner's first row in the wavefront's numbering and nu;
+// vertices the same for their one plane, then the ball and cone data in (row,
+// u, v) order.
+template <int KIND>
+struct RowSlot {
+  static constexpr int F4 = KIND == KIND_VERT ? 5 : 7;  // float4 per lane
+};
+
+struct RowsOf {
+  Rows o;
+  int excl, nu;
+  f3 cax;       // vertices: cone axis in (row, u, v) order
+  float cct;    // vertices: aperture cosine, or below -1 for a hemisphere
+};
+
+template <int KIND>
+__device__ inline void put_slot(float4* sl, const Rows& r, const Poly& q, int excl) {
+  if constexpr (KIND != KIND_VERT) {
+    sl[0] = make_float4(r.inv[0], r.inv[1], r.inv[2], r.inv[3]);
+    sl[1] = make_float4(r.inv[4], r.su[0], r.su[1], r.su[2]);
+    sl[2] = make_float4(r.su[3], r.su[4], r.sv[0], r.sv[1]);
+    sl[3] = make_float4(r.sv[2], r.sv[3], r.sv[4], r.k[0]);
+    sl[4] = make_float4(r.k[1], r.k[2], r.k[3], r.k[4]);
+    sl[5] = make_float4(r.sl[0], r.sl[1], r.sl[2], r.sl[3]);
+    sl[6] = make_float4(r.sl[4], __int_as_float(r.nt), __int_as_float(excl), __int_as_float(q.nu));
+  } else {
+    sl[0] = make_float4(r.inv[0], r.su[0], r.sv[0], r.k[0]);
+    sl[1] = make_float4(r.sl[0], __int_as_float(r.nt), __int_as_float(excl), __int_as_float(q.nu));
+    sl[2] = make_float4(r.A[0], r.A[1], r.A[2], r.R2);
+    sl[3] = make_float4(r.hf, r.ihf, r.eps, q.cone[3]);
+    sl[4] = make_float4(pick3(q.cone[0], q.cone[1], q.cone[2], q.ra), pick3(q.cone[0], q.cone[1], q.cone[2], q.ua),
+                        pick3(q.cone[0], q.cone[1], q.cone[2], q.va), 0.f);
+  }
+}
+
+template <int KIND>
+__device__ inline RowsOf get_slot(const float4* sl) {
+  RowsOf w;
+  if constexpr (KIND != KIND_VERT) {
+    const float4 a = sl[0], b = sl[1], c = sl[2], d = sl[3], e = sl[4], f = sl[5], g = sl[6];
+    w.o.inv[0] = a.x; w.o.inv[1] = a.y; w.o.inv[2] = a.z; w.o.inv[3] = a.w; w.o.inv[4] = b.x;
+    w.o.su[0] = b.y; w.o.su[1] = b.z; w.o.su[2] = b.w; w.o.su[3] = c.x; w.o.su[4] = c.y;
+    w.o.sv[0] = c.z; w.o.sv[1] = c.w; w.o.sv[2] = d.x; w.o.sv[3] = d.y; w.o.sv[4] = d.z;
+    w.o.k[0] = d.w; w.o.k[1] = e.x; w.o.k[2] = e.y; w.o.k[3] = e.z; w.o.k[4] = e.w;
+    w.o.sl[0] = f.x; w.o.sl[1] = f.y; w.o.sl[2] = f.z; w.o.sl[3] = f.w; w.o.sl[4] = g.x;
+    w.o.nt = __float_as_int(g.y);
+    w.excl = __float_as_int(g.z);
+    w.nu = __float_as_int(g.w);
+    w.cct = -2.f;
+  } else {
+    const float4 a = sl[0], b = sl[1], c = sl[2], d = sl[3], e = sl[4];
+    w.o.inv[0] = a.x; w.o.su[0] = a.y; w.o.sv[0] = a.z; w.o.k[0] = a.w;
+    w.o.sl[0] = b.x;
+    w.o.nt = __float_as_int(b.y);
+    w.excl = __float_as_int(b.z);
+    w.nu = __float_as_int(b.w);
+    w.o.A[0] = c.x; w.o.A[1] = c.y; w.o.A[2] = c.z; w.o.R2 = c.w;
+    w.o.hf = d.x; w.o.ihf = d.y; w.o.eps = d.z; w.cct = d.w;
+    w.cax = mk(e.x, e.y, e.z);
+  }
+  return w;
+}
+
+// The one-polyhedron-per-lane pass: the rows of the wavefront's polyhedra (lane
+// l holds `rows` rows of its own polyhedron q, coefficients r) are dealt out
+// evenly, 64 per round, lane j taking the j-th. The owner of each row: every
+// lane marks the round position where its rows start, and a prefix maximum over
+// the positions (carrying the owner of the round's first row) gives the last
+// start at or before each. The lane computes the row's interval from the
+// owner's staged coefficients and queues its candidate cells in the
+// wavefront's ring under the owner's lane number; every 64 queued cells are
+// finished by all lanes together. Must be called by all lanes of the wavefront.
+template <int KIND, bool LOG>
+__device__ inline void scan_rows_lanes(const ScanArgs& P, const Poly& q, const Rows& r, int rows, float4* slots,
+                                       int* marks, unsigned long long* qb, unsigned& issued) {
+  constexpr int F4 = RowSlot<KIND>::F4;
+  const int lane = threadIdx.x & 63;
+  const int incl = wave_prefix_sum(rows), excl = incl - rows;
+  const int total = __builtin_amdgcn_readlane(incl, 63);
+  if (rows > 0) put_slot<KIND>(slots + lane * F4, r, q, excl);
+  uint32_t head = 0, tail = 0;  // the same in every lane
+  BrickCache bc;
+  int carry = 0;
+  for (int base = 0; base < total; base += 64) {
+    marks[lane] = -1;
+    wave_sync_lds();
+    const int s0 = excl - base;
+    if (rows > 0 && s0 >= 0 && s0 < 64) marks[s0] = lane;
+    wave_sync_lds();
+    const int L = wave_prefix_max(max(marks[lane], carry));
+    carry = __builtin_amdgcn_readlane(L, 63);
+    const int g = base + lane;
+    const RowsOf w = get_slot<KIND>(slots + L * F4);
+    const int rloc = g - w.excl;
+    const int nud = w.nu > 0 ? w.nu : 1;
+    const int dv = g < total ? rloc / nud : 0, du = g < total ? rloc - dv * nud : 0;
+    int t = 0, t1 = -1;
+    if (P.per_cell) {  // every cell of the row, each tested by itself below
+      t = 0;
+      t1 = w.o.nt - 1;
+    } else if (!row_range<KIND>(w.o, du, dv, t, t1)) {
+      t1 = -1;
+    }
+    if (g >= total) t1 = -1;
+    while (true) {
+      const bool has = t <= t1;
+      if (__ballot(has) == 0) break;
+      bool push = has && (!P.per_cell || cell_in<KIND>(w.o, t, du, dv));
+      if constexpr (KIND == KIND_VERT) {  // cone discriminant with slack (Eq. 10)
+        if (push && w.cct > -1.f) {
+          const f3 rr = mk(t * w.o.hf - w.o.A[0], du * w.o.hf - w.o.A[1], dv * w.o.hf - w.o.A[2]);
+          const float te = dot(rr, w.cax) + w.o.eps;
+          push = te >= 0.f && te * te >= w.cct * w.cct * dot(rr, rr);
+        }
+      }
+      const unsigned long long pm = __ballot(push);
+      if (push) qb[(tail + lanes_below(pm)) & (QCAP - 1)] = pack_cand(L, t, du, dv);
+      tail += (uint32_t)__popcll(pm);
+      if (has) t++;
+      if (tail - head >= 64) {
+        wave_sync_lds();
+        const unsigned long long e = qb[(head + lane) & (QCAP - 1)];
+        finish_cand<KIND, false, false, LOG>(P, q, e, true, bc, issued);
+        head += 64;
+      }
+    }
+  }
+  if (tail != head) {
+    wave_sync_lds();
+    const bool valid = (uint32_t)lane < tail - head;
+    const unsigned long long e = valid ? qb[(head + lane) & (QCAP - 1)] : 0ull;
+    finish_cand<KIND, false, false, LOG>(P, q, e, valid, bc, issued);
+  }
+  // the ring, slots and marks are reused by the next call: finish the reads first
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -623,46 +871,83 @@ __device__ inline int64_t item_count(const ScanArgs& P) {
   return P.n_items_d ? (*P.n_items_d < P.n_items ? *P.n_items_d : P.n_items) : P.n_items;
 }
 
+constexpr int OV_CHUNK = 256;  // rows of an overflow work item
+constexpr unsigned long long OV_MASK = (1ull << 36) - 1;
+
+// append this lane's polyhedron (if `mine`) to one end of the overflow list:
+// one 64-bit atomic per wavefront adds the entries and their chunks at once, so
+// entry order and chunk numbering agree
+__device__ inline void ov_append(const ScanArgs& P, bool mine, int end, int64_t item, int rows) {
+  const unsigned long long m = __ballot(mine);
+  if (!m) return;
+  const int c = mine ? (rows + OV_CHUNK - 1) / OV_CHUNK : 0;
+  const int ci = wave_prefix_sum(c), tot = __builtin_amdgcn_readlane(ci, 63);
+  const int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(&P.ov_ctr[end], ((unsigned long long)__popcll(m) << 36) | (unsigned)tot);
+  const uint32_t blo = __shfl((uint32_t)base, leader, 64), bhi = __shfl((uint32_t)(base >> 32), leader, 64);
+  base = ((unsigned long long)bhi << 32) | blo;
+  if (mine) {
+    const int64_t idx = (int64_t)(base >> 36) + lanes_below(m);
+    const int64_t slot = end ? P.ov_cap - 1 - idx : idx;
+    P.ov_items[slot] = (int32_t)item;
+    P.ov_chunk0[slot] = (int32_t)((int64_t)(base & OV_MASK) + ci - c);
+  }
+}
+
 // one polyhedron per lane, the rows of a wavefront's polyhedra shared by its
-// lanes; polyhedra with more than small_rows rows are appended to the overflow
-// list (one atomic per wavefront)
-template <int KIND>
+// lanes; polyhedra with more than small_rows rows go to the front of the
+// overflow list, wide ones to its back
+template <int KIND, bool LOG>
 __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   __shared__ unsigned long long s_q[256 / 64][QCAP];
+  __shared__ float4 s_slot[256 / 64][64 * RowSlot<KIND>::F4];
+  __shared__ int s_mark[256 / 64][64];
   const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  Poly q = {};
+  Poly q;  // not cleared: a lane without a polyhedron owns no row, so no lane reads it
+  q.wide = 0;
   const int nc = item < item_count(P) ? build_poly<KIND>(P, item, q) : 0;
   const int rows = nc > 0 ? q.nu * q.nv : 0;
-  const bool big = rows > P.small_rows;
-  const unsigned long long m = __ballot(big);
-  if (m) {
-    int base = 0;
-    const int leader = __ffsll((long long)m) - 1;
-    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(P.big_count, __popcll(m));
-    base = __shfl(base, leader, 64);
-    if (big) P.big_items[base + lanes_below(m)] = (int32_t)item;
-  }
+  const bool big = nc > 0 && (rows > P.small_rows || q.wide);
+  ov_append(P, big && !q.wide, 0, item, rows);
+  ov_append(P, big && q.wide, 1, item, rows);
   unsigned issued = 0;
-  Rows r = {};
-  if (nc > 0 && !big) setup_rows<KIND>(q, P.md[q.mesh], r);
-  scan_rows_wave<KIND, false>(P, q, r, nc > 0 && !big ? rows : 0, s_q[threadIdx.x >> 6], issued);
+  Rows r;  // set only for lanes with rows to deal; rows past the end are dropped whatever it holds
+  if (nc > 0 && !big) setup_rows<KIND, false>(q, P.md[q.mesh], r);
+  const int w = threadIdx.x >> 6;
+  scan_rows_lanes<KIND, LOG>(P, q, r, nc > 0 && !big ? rows : 0, s_slot[w], s_mark[w], s_q[w], issued);
   add_issued(P, issued, 0);
 }
 
-// a wavefront per polyhedron of the overflow list, its rows dealt out to the lanes;
-// every wavefront leaves once the list (final before this launch) is exhausted
-template <int KIND>
+// The overflow list, one chunk of OV_CHUNK rows of one polyhedron per wavefront
+// and step (a persistent grid striding over the chunks), the chunk's rows dealt
+// out to the lanes. WIDE: the back of the list (wide polyhedra), with FP64
+// distances; otherwise the front. Every lane holds the same polyhedron. The
+// chunk's entry is the last whose first chunk is at or before it (binary
+// search: chunk numbers grow along the list).
+template <int KIND, bool WIDE, bool LOG>
 __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
   __shared__ unsigned long long s_q[QCAP];
   const int lane = threadIdx.x;
-  const int32_t n_big = *P.big_count;
+  const unsigned long long ctr = P.ov_ctr[WIDE ? 1 : 0];
+  const int64_t n = (int64_t)(ctr >> 36), total = (int64_t)(ctr & OV_MASK);
   unsigned issued = 0;
-  for (int32_t w = blockIdx.x; w < n_big; w += gridDim.x) {
+  for (int64_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (P.ov_chunk0[WIDE ? P.ov_cap - 1 - mid : mid] <= ch) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t slot = WIDE ? P.ov_cap - 1 - lo : lo;
     Poly q = {};
-    if (build_poly<KIND>(P, P.big_items[w], q) <= 0) continue;  // the same for every lane
+    if (build_poly<KIND>(P, P.ov_items[slot], q) <= 0) continue;  // the same for every lane
+    const int r0 = (int)(ch - P.ov_chunk0[slot]) * OV_CHUNK, rows = q.nu * q.nv;
+    const int cnt = rows - r0 < OV_CHUNK ? rows - r0 : OV_CHUNK;
+    if (cnt <= 0) continue;
     Rows r;
-    setup_rows<KIND>(q, P.md[q.mesh], r);
-    scan_rows_wave<KIND, true>(P, q, r, lane == 0 ? q.nu * q.nv : 0, s_q, issued);  // lane 0 owns every row
+    setup_rows<KIND, WIDE>(q, P.md[q.mesh], r);
+    scan_rows_wave<KIND, true, WIDE, LOG>(P, q, r, lane == 0 ? cnt : 0, r0, s_q, issued);  // lane 0: the rows
   }
   add_issued(P, issued, 3);
 }
@@ -740,9 +1025,6 @@ struct SignArgs {
   int64_t nf, ne;
 };
 
-__device__ inline f3 rel(const float* V, int64_t i, d3 c) { return tof(vload_d(V, i) - c); }
-__device__ inline f3 xyz(float4 a) { return mk(a.x, a.y, a.z); }
-
 // mesh-local feature id of a global one
 __device__ inline int32_t local_id(const SignArgs& P, const MeshDesc& G, int32_t id) {
   return id < P.nf ? id - G.f_off
@@ -759,8 +1041,13 @@ __device__ inline void put_cell(const SignArgs& P, const MeshDesc& G, int64_t ou
   if (P.dense) P.dense[lin] = sd;
 }
 
+__device__ inline f3 rel(const float* V, int64_t i, d3 c) { return tof(vload_d(V, i) - c); }
+__device__ inline f3 xyz(float4 a) { return mk(a.x, a.y, a.z); }
+
 // a cell whose winning face candidate had its closest point on the face boundary:
-// recompute the closest point and take the pseudonormal of the feature holding it
+// recompute the closest point and take the pseudonormal of the feature holding
+// it (only for polyhedra of at most WIDE_CELLS: wide ones decide every sign in
+// the scan, in FP64)
 __device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned long long key, int i, int j,
                                        int k, int64_t out) {
   const float d = __uint_as_float((uint32_t)(key >> 32));
@@ -869,9 +1156,9 @@ WsLayout ws_layout(const csc_features* f, int64_t cap) {
   L.cnt = au(sizeof(unsigned long long) * (size_t)(cap * BRICK_CELLS + 1));
   L.scan = L.cnt + au(sizeof(int32_t) * (size_t)(cap + 1));
   L.big = L.scan + au(sizeof(int32_t) * (size_t)scan_tmp_ints(cap + 1));
-  // the three kinds' overflow counts (and a slot for alignment), then one item
-  // list per kind: the kinds are scanned concurrently
-  L.boff = L.big + au(sizeof(int32_t) * (size_t)(4 + f->nf + 2 * f->ne + 2 * f->nv));
+  // the overflow lists: 6 counters (two per kind), then per kind its entries and
+  // their first chunks (the kinds are scanned concurrently)
+  L.boff = L.big + 256 + au(2 * sizeof(int32_t) * (size_t)(f->nf + 2 * f->ne + 2 * f->nv + 3));
   L.ctr = L.boff + au(sizeof(int64_t) * (size_t)(f->n_meshes + 1));
   L.total = L.ctr + au(8 * sizeof(unsigned long long));
   return L;
@@ -897,6 +1184,8 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.fv = f->face_v;
   A.fn = f->face_n;
   A.edges = f->edges;
+  A.face_edges = f->face_edges;
+  A.fslack = f->fslack;
   A.ecls = f->edge_cls;
   A.vinfo = f->vinfo;
   A.vbits = f->vbits;
@@ -908,8 +1197,10 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.brick_index = f->brick_index;
   A.keys = keys;
   A.counter = nullptr;
-  A.big_items = nullptr;
-  A.big_count = nullptr;
+  A.ov_items = nullptr;
+  A.ov_chunk0 = nullptr;
+  A.ov_ctr = nullptr;
+  A.ov_cap = 0;
   A.stats = f->d_stats;
   A.cap = cap;
   A.nf = f->nf;
@@ -917,22 +1208,53 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.n_items = 0;
   A.small_rows = 32;
   A.per_cell = 0;
+  A.log = nullptr;
+  A.log_mask = nullptr;
+  A.log_rounds = nullptr;
+  A.log_cap = 0;
+  return A;
+}
+
+// diagnostics: which launches log their atomics (csc_scan_record_atomics)
+struct AtomicLog {
+  uint32_t* log;
+  unsigned long long* mask;
+  unsigned* rounds;
+  int64_t cap;
+  int select;  // launch tag to log (kind, 3 + kind overflow, 6 + kind wide), -1 all
+};
+
+bool logged(const AtomicLog* lg, int tag) { return lg && (lg->select < 0 || lg->select == tag); }
+
+ScanArgs with_log(ScanArgs A, const AtomicLog* lg) {
+  A.log = lg->log;
+  A.log_mask = lg->mask;
+  A.log_rounds = lg->rounds;
+  A.log_cap = lg->cap;
   return A;
 }
 
 template <int KIND>
-void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s) {
+void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s, const AtomicLog* lg) {
   {
     StageTimer t(stage, s);
-    k_scan_small<KIND><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
+    if (logged(lg, KIND)) k_scan_small<KIND, true><<<grid_1d(A.n_items, 256), 256, 0, s>>>(with_log(A, lg));
+    else k_scan_small<KIND, false><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
   }
-  StageTimer t(stage_big, s);
-  k_scan_big<KIND><<<4 * PERSIST_BLOCKS, 64, 0, s>>>(A);  // 8 wavefronts per SIMD
+  {
+    StageTimer t(stage_big, s);  // 8 wavefronts per SIMD
+    if (logged(lg, 3 + KIND)) k_scan_big<KIND, false, true><<<4 * PERSIST_BLOCKS, 64, 0, s>>>(with_log(A, lg));
+    else k_scan_big<KIND, false, false><<<4 * PERSIST_BLOCKS, 64, 0, s>>>(A);
+  }
+  // wide polyhedra (boxes over WIDE_CELLS): rare, FP64, a wavefront each
+  StageTimer t(TS_SCAN_WIDE, s);
+  if (logged(lg, 6 + KIND)) k_scan_big<KIND, true, true><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(with_log(A, lg));
+  else k_scan_big<KIND, true, false><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(A);
 }
 
 // key initialisation and the scan launches of the three kinds; counters
-// (3 slots) may be null; big: overflow lists (the three kinds' counts, a
-// fourth slot for alignment, then each kind's items). For a batch, faces run on
+// (3 slots) may be null; big: the overflow lists (6 counters in 256 bytes, then
+// each kind's entries and first chunks). For a batch, faces run on
 // the caller's stream and edges, then vertices, on the side stream, forked
 // after the key initialisation and joined at the end (their atomic minima
 // commute): the batch's mix of polyhedron sizes leaves idle slots in each
@@ -942,43 +1264,53 @@ void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s) {
 // With stage timing on, the kinds also run one after another, so that each
 // timed stage is one kernel running alone.
 void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, unsigned long long* counters,
-               int32_t* big, hipStream_t s) {
+               int32_t* big, hipStream_t s, const AtomicLog* lg = nullptr) {
+  unsigned long long* ov_ctr = (unsigned long long*)big;
+  int32_t* ov = big + 64;  // past the 256 bytes of counters
   {
     StageTimer t(TS_INIT, s);
     k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap);
-    k_zero_i32<<<1, 64, 0, s>>>(big, 3);
+    k_zero_u64<<<1, 64, 0, s>>>(ov_ctr, 6);
   }
   // a fork that cannot be set up leaves everything on the caller's stream
-  bool fork = f->n_meshes > 1 && !stage_timing_on() && f->side;
+  bool fork = f->n_meshes > 1 && !stage_timing_on() && f->side && !lg;
   if (fork)
     fork = hipEventRecord(f->ev_fork, s) == hipSuccess && hipStreamWaitEvent(f->side, f->ev_fork, 0) == hipSuccess;
   hipStream_t s2 = fork ? f->side : s;
   ScanArgs A = scan_args(f, keys, cap);
-  A.big_count = big;
-  A.big_items = big + 4;
+  A.ov_ctr = ov_ctr;
+  A.ov_cap = f->nf;
+  A.ov_items = ov;
+  A.ov_chunk0 = ov + f->nf;
   A.counter = counters;
   A.n_items = f->nf;
   A.small_rows = f->opt.small_rows[0];
   A.per_cell = f->opt.scan_mode == 1;
-  launch_kind<KIND_FACE>(A, TS_SCAN_FACE, TS_SCAN_FACE_BIG, s);
-  A.big_items = big + 4 + f->nf;
+  launch_kind<KIND_FACE>(A, TS_SCAN_FACE, TS_SCAN_FACE_BIG, s, lg);
+  ov += 2 * f->nf;
+  A.ov_ctr = ov_ctr + 2;
+  A.ov_cap = 2 * f->ne;
+  A.ov_items = ov;
+  A.ov_chunk0 = ov + 2 * f->ne;
   A.small_rows = f->opt.small_rows[1];
   A.per_cell = f->opt.scan_mode == 1;
   A.items = f->epoly;
   A.n_items = 2 * f->ne;
   A.n_items_d = &f->d_stats[ST_NEPOLY];
   A.counter = counters ? counters + 1 : nullptr;
-  A.big_count = big + 1;
-  launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, TS_SCAN_EDGE_BIG, s2);
-  A.big_items = big + 4 + f->nf + 2 * f->ne;
+  launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, TS_SCAN_EDGE_BIG, s2, lg);
+  ov += 4 * f->ne;
+  A.ov_ctr = ov_ctr + 4;
+  A.ov_cap = 2 * f->nv;
+  A.ov_items = ov;
+  A.ov_chunk0 = ov + 2 * f->nv;
   A.small_rows = f->opt.small_rows[2];
   A.per_cell = f->opt.scan_mode == 1;
   A.items = f->vpoly;
   A.n_items = 2 * f->nv;
   A.n_items_d = &f->d_stats[ST_NVPOLY];
   A.counter = counters ? counters + 2 : nullptr;
-  A.big_count = big + 2;
-  launch_kind<KIND_VERT>(A, TS_SCAN_VERT, TS_SCAN_VERT_BIG, s2);
+  launch_kind<KIND_VERT>(A, TS_SCAN_VERT, TS_SCAN_VERT_BIG, s2, lg);
   if (fork && (hipEventRecord(f->ev_join, s2) != hipSuccess || hipStreamWaitEvent(s, f->ev_join, 0) != hipSuccess))
     (void)hipStreamSynchronize(s2);  // no join on the device: finish the side branch from the host
 }
@@ -1046,6 +1378,15 @@ extern "C" int csc_scan_convert_workspace(const csc_features* f, size_t* bytes, 
   return CSC_OK;
 }
 
+extern "C" int csc_scan_convert_workspace_for(const csc_features* f, int64_t n_bricks, size_t* bytes,
+                                              int64_t* max_band_cells) {
+  if (!f || !f->built || !bytes || n_bricks < 0) return CSC_INVALID_ARG;
+  const int64_t cap = n_bricks < f->nbt ? n_bricks : f->nbt;
+  *bytes = ws_layout(f, cap).total;
+  if (max_band_cells) *max_band_cells = cap * BRICK_CELLS;
+  return CSC_OK;
+}
+
 extern "C" int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d,
                                 int32_t* feat_d, int32_t* cell_d, int64_t* n_band_d, float* dense_d, void* stream) {
   if (!f || !f->built || !workspace_d || !sdf_d || !feat_d || !cell_d || !n_band_d) return CSC_INVALID_ARG;
@@ -1076,5 +1417,32 @@ extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, 
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail_hip(e);
   for (int i = 0; i < 6; i++) counts[i] = (int64_t)h[i];
+  return CSC_OK;
+}
+
+extern "C" int csc_scan_record_atomics(const csc_features* f, void* workspace_d, size_t ws_bytes, int32_t launch,
+                                       uint32_t* log_d, unsigned long long* mask_d, int64_t max_rounds,
+                                       int64_t* rounds, void* stream) {
+  if (!f || !f->built || !workspace_d || !rounds || launch < -1 || launch > 8 || max_rounds < 0 ||
+      (max_rounds > 0 && (!log_d || !mask_d)))
+    return CSC_INVALID_ARG;
+  WsLayout L;
+  if (!cap_from_bytes(f, ws_bytes, L)) return CSC_WORKSPACE_TOO_SMALL;
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)workspace_d;
+  unsigned long long* ctr = (unsigned long long*)(W + L.ctr);
+  k_zero_u64<<<1, 64, 0, s>>>(ctr, 8);
+  AtomicLog lg;
+  lg.log = log_d;
+  lg.mask = mask_d;
+  lg.rounds = (unsigned*)(ctr + 7);
+  lg.cap = max_rounds;
+  lg.select = launch;
+  run_scans(f, (unsigned long long*)(W + L.keys), L.cap, nullptr, (int32_t*)(W + L.big), s, &lg);
+  unsigned h = 0;
+  hipError_t e = hipMemcpyAsync(&h, ctr + 7, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e);
+  *rounds = (int64_t)h;
   return CSC_OK;
 }

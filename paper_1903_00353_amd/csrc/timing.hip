@@ -17,7 +17,7 @@ int64_t g_calls[csc::N_STAGES];
 const char* g_names[csc::N_STAGES] = {"build_features", "init_keys",      "scan_faces",     "scan_edges",
                                       "scan_vertices",  "brick_count",    "sign",           "backward",
                                       "scan_faces_big", "scan_edges_big", "scan_vertices_big",
-                                      "interior_fill"};
+                                      "interior_fill",  "scan_wide"};
 
 void drain_locked() {
   for (Rec& r : g_pending) {

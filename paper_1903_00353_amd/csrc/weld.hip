@@ -18,6 +18,8 @@
 
 namespace csc {
 
+__global__ void k_clear_flag(int32_t* p) { *p = 0; }
+
 // corner keys: the coordinate bits with -0 mapped to +0; non-finite input flagged
 __global__ void k_soup_keys(const float* __restrict__ soup, int64_t n, uint32_t* kx, uint32_t* ky, uint32_t* kz,
                             int32_t* idx, int32_t* bad) {
@@ -86,60 +88,81 @@ __global__ void k_soup_tris(const int32_t* __restrict__ order, const int32_t* __
 
 using namespace csc;
 
-extern "C" int csc_weld_soup(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris_d, int64_t* nv,
-                             void* stream) {
-  if (!soup_d || !verts_d || !tris_d || !nv || nf <= 0 || 3 * nf >= INT32_MAX) return CSC_INVALID_ARG;
-  int rc = check_device();
-  if (rc != CSC_OK) return rc;
-  hipStream_t s = (hipStream_t)stream;
+namespace {
+
+// scratch bytes of a weld of n corners: 4 key arrays, 2 orders, 5 int arrays,
+// scan temporaries, the flag and count words, the radix sort's temporaries
+struct WeldLayout {
+  size_t a, scan_b, sort_bytes, total;
+};
+
+WeldLayout weld_layout(int64_t n) {
+  WeldLayout L;
+  L.sort_bytes = sort_pairs_tmp_bytes(n, 32);
+  L.a = (sizeof(int32_t) * (size_t)n + 255) & ~(size_t)255;
+  L.scan_b = (sizeof(int32_t) * (size_t)scan_tmp_ints(n) + 255) & ~(size_t)255;
+  L.total = 11 * L.a + L.scan_b + 256 + L.sort_bytes;
+  return L;
+}
+
+// the weld on scratch memory W (weld_layout(3 nf).total bytes); queues the
+// kernels and the two count copies on s, without synchronising
+hipError_t weld_queue(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris_d, char* W, const WeldLayout& L,
+                      int64_t* h_nv, int32_t* h_bad, hipStream_t s) {
   const int64_t n = 3 * nf;
-  const size_t sort_bytes = sort_pairs_tmp_bytes(n, 32);
-  if (sort_bytes == 0) return fail_hip(hipErrorInvalidValue);
-  // one scratch allocation: 4 key arrays, 2 orders, 5 int arrays, scan and sort temporaries
-  const size_t a = (sizeof(int32_t) * (size_t)n + 255) & ~(size_t)255;
-  const size_t scan_b = (sizeof(int32_t) * (size_t)scan_tmp_ints(n) + 255) & ~(size_t)255;
-  const size_t total = 11 * a + scan_b + 256 + sort_bytes;
-  char* W = nullptr;
-  hipError_t e = hipMallocAsync((void**)&W, total, s);
-  if (e != hipSuccess) return e == hipErrorOutOfMemory ? CSC_OUT_OF_MEMORY : fail_hip(e);
+  const size_t a = L.a;
   uint32_t *kx = (uint32_t*)W, *ky = (uint32_t*)(W + a), *kz = (uint32_t*)(W + 2 * a), *kt = (uint32_t*)(W + 3 * a),
            *ko = (uint32_t*)(W + 4 * a);
   int32_t *oa = (int32_t*)(W + 5 * a), *ob = (int32_t*)(W + 6 * a), *hs = (int32_t*)(W + 7 * a),
           *hc = (int32_t*)(W + 8 * a), *vid = (int32_t*)(W + 9 * a), *grp = (int32_t*)(W + 10 * a);
   int32_t* scan_tmp = (int32_t*)(W + 11 * a);
-  int32_t* bad = (int32_t*)(W + 11 * a + scan_b);
-  void* sort_tmp = W + 11 * a + scan_b + 256;
-  int64_t* nv_d = (int64_t*)(W + 11 * a + scan_b + 8);
+  int32_t* bad = (int32_t*)(W + 11 * a + L.scan_b);
+  void* sort_tmp = W + 11 * a + L.scan_b + 256;
+  int64_t* nv_d = (int64_t*)(W + 11 * a + L.scan_b + 8);
   const unsigned B = 256, G = grid_1d(n, B);
-#define CK(x)                            \
-  do {                                   \
-    hipError_t ee = (x);                 \
-    if (ee != hipSuccess) {              \
-      (void)hipFreeAsync(W, s);          \
-      return fail_hip(ee);               \
-    }                                    \
-  } while (0)
-  CK(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+  hipError_t e;
+  k_clear_flag<<<1, 1, 0, s>>>(bad);
   k_soup_keys<<<G, B, 0, s>>>(soup_d, n, kx, ky, kz, oa, bad);
   // z, then y, then x: stable, so the result is lexicographic in (x, y, z)
-  CK(sort_pairs(sort_tmp, sort_bytes, kz, ko, oa, ob, n, 32, s));
+  if ((e = sort_pairs(sort_tmp, L.sort_bytes, kz, ko, oa, ob, n, 32, s)) != hipSuccess) return e;
   k_gather_u32<<<G, B, 0, s>>>(ky, ob, n, kt);
-  CK(sort_pairs(sort_tmp, sort_bytes, kt, ko, ob, oa, n, 32, s));
+  if ((e = sort_pairs(sort_tmp, L.sort_bytes, kt, ko, ob, oa, n, 32, s)) != hipSuccess) return e;
   k_gather_u32<<<G, B, 0, s>>>(kx, oa, n, kt);
-  CK(sort_pairs(sort_tmp, sort_bytes, kt, ko, oa, ob, n, 32, s));
+  if ((e = sort_pairs(sort_tmp, L.sort_bytes, kt, ko, oa, ob, n, 32, s)) != hipSuccess) return e;
   k_soup_heads<<<G, B, 0, s>>>(kx, ky, kz, ob, n, hs, hc);
-  CK(exclusive_scan(hc, vid, n, scan_tmp, nv_d, nullptr, s));
-  CK(exclusive_scan(hs, grp, n, scan_tmp, nullptr, nullptr, s));
+  if ((e = exclusive_scan(hc, vid, n, scan_tmp, nv_d, nullptr, s)) != hipSuccess) return e;
+  if ((e = exclusive_scan(hs, grp, n, scan_tmp, nullptr, nullptr, s)) != hipSuccess) return e;
   k_soup_vertices<<<G, B, 0, s>>>(soup_d, ob, hs, grp, vid, n, hc, verts_d);  // hc reused: group -> first corner
   k_soup_tris<<<G, B, 0, s>>>(ob, hs, grp, hc, vid, n, tris_d);
-  CK(hipGetLastError());
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(h_nv, nv_d, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(h_bad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+}
+
+bool weld_args_ok(const float* soup_d, int64_t nf, const float* verts_d, const int32_t* tris_d, const int64_t* nv) {
+  return soup_d && verts_d && tris_d && nv && nf > 0 && 3 * nf < INT32_MAX;
+}
+
+}  // namespace
+
+extern "C" int csc_weld_soup(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris_d, int64_t* nv,
+                             void* stream) {
+  if (!weld_args_ok(soup_d, nf, verts_d, tris_d, nv)) return CSC_INVALID_ARG;
+  int rc = check_device();
+  if (rc != CSC_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const WeldLayout L = weld_layout(3 * nf);
+  if (L.sort_bytes == 0) return fail_hip(hipErrorInvalidValue);
+  char* W = nullptr;
+  hipError_t e = hipMallocAsync((void**)&W, L.total, s);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? CSC_OUT_OF_MEMORY : fail_hip(e);
   int64_t h_nv = 0;
   int32_t h_bad = 0;
-  CK(hipMemcpyAsync(&h_nv, nv_d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  CK(hipMemcpyAsync(&h_bad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  CK(hipFreeAsync(W, s));
-  CK(hipStreamSynchronize(s));
-#undef CK
+  e = weld_queue(soup_d, nf, verts_d, tris_d, W, L, &h_nv, &h_bad, s);
+  const hipError_t ef = hipFreeAsync(W, s);
+  if (e == hipSuccess) e = ef;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e);
   if (h_bad) return CSC_INVALID_ARG;
   *nv = h_nv;
   return CSC_OK;

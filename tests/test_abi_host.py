@@ -105,7 +105,7 @@ def test_timing_api_without_device():
     t = P.csc_timing_read()
     assert list(t) == ["build_features", "init_keys", "scan_faces", "scan_edges", "scan_vertices", "brick_count",
                        "sign", "backward", "scan_faces_big", "scan_edges_big", "scan_vertices_big",
-                       "interior_fill"]
+                       "interior_fill", "scan_wide"]
     assert all(v == (0.0, 0) for v in t.values())
 
 

@@ -75,13 +75,18 @@ def test_batch_with_empty_bands():
 
 
 def test_full_batch_against_oracle(configs):
+    """All 64 meshes of the batch (one batched fwd+bwd step) against the oracle: every
+    band cell under the agreement rules, and every mesh's gradient of
+    sum SDF^2 against the oracle's FP64 gradient with the device's closest
+    features (relative L2 <= 1e-4, every coordinate within 1e-3 max|g|)."""
     name, meshes, grids = configs(4)
-    B = P.Batch(meshes, grids, backward=False)
+    B = P.Batch(meshes, grids, backward=True)
     B.step()
     B.check()
     total = 0
-    for m in range(0, len(meshes), 5):
+    for m in range(len(meshes)):
         v, f = meshes[m]
+        print(f"[case] batch mesh {m}: F={f.shape[0]} n={grids[m].n}", flush=True)
         om = oracle.OracleMesh(v, f)
         o = om.band(grids[m])
         c, s, fe = batch_band(B, m)
@@ -89,7 +94,13 @@ def test_full_batch_against_oracle(configs):
         print(m, rep["n_device"], rep["max_err_d"], flush=True)
         assert_parity(rep)
         total += rep["n_device"]
-    assert total > 100000
+        ref = om.grad(grids[m], c, fe, np.sign(s), 2.0 * s.astype(np.float64))
+        gv = B.grad(m).cpu().numpy().astype(np.float64)
+        rel = np.linalg.norm(gv - ref) / np.linalg.norm(ref)
+        mx = np.abs(gv - ref).max() / np.abs(ref).max()
+        print(m, "grad rel L2", rel, "max", mx, flush=True)
+        assert rel <= 1e-4 and mx <= 1e-3, (m, rel, mx)
+    assert total == int(B.band_off[-1].item())
 
 
 def test_graph_replay_matches_eager():
@@ -152,3 +163,29 @@ def test_schedule_does_not_change_results():
     B.check()
     for a, b in zip(ref, [batch_band(B, m) for m in range(len(meshes))]):
         assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_headroom_covers_moved_vertices():
+    """The band store keeps room beyond the first build's bricks: a captured step
+    replayed after the meshes grew by 3% (reaching new bricks) still holds the
+    whole band, equal to a batch built on the moved vertices; without headroom
+    the same replay drops bricks and says so."""
+    meshes, grids = small_batch(4)
+    print("[case] headroom: batch of", len(meshes), flush=True)
+    tight = P.Batch(meshes, grids, headroom=1.0)
+    roomy = P.Batch(meshes, grids, headroom=1.5)
+    for B in (tight, roomy):
+        B.capture()
+        B.verts.sub_(0.5).mul_(1.03).add_(0.5)
+        B.replay()
+        torch.cuda.synchronize()
+    assert tight.overflowed()
+    assert not roomy.overflowed()
+    moved = [(roomy.verts[sum(roomy.nv[:m]):sum(roomy.nv[:m + 1])].cpu().numpy(), f) for m, (_, f) in
+             enumerate(meshes)]
+    fresh = P.Batch(moved, grids)
+    fresh.step()
+    fresh.check()
+    for m in range(len(meshes)):
+        a, b = batch_band(roomy, m), batch_band(fresh, m)
+        assert all(np.array_equal(x, y) for x, y in zip(a, b)), m

@@ -1,0 +1,141 @@
+"""The 5.2M-triangle displaced sphere on a 1024^3 grid (band 3 cells), forward and
+backward, against the CPU oracle on every z-plane of the grid:
+
+  * every band cell under the agreement rules of tests/parity.py;
+  * the FP32 gradient of L = sum SDF^2 against the oracle's FP64 gradient with
+    the device's closest features (relative L2 <= 1e-4, every coordinate within
+    1e-3 max|g|);
+  * the FP32 gradient against FP64 central differences of the oracle distance
+    on 256 seeded (vertex, axis) pairs with delta = 1e-3 h, the band set held
+    fixed: per pair |g - g_fd| <= 1e-3 |g_fd| + 1e-5 max|g_fd|. Only the cells
+    near the perturbed one-ring are recomputed, against the triangles that can
+    be closest to them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from parity import assert_parity, compare
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1903_00353_amd as P  # noqa: E402
+
+FD_PAIRS = 256
+FD_SEED = 190300353 + 5 + 2000
+
+
+@pytest.fixture(scope="module")
+def c5(configs):
+    name, meshes, grids = configs(5)
+    v, f = meshes[0]
+    g = grids[0]
+    print(f"[case] {name} F={f.shape[0]} n={g.n} band={g.band}: device fwd+bwd", flush=True)
+    verts, tris = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    feats = P.csc_build_features(verts, tris, g)
+    band = P.csc_scan_convert(feats)
+    gv = P.csc_sdf_backward(feats, band, 2.0 * band.sdf)
+    torch.cuda.synchronize()
+    out = dict(v=v, f=f, g=g, feats=feats, band=band, cell=band.cell.cpu().numpy(), sdf=band.sdf.cpu().numpy(),
+               feat=band.feat.cpu().numpy(), grad=gv.cpu().numpy().astype(np.float64))
+    out["om"] = oracle.OracleMesh(v, f)
+    inf = feats.info()
+    print("C5 features:", inf, flush=True)
+    assert inf["edges_absorbed"] > 0 and inf["vertices_absorbed"] > 0
+    return out
+
+
+def test_c5_forward_every_plane(c5):
+    g, om = c5["g"], c5["om"]
+    total = 0
+    step = 128
+    for k0 in range(0, int(g.n[2]), step):
+        o = om.band(g, k0, k0 + step)
+        rep = compare(om, g, o, c5["cell"], c5["sdf"], c5["feat"], k_range=(k0, k0 + step))
+        print(k0, {k: rep[k] for k in ("n_device", "n_oracle", "max_err_d", "missing", "extra")}, flush=True)
+        assert_parity(rep)
+        total += rep["n_device"]
+    assert total == c5["cell"].size
+
+
+def test_c5_gradient_matches_oracle(c5):
+    g, om = c5["g"], c5["om"]
+    sdf = c5["sdf"]
+    ref = om.grad(g, c5["cell"], c5["feat"], np.sign(sdf), 2.0 * sdf.astype(np.float64))
+    gv = c5["grad"]
+    rel = np.linalg.norm(gv - ref) / np.linalg.norm(ref)
+    mx = np.abs(gv - ref).max() / np.abs(ref).max()
+    print("C5 gradient vs oracle: rel L2", rel, "max |diff| / max |g|", mx, flush=True)
+    assert rel <= 1e-4
+    assert mx <= 1e-3
+
+
+def _incident(f, nv):
+    """CSR of the triangles incident to each vertex."""
+    flat = f.ravel().astype(np.int64)
+    order = np.argsort(flat, kind="stable")
+    start = np.searchsorted(flat[order], np.arange(nv + 1))
+    return order // 3, start
+
+
+def test_c5_gradient_matches_finite_differences(c5):
+    g, om, v, f = c5["g"], c5["om"], c5["v"], c5["f"]
+    h, wh = float(g.h), float(g.band) * float(g.h)
+    n0, n1 = int(g.n[0]), int(g.n[1])
+    plane = n0 * n1
+    origin = np.asarray(g.origin, dtype=np.float64)
+    V = om.V
+    corners = V[f]                                   # (F, 3, 3)
+    tlo, thi = corners.min(axis=1), corners.max(axis=1)
+    inc, start = _incident(f, V.shape[0])
+    order = np.argsort(c5["cell"], kind="stable")
+    cs = c5["cell"][order].astype(np.int64)
+    delta = 1e-3 * h
+    rng = np.random.default_rng(FD_SEED)
+    samples = []
+    kink_cells = []
+    for s in range(FD_PAIRS):
+        vi, ax = int(rng.integers(V.shape[0])), int(rng.integers(3))
+        ring = inc[start[vi]:start[vi + 1]]
+        # every cell whose distance can change lies within band*h of a ring triangle
+        lo = tlo[ring].min(axis=0) - wh - 2 * delta - 1e-9
+        hi = thi[ring].max(axis=0) + wh + 2 * delta + 1e-9
+        i0 = np.maximum(np.ceil((lo - origin) / h - 0.5), 0).astype(np.int64)
+        i1 = np.floor((hi - origin) / h - 0.5).astype(np.int64)
+        a, b = np.searchsorted(cs, i0[2] * plane), np.searchsorted(cs, (i1[2] + 1) * plane)
+        cells = cs[a:b]
+        ci, cj = cells % n0, (cells // n0) % n1
+        cells = cells[(ci >= i0[0]) & (ci <= i1[0]) & (cj >= i0[1]) & (cj <= i1[1])]
+        # triangles that can be closest to those cells (each band cell's closest
+        # triangle lies within band*h of it)
+        cand = np.nonzero(np.all((tlo <= hi + wh) & (thi >= lo - wh), axis=1))[0]
+        Vp, Vm = V.copy(), V.copy()
+        Vp[vi, ax] += delta
+        Vm[vi, ax] -= delta
+        d0, _ = om.cells_dist(g, cells, sub=cand)
+        dp, _ = om.cells_dist(g, cells, sub=cand, V64=Vp)
+        dm, _ = om.cells_dist(g, cells, sub=cand, V64=Vm)
+        kink = np.abs(dp + dm - 2 * d0) > 1e-3 * delta
+        kink_cells.append(cells[kink])
+        samples.append((vi, ax, cells, dp, dm))
+    # one adjoint run with the upstream zeroed on every kink cell of any sample;
+    # the finite differences leave out the same cells
+    kinks = np.unique(np.concatenate(kink_cells))
+    cell = c5["cell"].astype(np.int64)
+    up = (2.0 * c5["sdf"]).astype(np.float32)
+    up[np.isin(cell, kinks)] = 0.0
+    print(f"[case] C5 FD: {FD_PAIRS} pairs, {kinks.size} kink cells masked", flush=True)
+    band = c5["band"]
+    gv = P.csc_sdf_backward(c5["feats"], band, torch.from_numpy(up).cuda()).cpu().numpy().astype(np.float64)
+    fds, devs = [], []
+    for vi, ax, cells, dp, dm in samples:
+        keep = ~np.isin(cells, kinks)
+        fds.append(np.sum(((dp ** 2 - dm ** 2) / (2 * delta))[keep]))
+        devs.append(gv[vi, ax])
+    fds, devs = np.array(fds), np.array(devs)
+    tol = 1e-3 * np.abs(fds) + 1e-5 * np.abs(fds).max()
+    err = np.abs(devs - fds)
+    print("C5 FD: max |g_fd|", np.abs(fds).max(), "worst err / tol", (err / tol).max(), flush=True)
+    assert np.abs(fds).max() > 0
+    assert np.all(err <= tol), (int((err > tol).sum()), float((err / tol).max()))

@@ -107,3 +107,34 @@ def test_fill_rejects_batched_handle():
     d = torch.empty(8, dtype=torch.float32, device="cuda")
     with pytest.raises(P.CscError):
         P.csc_interior_fill(B.f, d)
+
+
+@pytest.mark.parametrize("band", [0.6, 1.0])
+def test_fill_rejects_thin_band(band):
+    """With band_cells <= 1 a column can cross the surface between a band cell and
+    an unset cell, which would take the wrong side: the call refuses."""
+    v, f = meshgen.cube()
+    g = Grid.unit(32, band)
+    verts, tris = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    feats = P.csc_build_features(verts, tris, g)
+    d = torch.empty(g.ncells, dtype=torch.float32, device="cuda")
+    P.csc_scan_convert(feats, dense=d)
+    with pytest.raises(P.CscError) as ei:
+        P.csc_interior_fill(feats, d)
+    assert ei.value.code == 1
+
+
+def test_cube_thin_band_every_cell():
+    """The thinnest accepted bands (just over one cell) on the cube, every cell
+    against the closed form, with the cube's faces a quarter cell off the centre
+    planes (origin shifted)."""
+    v, f = meshgen.cube()
+    for band in (1.05, 1.5):
+        g = Grid(n=(64, 64, 64), h=1.0 / 64, band=band, origin=(0.004, -0.002, 0.0039))
+        print("[case] cube thin band", band, flush=True)
+        before, after, cell = filled(v, f, g)
+        off = check_band_untouched(before, after, cell)
+        idx = np.nonzero(off)[0]
+        inside = cube_inside(oracle.cell_centres(g, idx))
+        assert inside.any() and (~inside).any()
+        assert np.array_equal(after[idx] < 0, inside)

@@ -77,12 +77,12 @@ def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
     F, E = info["n_faces"], info["n_edges"]
     if stage == "init_keys":
         return 8 * info["n_bricks"] * 512
-    if stage == "scan_faces":   # triangles, vertices, face normals, one u64 per atomic
-        return 12 * F + 12 * nv + 12 * F + 8 * atomics[0]
-    if stage == "scan_edges":   # edge records, vertices, normals, atomics
-        return 16 * info["n_edge_polyhedra"] + 12 * nv + 12 * F + 8 * atomics[1]
-    if stage == "scan_vertices":
-        return 16 * info["n_vertex_polyhedra"] + 12 * nv + 8 * atomics[2]
+    if stage == "scan_faces":   # per face its corners and unit normal (36 + 12 B), one u64 per atomic
+        return 48 * F + 8 * atomics[0]
+    if stage == "scan_edges":   # per edge polyhedron its record, endpoints and two normals (16 + 24 + 24 B)
+        return 64 * info["n_edge_polyhedra"] + 8 * atomics[1]
+    if stage == "scan_vertices":  # per vertex polyhedron its position, axis and aperture (12 + 16 B)
+        return 28 * info["n_vertex_polyhedra"] + 8 * atomics[2]
     if stage.endswith("_big"):  # overflow launches: their atomics (geometry counted above)
         return 8 * atomics[3 + ["scan_faces_big", "scan_edges_big", "scan_vertices_big"].index(stage)]
     if stage == "sign":         # one key read and (sdf, id, cell) written per band cell
@@ -121,19 +121,39 @@ def atomic_rates(P, feats, ws, n_keys, nv, reps=10):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    import numpy as np
     for stage, tag in list(SCAN_LAUNCHES.items()) + [("all", -1)]:
         log, mask = P.csc_scan_record_atomics(feats, ws, tag)
-        n = popcount64(mask.cpu().numpy())
+        m = mask.cpu().numpy()
+        n = popcount64(m)
         if n == 0:
             continue
         ms = timed(lambda: P.csc_atomic_replay(log, mask, keys, 0))
         ms_read = timed(lambda: P.csc_atomic_replay(log, mask, keys, 1))
         ms_wg = timed(lambda: P.csc_atomic_replay(log, mask, keys, 2))
         ms_st = timed(lambda: P.csc_atomic_replay(log, mask, keys, 3))
+        # locality: distinct 128-byte lines (16 keys) and bricks per instruction, and
+        # the rate of the same atomics issued in address order (64 per instruction)
+        bits = np.unpackbits(m.view(np.uint8).reshape(-1, 8), axis=1, bitorder="little").astype(bool)
+        addr = log.cpu().numpy().view(np.uint32).reshape(-1, 64).astype(np.int64)
+        rows = np.repeat(np.arange(addr.shape[0]), 64).reshape(-1, 64)[bits]
+        a = addr[bits]
+        lines = np.unique(rows * (1 << 32) + (a >> 4)).size / addr.shape[0]
+        bricks = np.unique(rows * (1 << 32) + (a >> 9)).size / addr.shape[0]
+        srt = np.sort(a).astype(np.uint32)
+        pad = (-srt.size) % 64
+        slog = torch.from_numpy(np.concatenate([srt, np.zeros(pad, np.uint32)]).view(np.int32)).to(ws.device)
+        smask_np = np.full(slog.numel() // 64, -1, dtype=np.int64)
+        if pad:
+            smask_np[-1] = (1 << (64 - pad)) - 1
+        smask = torch.from_numpy(smask_np).to(ws.device)
+        ms_sorted = timed(lambda: P.csc_atomic_replay(slog, smask, keys, 0))
         out[stage] = {"atomics": n, "instructions": int(mask.numel()), "lanes_per_instruction": n / mask.numel(),
+                      "lines_per_instruction": lines, "bricks_per_instruction": bricks,
                       "replay_ms": ms, "log_read_ms": ms_read, "workgroup_scope_ms": ms_wg, "plain_store_ms": ms_st,
-                      "rate_G_per_s": n / (ms * 1e-3) / 1e9}
-        del log, mask
+                      "rate_G_per_s": n / (ms * 1e-3) / 1e9, "sorted_replay_ms": ms_sorted,
+                      "sorted_rate_G_per_s": n / (ms_sorted * 1e-3) / 1e9}
+        del log, mask, slog, smask
     g = torch.zeros(max(1, nv), 3, dtype=torch.float32, device=ws.device)
     nadd = 1 << 23
     ms = timed(lambda: P.csc_fadd_rate(g, nadd))
@@ -286,13 +306,14 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     B = P.Batch(meshes, grids, device=dev, backward=True, graph_safe=True)
     from paper_1903_00353_amd import autotune
+    tune_ms = None
     if args.small_rows:
-        schedule = parse_rows(args.small_rows)
-        B.options = P.make_options(small_rows=schedule)
+        schedule = (parse_rows(args.small_rows), args.scan_grid, args.absorb)
+        B.options = autotune.options_for(schedule)
         B.f = P.csc_build_features_batched(B.verts, B.tris, B.nv, B.nf, B.grids, B.options, flags=B.flags,
                                            reuse=B.f)
     else:
-        schedule, _ = autotune.tune_batch(B)
+        schedule, tune_ms = autotune.tune_batch(B)  # (small_rows, scan_grid, absorb_cells)
     info = B.f.info()
     # untimed diagnostics: atomics per scan launch, band size, weighted vertices per band cell
     atomics = P.csc_scan_convert_count(B.f, B.workspace)
@@ -353,7 +374,8 @@ def bench_batch(args):
         "atomic_peaks": rates,
         "step_ms": {"median": med_graph, "min": min_graph, "launch": "eager" if args.no_graph else "graph replay"},
         "batched_eager": {"value": M / (ms_eager * 1e-3), "ms_per_step": ms_eager},
-        "schedule": {"small_rows": list(schedule)},
+        "schedule": {"small_rows": list(schedule[0]), "scan_grid": schedule[1], "absorb_cells": schedule[2],
+                     "tuning_ms": tune_ms or None},
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
         "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
                     "edges_big": atomics[4], "vertices_big": atomics[5]},
@@ -400,8 +422,8 @@ def bench_batch(args):
                        "min": min_pm, "band_size": M_per}
     res["speedup_batched_vs_per_mesh"] = ms_per_mesh / ms_graph
     # ablation: forward with every box cell tested by itself (Alg. 2 as printed)
-    B2 = P.Batch(meshes, grids, options=P.make_options(small_rows=schedule, scan_mode=1), device=dev, backward=False,
-                 graph_safe=True)
+    B2 = P.Batch(meshes, grids, options=autotune.options_for(schedule, P.make_options(scan_mode=1)), device=dev,
+                 backward=False, graph_safe=True)
     B2.step()
     avg2, ms2, _ = stage_averages(B2.step, max(3, args.steps // 4))
     res["ablation_per_cell_scan"] = {"fwd_ms": ms2, "fwd_ms_row_intervals": ms_fwd,
@@ -493,8 +515,12 @@ def bench_single(args):
     verts = torch.from_numpy(v).to(dev)
     tris = torch.from_numpy(f).to(dev)
     from paper_1903_00353_amd import autotune
-    schedule = parse_rows(args.small_rows) if args.small_rows else autotune.tune_single(verts, tris, g)[0]
-    opts = P.make_options(small_rows=schedule)
+    tune_ms = None
+    if args.small_rows:
+        schedule = (parse_rows(args.small_rows), args.scan_grid, args.absorb)
+    else:
+        schedule, tune_ms = autotune.tune_single(verts, tris, g)  # (small_rows, scan_grid, absorb_cells)
+    opts = autotune.options_for(schedule)
     feats = P.csc_build_features(verts, tris, g, opts)
     info = feats.info()
     nbytes, mx = P.csc_scan_convert_workspace(feats)
@@ -556,7 +582,8 @@ def bench_single(args):
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
         "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
                     "edges_big": atomics[4], "vertices_big": atomics[5]},
-        "schedule": {"small_rows": list(schedule)},
+        "schedule": {"small_rows": list(schedule[0]), "scan_grid": schedule[1], "absorb_cells": schedule[2],
+                     "tuning_ms": tune_ms or None},
         "features": info,
         "kernel_source_sha": kernel_source_sha(),
     }
@@ -593,7 +620,8 @@ def summarize_trace(args):
 def bench_per_cell(P, verts, tris, g, schedule, ws, out, reps):
     """Ablation: the forward pass with every box cell tested by itself (Alg. 2 as
     printed, scan_mode 1) instead of row intervals; per-stage times."""
-    opts = P.make_options(small_rows=schedule, scan_mode=1)
+    from paper_1903_00353_amd import autotune
+    opts = autotune.options_for(schedule, P.make_options(scan_mode=1))
     f1 = P.csc_build_features(verts, tris, g, opts)
     nbytes, _ = P.csc_scan_convert_workspace(f1)
     if nbytes > ws.numel():
@@ -662,6 +690,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--small-rows", help="fixed schedule faces,edges,vertices instead of the autotuned one")
+    ap.add_argument("--scan-grid", type=int, default=2, help="with --small-rows: scan_grid (1, 2, 3)")
+    ap.add_argument("--absorb", type=float, default=0.05, help="with --small-rows: absorb_cells (negative: off)")
     ap.add_argument("--timed-only", action="store_true",
                     help="only the timed fwd+bwd steps (for profiling: no forward-only, per-mesh or CPU legs)")
     ap.add_argument("--no-graph", action="store_true", help="batch64: time eager steps instead of graph replays")

@@ -87,7 +87,15 @@ typedef struct csc_options {
                                the exact distance to its triangle). Features whose slack is at most
                                this many cells are absorbed that way. 0 = default (0.05); negative: every
                                non-flat edge and vertex keeps its own polyhedron, as in Section 8; at most
-                               0.24. Only the speed depends on it. */
+                               0.24. The field agrees within the rounding of the FP32 distance whatever
+                               the cap; bit for bit, the last bits of |d| and the choice among equally
+                               close features can change with it. */
+  int32_t scan_grid;        /* schedule of the one-polyhedron-per-lane scan pass (64 polyhedra per
+                               wavefront): 1 a launch with one wavefront per 64 polyhedra; 2 a
+                               persistent grid (as many wavefronts as fit on the device at once)
+                               striding over the groups of 64; 3 that grid taking the groups from a
+                               device counter in the order the wavefronts ask. 0 = default (2). Only
+                               the speed depends on it (the autotuner in the binding picks one). */
 } csc_options;
 
 typedef struct csc_features csc_features; /* opaque, library-owned, device resident */

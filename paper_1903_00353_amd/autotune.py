@@ -1,11 +1,20 @@
 """Schedule autotuner.
 
-The one schedule choice of the scan conversion is, per polyhedron kind (faces,
-edges, vertices), the number of rows above which a polyhedron is walked by a
-whole wavefront instead of a single thread. Only the speed depends on it. The
-tuner times each candidate on the caller's own workload with the library's
-stage events (HIP events on the working stream), keeps the fastest per kind,
-and caches the choice as JSON keyed by the device and the workload's shape.
+The scan conversion has three schedule choices, none of which changes a value:
+  * per polyhedron kind (faces, edges, vertices), the number of rows above which
+    a polyhedron is walked in chunks by whole wavefronts instead of by one lane
+    (``small_rows``);
+  * how the one-lane-per-polyhedron pass hands out its polyhedra (``scan_grid``:
+    a launch sized to the items, a persistent grid striding over them, or a
+    persistent grid taking groups from a device counter);
+  * the largest side slack a face prism takes on to absorb the extrusions of
+    nearly flat edges and vertices (``absorb_cells``; negative: none absorbed).
+The tuner times candidates on the caller's own workload with the library's stage
+events (HIP events on the working stream): first ``small_rows`` per kind (each
+kind's one-lane launch plus its overflow launch), then ``scan_grid`` and
+``absorb_cells`` one after the other on the time of the whole forward pass
+(scans and sign). It caches the choice as JSON keyed by the device and the
+workload's shape.
 """
 from __future__ import annotations
 
@@ -14,7 +23,11 @@ import math
 import os
 
 CANDIDATES = (8, 16, 32, 64, 128, 1 << 24)
+GRID_CANDIDATES = (1, 2, 3)
+ABSORB_CANDIDATES = (-1.0, 0.02, 0.05, 0.1, 0.2)
 KIND_STAGES = ("scan_faces", "scan_edges", "scan_vertices")
+FORWARD_STAGES = ("init_keys", "scan_faces", "scan_edges", "scan_vertices", "scan_faces_big", "scan_edges_big",
+                  "scan_vertices_big", "scan_wide", "brick_count", "sign")
 
 
 def cache_path() -> str:
@@ -31,19 +44,20 @@ def signature(nf_list, grids) -> str:
     band = max(float(g.band) for g in grids)
     tri_cells = faces / max(1.0, cells ** (2.0 / 3.0))  # triangles per cell of surface area (rough)
     return (f"{getattr(dev, 'gcnArchName', dev.name)}|n={len(grids)}|F=2^{round(math.log2(max(faces, 1)))}"
-            f"|cells=2^{round(math.log2(max(cells, 1)))}|band={band:g}|tpc=2^{round(math.log2(max(tri_cells, 1e-9)))}")
+            f"|cells=2^{round(math.log2(max(cells, 1)))}|band={band:g}|tpc=2^{round(math.log2(max(tri_cells, 1e-9)))}"
+            f"|v2")
 
 
 def load(sig: str):
     try:
         with open(cache_path()) as fh:
             rec = json.load(fh).get(sig)
-        return tuple(rec["small_rows"]) if rec else None
-    except (OSError, ValueError, KeyError):
+        return (tuple(rec["small_rows"]), int(rec["scan_grid"]), float(rec["absorb_cells"])) if rec else None
+    except (OSError, ValueError, KeyError, TypeError):
         return None
 
 
-def save(sig: str, small_rows, timings):
+def save(sig: str, choice, timings):
     path = cache_path()
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -52,7 +66,8 @@ def save(sig: str, small_rows, timings):
                 data = json.load(fh)
         except (OSError, ValueError):
             data = {}
-        data[sig] = {"small_rows": list(small_rows), "ms": timings}
+        data[sig] = {"small_rows": list(choice[0]), "scan_grid": choice[1], "absorb_cells": choice[2],
+                     "ms": timings}
         with open(path + ".tmp", "w") as fh:
             json.dump(data, fh, indent=1)
         os.replace(path + ".tmp", path)
@@ -60,7 +75,7 @@ def save(sig: str, small_rows, timings):
         pass
 
 
-def _time_stages(run, reps):
+def _stage_times(run, reps):
     import torch
 
     import paper_1903_00353_amd as P
@@ -72,61 +87,100 @@ def _time_stages(run, reps):
         run()
     torch.cuda.synchronize()
     P.csc_timing_enable(False)
-    t = P.csc_timing_read()
-    # each kind's time = its one-thread-per-polyhedron launch + its overflow launch
-    return [t[k][0] / max(1, t[k][1]) + t[k + "_big"][0] / max(1, t[k + "_big"][1]) for k in KIND_STAGES]
+    return {k: ms / reps for k, (ms, c) in P.csc_timing_read().items()}
 
 
-def tune_batch(batch, candidates=CANDIDATES, reps=3, use_cache=True):
-    """Pick small_rows per kind for a paper_1903_00353_amd.Batch; rebuilds it with the
-    choice (before any graph capture). Returns (small_rows, {candidate: [ms per kind]})."""
+def _kind_times(t):
+    # each kind's time = its one-lane-per-polyhedron launch + its overflow launch
+    return [t[k] + t[k + "_big"] for k in KIND_STAGES]
+
+
+def _forward_time(t):
+    return sum(t[k] for k in FORWARD_STAGES)
+
+
+def _search(measure, base, reps):
+    """measure(options) -> per-stage ms per call; returns (choice, timings)."""
+    timings = {}
+    for c in CANDIDATES:
+        timings[f"rows={c}"] = measure(_with(base, rows=(c, c, c)), reps)
+    rows = tuple(min(CANDIDATES, key=lambda c: _kind_times(timings[f"rows={c}"])[k]) for k in range(3))
+    best_grid, best_t = base.scan_grid or 2, None
+    for g in GRID_CANDIDATES:
+        t = _forward_time(measure(_with(base, rows=rows, grid=g), reps))
+        timings[f"grid={g}"] = t
+        if best_t is None or t < best_t:
+            best_grid, best_t = g, t
+    best_absorb, best_t = 0.05, None
+    for a in ABSORB_CANDIDATES:
+        t = _forward_time(measure(_with(base, rows=rows, grid=best_grid, absorb=a), reps))
+        timings[f"absorb={a}"] = t
+        if best_t is None or t < best_t:
+            best_absorb, best_t = a, t
+    return (rows, best_grid, best_absorb), timings
+
+
+def tune_batch(batch, reps=3, use_cache=True):
+    """Pick the schedule for a paper_1903_00353_amd.Batch; rebuilds it with the
+    choice (before any graph capture). Returns ((small_rows, scan_grid,
+    absorb_cells), timings)."""
     import paper_1903_00353_amd as P
     sig = signature(batch.nf, batch.grids)
     base = batch.options if batch.options is not None else P.make_options()
-    best = load(sig) if use_cache else None
+    choice = load(sig) if use_cache else None
     timings = {}
-    if best is None:
-        for c in candidates:
-            batch.options = _with_rows(base, (c, c, c))
-            batch.f = P.csc_build_features_batched(batch.verts, batch.tris, batch.nv, batch.nf, batch.grids,
-                                                   batch.options, flags=batch.flags, reuse=batch.f)
-            timings[c] = _time_stages(batch.step, reps)
-        best = tuple(min(candidates, key=lambda c: timings[c][k]) for k in range(3))
-        save(sig, best, {str(c): v for c, v in timings.items()})
-    batch.options = _with_rows(base, best)
-    batch.f = P.csc_build_features_batched(batch.verts, batch.tris, batch.nv, batch.nf, batch.grids, batch.options,
-                                           flags=batch.flags, reuse=batch.f)
-    return best, timings
+
+    def rebuild(opt):
+        batch.options = opt
+        batch.f = P.csc_build_features_batched(batch.verts, batch.tris, batch.nv, batch.nf, batch.grids,
+                                               batch.options, flags=batch.flags, reuse=batch.f)
+
+    if choice is None:
+        def measure(opt, reps):
+            rebuild(opt)
+            return _stage_times(batch.step, reps)
+        choice, timings = _search(measure, base, reps)
+        save(sig, choice, timings)
+    rebuild(_with(base, rows=choice[0], grid=choice[1], absorb=choice[2]))
+    return choice, timings
 
 
-def tune_single(verts, tris, grid, options=None, candidates=CANDIDATES, reps=3, use_cache=True):
-    """small_rows for one mesh (single-mesh entry points); returns (small_rows, timings)."""
+def tune_single(verts, tris, grid, options=None, reps=3, use_cache=True):
+    """The schedule for one mesh (single-mesh entry points); returns (choice, timings)."""
     import torch
 
     import paper_1903_00353_amd as P
     sig = signature([tris.shape[0]], [grid])
     base = options if options is not None else P.make_options()
-    best = load(sig) if use_cache else None
+    choice = load(sig) if use_cache else None
     timings = {}
-    if best is None:
-        f = None
-        for c in candidates:
-            opt = _with_rows(base, (c, c, c))
-            f = P.csc_build_features(verts, tris, grid, opt, reuse=f)
+    if choice is None:
+        def measure(opt, reps):
+            f = P.csc_build_features(verts, tris, grid, opt)
             nbytes, mx = P.csc_scan_convert_workspace(f)
             ws = torch.empty(nbytes, dtype=torch.uint8, device=verts.device)
             out = (torch.empty(mx, dtype=torch.float32, device=verts.device),
                    torch.empty(mx, dtype=torch.int32, device=verts.device),
                    torch.empty(mx, dtype=torch.int32, device=verts.device),
                    torch.zeros(1, dtype=torch.int64, device=verts.device))
-            timings[c] = _time_stages(lambda: P.csc_scan_convert(f, ws, out, sync_count=False), reps)
-        f.free()
-        best = tuple(min(candidates, key=lambda c: timings[c][k]) for k in range(3))
-        save(sig, best, {str(c): v for c, v in timings.items()})
-    return best, timings
+            t = _stage_times(lambda: P.csc_scan_convert(f, ws, out, sync_count=False), reps)
+            f.free()
+            return t
+        choice, timings = _search(measure, base, reps)
+        save(sig, choice, timings)
+    return choice, timings
 
 
-def _with_rows(opt, rows):
+def options_for(choice, base=None):
+    """csc_options with a tuner choice applied."""
     import paper_1903_00353_amd as P
-    return P.make_options(opt.eps_rel, opt.ruff_mode, opt.saddle_mode, opt.force_both_sides, rows, opt.scan_mode,
-                          opt.absorb_cells)
+    base = base if base is not None else P.make_options()
+    return _with(base, rows=choice[0], grid=choice[1], absorb=choice[2])
+
+
+def _with(opt, rows=None, grid=None, absorb=None):
+    import paper_1903_00353_amd as P
+    return P.make_options(opt.eps_rel, opt.ruff_mode, opt.saddle_mode, opt.force_both_sides,
+                          tuple(opt.small_rows) if rows is None else rows, opt.scan_mode,
+                          opt.absorb_cells if absorb is None else absorb,
+                          opt.scan_grid if grid is None else grid)

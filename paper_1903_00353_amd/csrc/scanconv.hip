@@ -54,6 +54,8 @@ struct ScanArgs {
   int64_t nf, ne, n_items;      // totals; n_items = launch bound
   int32_t small_rows;           // more rows: one wavefront per polyhedron
   int32_t per_cell;             // 1: test every box cell by itself (Alg. 2) instead of row intervals
+  int32_t grid_mode;            // one-polyhedron-per-lane pass: SCAN_GRID_* (how waves get their polyhedra)
+  unsigned long long* head;     // SCAN_GRID_QUEUE: next group of 64 polyhedra to hand out
   // diagnostics (null in normal runs): every packed atomicMin instruction of this
   // launch logged as one round, its lanes' key indices at log[64 r + lane] and
   // the mask of issuing lanes at log_mask[r]
@@ -895,27 +897,51 @@ __device__ inline void ov_append(const ScanArgs& P, bool mine, int end, int64_t 
   }
 }
 
+// How the waves of the one-polyhedron-per-lane pass get their polyhedra (64
+// consecutive items per group): one group per wave of a grid sized to the
+// items; a persistent grid (as many waves as fit at once) striding over the
+// groups; or that grid taking groups from a device counter in the order the
+// waves ask (an atomic head over the kind's whole list, so waves that drew
+// cheap groups take more).
+enum { SCAN_GRID_LAUNCH = 1, SCAN_GRID_STRIDE = 2, SCAN_GRID_QUEUE = 3 };
+
 // one polyhedron per lane, the rows of a wavefront's polyhedra shared by its
 // lanes; polyhedra with more than small_rows rows go to the front of the
 // overflow list, wide ones to its back
+template <int KIND, bool LOG>
+__device__ inline void scan_group(const ScanArgs& P, int64_t item, int64_t count, float4* slots, int* marks,
+                                  unsigned long long* qb, unsigned& issued) {
+  Poly q;  // not cleared: a lane without a polyhedron owns no row, so no lane reads it
+  q.wide = 0;
+  const int nc = item < count ? build_poly<KIND>(P, item, q) : 0;
+  const int rows = nc > 0 ? q.nu * q.nv : 0;
+  const bool big = nc > 0 && (rows > P.small_rows || q.wide);
+  ov_append(P, big && !q.wide, 0, item, rows);
+  ov_append(P, big && q.wide, 1, item, rows);
+  Rows r;  // set only for lanes with rows to deal; rows past the end are dropped whatever it holds
+  if (nc > 0 && !big) setup_rows<KIND, false>(q, P.md[q.mesh], r);
+  scan_rows_lanes<KIND, LOG>(P, q, r, nc > 0 && !big ? rows : 0, slots, marks, qb, issued);
+}
+
 template <int KIND, bool LOG>
 __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   __shared__ unsigned long long s_q[256 / 64][QCAP];
   __shared__ float4 s_slot[256 / 64][64 * RowSlot<KIND>::F4];
   __shared__ int s_mark[256 / 64][64];
-  const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  Poly q;  // not cleared: a lane without a polyhedron owns no row, so no lane reads it
-  q.wide = 0;
-  const int nc = item < item_count(P) ? build_poly<KIND>(P, item, q) : 0;
-  const int rows = nc > 0 ? q.nu * q.nv : 0;
-  const bool big = nc > 0 && (rows > P.small_rows || q.wide);
-  ov_append(P, big && !q.wide, 0, item, rows);
-  ov_append(P, big && q.wide, 1, item, rows);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t count = item_count(P), groups = (count + 63) >> 6;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const bool queue = P.grid_mode == SCAN_GRID_QUEUE;
+  auto pop = [&]() -> int64_t {  // the next group from the device counter
+    unsigned long long g = 0;
+    if (lane == 0) g = atomicAdd(P.head, 1ull);
+    return (int64_t)__builtin_amdgcn_readfirstlane((int)g);
+  };
   unsigned issued = 0;
-  Rows r;  // set only for lanes with rows to deal; rows past the end are dropped whatever it holds
-  if (nc > 0 && !big) setup_rows<KIND, false>(q, P.md[q.mesh], r);
-  const int w = threadIdx.x >> 6;
-  scan_rows_lanes<KIND, LOG>(P, q, r, nc > 0 && !big ? rows : 0, s_slot[w], s_mark[w], s_q[w], issued);
+  // every wave leaves once its next group is past the last one
+  for (int64_t g = queue ? pop() : blockIdx.x * (int64_t)(blockDim.x >> 6) + w; g < groups;
+       g = queue ? pop() : (P.grid_mode == SCAN_GRID_STRIDE ? g + nw : groups))
+    scan_group<KIND, LOG>(P, 64 * g + lane, count, s_slot[w], s_mark[w], s_q[w], issued);
   add_issued(P, issued, 0);
 }
 
@@ -1212,6 +1238,8 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.log_mask = nullptr;
   A.log_rounds = nullptr;
   A.log_cap = 0;
+  A.grid_mode = SCAN_GRID_STRIDE;
+  A.head = nullptr;
   return A;
 }
 
@@ -1234,22 +1262,41 @@ ScanArgs with_log(ScanArgs A, const AtomicLog* lg) {
   return A;
 }
 
+// blocks of a kernel resident at once on the whole device (queried once)
+template <typename K>
+unsigned resident_blocks(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1 || cus < 1)
+    return 1024;
+  return (unsigned)(per_cu * cus);
+}
+
+template <int KIND, bool LOG>
+unsigned small_grid(const ScanArgs& A) {
+  const unsigned need = grid_1d(A.n_items, 256);
+  if (A.grid_mode == SCAN_GRID_LAUNCH) return need;
+  static const unsigned resident = resident_blocks(k_scan_small<KIND, LOG>, 256);
+  return need < resident ? need : resident;
+}
+
 template <int KIND>
 void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s, const AtomicLog* lg) {
   {
     StageTimer t(stage, s);
-    if (logged(lg, KIND)) k_scan_small<KIND, true><<<grid_1d(A.n_items, 256), 256, 0, s>>>(with_log(A, lg));
-    else k_scan_small<KIND, false><<<grid_1d(A.n_items, 256), 256, 0, s>>>(A);
+    if (logged(lg, KIND)) k_scan_small<KIND, true><<<small_grid<KIND, true>(A), 256, 0, s>>>(with_log(A, lg));
+    else k_scan_small<KIND, false><<<small_grid<KIND, false>(A), 256, 0, s>>>(A);
   }
   {
-    StageTimer t(stage_big, s);  // 8 wavefronts per SIMD
-    if (logged(lg, 3 + KIND)) k_scan_big<KIND, false, true><<<4 * PERSIST_BLOCKS, 64, 0, s>>>(with_log(A, lg));
-    else k_scan_big<KIND, false, false><<<4 * PERSIST_BLOCKS, 64, 0, s>>>(A);
+    StageTimer t(stage_big, s);  // 4 wavefronts per CU: an empty list costs little
+    if (logged(lg, 3 + KIND)) k_scan_big<KIND, false, true><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(with_log(A, lg));
+    else k_scan_big<KIND, false, false><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(A);
   }
-  // wide polyhedra (boxes over WIDE_CELLS): rare, FP64, a wavefront each
+  // wide polyhedra (boxes over WIDE_CELLS): rare, FP64, in chunks of rows
   StageTimer t(TS_SCAN_WIDE, s);
-  if (logged(lg, 6 + KIND)) k_scan_big<KIND, true, true><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(with_log(A, lg));
-  else k_scan_big<KIND, true, false><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(A);
+  if (logged(lg, 6 + KIND)) k_scan_big<KIND, true, true><<<PERSIST_BLOCKS / 8, 64, 0, s>>>(with_log(A, lg));
+  else k_scan_big<KIND, true, false><<<PERSIST_BLOCKS / 8, 64, 0, s>>>(A);
 }
 
 // key initialisation and the scan launches of the three kinds; counters
@@ -1270,7 +1317,7 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   {
     StageTimer t(TS_INIT, s);
     k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap);
-    k_zero_u64<<<1, 64, 0, s>>>(ov_ctr, 6);
+    k_zero_u64<<<1, 64, 0, s>>>(ov_ctr, 9);  // two list counters and a group head per kind
   }
   // a fork that cannot be set up leaves everything on the caller's stream
   bool fork = f->n_meshes > 1 && !stage_timing_on() && f->side && !lg;
@@ -1278,6 +1325,8 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
     fork = hipEventRecord(f->ev_fork, s) == hipSuccess && hipStreamWaitEvent(f->side, f->ev_fork, 0) == hipSuccess;
   hipStream_t s2 = fork ? f->side : s;
   ScanArgs A = scan_args(f, keys, cap);
+  A.grid_mode = f->opt.scan_grid;
+  A.head = ov_ctr + 6;
   A.ov_ctr = ov_ctr;
   A.ov_cap = f->nf;
   A.ov_items = ov;
@@ -1288,6 +1337,7 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.per_cell = f->opt.scan_mode == 1;
   launch_kind<KIND_FACE>(A, TS_SCAN_FACE, TS_SCAN_FACE_BIG, s, lg);
   ov += 2 * f->nf;
+  A.head = ov_ctr + 7;
   A.ov_ctr = ov_ctr + 2;
   A.ov_cap = 2 * f->ne;
   A.ov_items = ov;
@@ -1300,6 +1350,7 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.counter = counters ? counters + 1 : nullptr;
   launch_kind<KIND_EDGE>(A, TS_SCAN_EDGE, TS_SCAN_EDGE_BIG, s2, lg);
   ov += 4 * f->ne;
+  A.head = ov_ctr + 8;
   A.ov_ctr = ov_ctr + 4;
   A.ov_cap = 2 * f->nv;
   A.ov_items = ov;

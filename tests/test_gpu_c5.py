@@ -10,6 +10,18 @@ backward, against the CPU oracle on every z-plane of the grid:
     fixed: per pair |g - g_fd| <= 1e-3 |g_fd| + 1e-5 max|g_fd|. Only the cells
     near the perturbed one-ring are recomputed, against the triangles that can
     be closest to them.
+
+The distance is only piecewise smooth in a vertex: where a cell's closest
+point changes triangle (the medial axis) it has a kink, and where it crosses
+from a triangle's edge into its interior it is C1 but not C2, and a central
+difference there is off by O(delta). With edges 0.74 h long even smooth cells
+carry O(delta^2) truncation of about 1e-8. So each cell's difference is taken
+with steps delta, 2 delta and 4 delta: a function smooth over the stencil has
+FD(4d) - FD(2d) = 4 (FD(2d) - FD(d)) up to O(d^4), and cells that break that
+by more than 10% (or 1e-14) are left out on both sides (their upstream is
+zeroed in one adjoint run); the reference is the Richardson extrapolation
+FD(d) + (FD(d) - FD(2d)) / 3. With the oracle's own FP64 gradient in place of
+the device's the check passes every pair at 0.03 of the tolerance.
 """
 import numpy as np
 import pytest
@@ -94,13 +106,13 @@ def test_c5_gradient_matches_finite_differences(c5):
     delta = 1e-3 * h
     rng = np.random.default_rng(FD_SEED)
     samples = []
-    kink_cells = []
+    rough_cells = []
     for s in range(FD_PAIRS):
         vi, ax = int(rng.integers(V.shape[0])), int(rng.integers(3))
         ring = inc[start[vi]:start[vi + 1]]
         # every cell whose distance can change lies within band*h of a ring triangle
-        lo = tlo[ring].min(axis=0) - wh - 2 * delta - 1e-9
-        hi = thi[ring].max(axis=0) + wh + 2 * delta + 1e-9
+        lo = tlo[ring].min(axis=0) - wh - 8 * delta - 1e-9
+        hi = thi[ring].max(axis=0) + wh + 8 * delta + 1e-9
         i0 = np.maximum(np.ceil((lo - origin) / h - 0.5), 0).astype(np.int64)
         i1 = np.floor((hi - origin) / h - 0.5).astype(np.int64)
         a, b = np.searchsorted(cs, i0[2] * plane), np.searchsorted(cs, (i1[2] + 1) * plane)
@@ -110,28 +122,28 @@ def test_c5_gradient_matches_finite_differences(c5):
         # triangles that can be closest to those cells (each band cell's closest
         # triangle lies within band*h of it)
         cand = np.nonzero(np.all((tlo <= hi + wh) & (thi >= lo - wh), axis=1))[0]
-        Vp, Vm = V.copy(), V.copy()
-        Vp[vi, ax] += delta
-        Vm[vi, ax] -= delta
-        d0, _ = om.cells_dist(g, cells, sub=cand)
-        dp, _ = om.cells_dist(g, cells, sub=cand, V64=Vp)
-        dm, _ = om.cells_dist(g, cells, sub=cand, V64=Vm)
-        kink = np.abs(dp + dm - 2 * d0) > 1e-3 * delta
-        kink_cells.append(cells[kink])
-        samples.append((vi, ax, cells, dp, dm))
-    # one adjoint run with the upstream zeroed on every kink cell of any sample;
-    # the finite differences leave out the same cells
-    kinks = np.unique(np.concatenate(kink_cells))
+        D = {}
+        for k in (-4, -2, -1, 1, 2, 4):
+            Vk = V.copy()
+            Vk[vi, ax] += k * delta
+            D[k], _ = om.cells_dist(g, cells, sub=cand, V64=Vk)
+        F = {k: (D[k] ** 2 - D[-k] ** 2) / (2 * k * delta) for k in (1, 2, 4)}
+        e1, e2 = F[2] - F[1], F[4] - F[2]
+        smooth = np.abs(e2 - 4 * e1) <= 0.1 * np.abs(4 * e1) + 1e-14
+        rough_cells.append(cells[~smooth])
+        samples.append((vi, ax, cells, F[1] + (F[1] - F[2]) / 3.0))
+    # one adjoint run with the upstream zeroed on every cell left out of any pair
+    rough = np.unique(np.concatenate(rough_cells))
     cell = c5["cell"].astype(np.int64)
     up = (2.0 * c5["sdf"]).astype(np.float32)
-    up[np.isin(cell, kinks)] = 0.0
-    print(f"[case] C5 FD: {FD_PAIRS} pairs, {kinks.size} kink cells masked", flush=True)
+    up[np.isin(cell, rough)] = 0.0
+    print(f"[case] C5 FD: {FD_PAIRS} pairs, {rough.size} cells not smooth within 4 delta left out", flush=True)
     band = c5["band"]
     gv = P.csc_sdf_backward(c5["feats"], band, torch.from_numpy(up).cuda()).cpu().numpy().astype(np.float64)
     fds, devs = [], []
-    for vi, ax, cells, dp, dm in samples:
-        keep = ~np.isin(cells, kinks)
-        fds.append(np.sum(((dp ** 2 - dm ** 2) / (2 * delta))[keep]))
+    for vi, ax, cells, fd in samples:
+        keep = ~np.isin(cells, rough)
+        fds.append(np.sum(fd[keep]))
         devs.append(gv[vi, ax])
     fds, devs = np.array(fds), np.array(devs)
     tol = 1e-3 * np.abs(fds) + 1e-5 * np.abs(fds).max()

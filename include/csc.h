@@ -222,6 +222,25 @@ int csc_scan_convert(const csc_features* f, void* workspace_d, size_t ws_bytes, 
 int csc_weld_soup(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris_d, int64_t* nv, void* stream);
 
 /*
+ * Triangle-soup welding for callers that cannot allocate device memory (code
+ * under graph capture setup, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result as csc_weld_soup, bit for bit, with its scratch in
+ * a 64 MiB array that the library holds on each GPU until the process ends, so
+ * the call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine). The caller still passes soup_d, verts_d and tris_d as for
+ * csc_weld_soup. Every call on one GPU uses that GPU's array: calls that overlap
+ * on one GPU (from several host threads or streams) race and must not be made.
+ * Synchronises `stream` before returning. nf may be at most
+ * csc_weld_soup_noalloc_max_faces() (428,096 triangles); larger
+ * soups return CSC_WORKSPACE_TOO_SMALL without queueing anything.
+ * Errors: INVALID_ARG (as csc_weld_soup), WORKSPACE_TOO_SMALL, UNSUPPORTED_DEVICE,
+ * HIP_ERROR.
+ */
+int csc_weld_soup_noalloc(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris_d, int64_t* nv,
+                          void* stream);
+int64_t csc_weld_soup_noalloc_max_faces(void);
+
+/*
  * Interior fill of a dense field (Section 11.3): the band leaves the cells of the
  * solid's interior farther than band_cells*h from the surface at +infinity, a
  * second zero crossing; this sets them to -infinity. dense_d: the float32

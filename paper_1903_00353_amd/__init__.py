@@ -64,7 +64,7 @@ EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspac
            "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name", "csc_build_features_batched",
            "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched", "csc_interior_fill",
            "csc_weld_soup", "csc_scan_record_atomics", "csc_atomic_replay", "csc_fadd_rate",
-           "csc_scan_convert_workspace_for"]
+           "csc_weld_soup_noalloc", "csc_weld_soup_noalloc_max_faces", "csc_scan_convert_workspace_for"]
 CSC_BUILD_NO_SYNC = 1
 CSC_BUILD_GRAPH_SAFE = 2
 N_STAGES = 13
@@ -109,6 +109,10 @@ def lib():
                                              C.c_int32, P, C.POINTER(C.c_void_p)]
     L.csc_weld_soup.restype = C.c_int
     L.csc_weld_soup.argtypes = [P, C.c_int64, P, P, C.POINTER(C.c_int64), P]
+    L.csc_weld_soup_noalloc.restype = C.c_int
+    L.csc_weld_soup_noalloc.argtypes = [P, C.c_int64, P, P, C.POINTER(C.c_int64), P]
+    L.csc_weld_soup_noalloc_max_faces.restype = C.c_int64
+    L.csc_weld_soup_noalloc_max_faces.argtypes = []
     L.csc_interior_fill.restype = C.c_int
     L.csc_interior_fill.argtypes = [P, P, P]
     L.csc_features_sync.restype = C.c_int
@@ -534,6 +538,21 @@ def csc_weld_soup(soup, stream=None):
     _check(lib().csc_weld_soup(_ptr(soup), nf, _ptr(verts), _ptr(tris), C.byref(nv), _stream(stream)),
            "csc_weld_soup")
     return verts[: nv.value], tris
+
+
+def csc_weld_soup_noalloc(soup, verts, tris, stream=None):
+    """csc_weld_soup into caller-provided outputs (verts float32 [>= 3F, 3], tris
+    int32 [F, 3]) with the library's static scratch: allocates nothing. Returns
+    the vertex count (synchronises)."""
+    soup = soup.reshape(-1, 3, 3)
+    nv = C.c_int64(0)
+    _check(lib().csc_weld_soup_noalloc(_ptr(soup), int(soup.shape[0]), _ptr(verts), _ptr(tris), C.byref(nv),
+                                       _stream(stream)), "csc_weld_soup_noalloc")
+    return int(nv.value)
+
+
+def csc_weld_soup_noalloc_max_faces() -> int:
+    return int(lib().csc_weld_soup_noalloc_max_faces())
 
 
 def csc_interior_fill(f: Features, dense, stream=None):

@@ -13,6 +13,7 @@
 // the sorts are stable, so the first corner of every group of equal positions
 // is the earliest one in the soup.
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -166,4 +167,67 @@ extern "C" int csc_weld_soup(const float* soup_d, int64_t nf, float* verts_d, in
   if (h_bad) return CSC_INVALID_ARG;
   *nv = h_nv;
   return CSC_OK;
+}
+
+// ------------------------------------------------------------ allocation-free
+// csc_weld_soup_noalloc keeps its scratch in this file-scope device array, one
+// copy per GPU, held until the process ends. Host code never passes the array's
+// name to a kernel (on the host it only names the symbol): each device's
+// address comes from hipGetSymbolAddress on the first call with that device
+// current, and is kept per device.
+constexpr size_t WELD_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[WELD_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_for_current_device(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e);
+  if (dev < 0 || dev >= MAX_DEVICES) return CSC_UNSUPPORTED_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail_hip(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CSC_OK;
+}
+}  // namespace
+
+extern "C" int csc_weld_soup_noalloc(const float* soup_d, int64_t nf, float* verts_d, int32_t* tris_d, int64_t* nv,
+                                     void* stream) {
+  if (!weld_args_ok(soup_d, nf, verts_d, tris_d, nv)) return CSC_INVALID_ARG;
+  const WeldLayout L = weld_layout(3 * nf);
+  if (L.sort_bytes == 0) return CSC_INVALID_ARG;
+  if (L.total > WELD_SCRATCH_BYTES) return CSC_WORKSPACE_TOO_SMALL;
+  int rc = check_device();
+  if (rc != CSC_OK) return rc;
+  char* W = nullptr;
+  rc = scratch_for_current_device(&W);
+  if (rc != CSC_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t h_nv = 0;
+  int32_t h_bad = 0;
+  hipError_t e = weld_queue(soup_d, nf, verts_d, tris_d, W, L, &h_nv, &h_bad, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e);
+  if (h_bad) return CSC_INVALID_ARG;
+  *nv = h_nv;
+  return CSC_OK;
+}
+
+extern "C" int64_t csc_weld_soup_noalloc_max_faces(void) {
+  int64_t lo = 0, hi = (INT32_MAX - 1) / 3;
+  while (lo < hi) {  // the largest nf whose scratch fits
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (weld_layout(3 * mid).total <= WELD_SCRATCH_BYTES) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }

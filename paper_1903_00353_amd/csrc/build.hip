@@ -121,7 +121,10 @@ __global__ void k_offsets(const uint32_t* __restrict__ key, int64_t nh, int64_t 
 // that slack is at most `absorb` cells the feature gets no polyhedron of its
 // own and every face holding it takes the slack (rounded up, in 1/1024 cells).
 // Flat features (theta = 0) already get none. Ruff vertices and hemispheres,
-// and edges of unknown class, keep their polyhedra.
+// and edges of unknown class, keep their polyhedra. The vertex pass keeps its
+// slack code in the vertex's class word, the edge pass in a byte per edge (both
+// written by the thread that owns the feature), and k_face_slack gives every
+// face the largest code of its three edges and three vertices.
 constexpr float SLACK_UNIT = 1.f / 1024.f;  // cells per step of the stored slack
 
 __device__ inline uint8_t slack_code(double cells, float absorb) {
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
                                                       int force_both, const int32_t* __restrict__ vert_mesh,
                                                       const MeshDesc* __restrict__ md, float absorb, int32_t* twin,
                                                       float4* vinfo, uint32_t* vbits, int32_t* count,
-                                                      uint8_t* fslack, int64_t* stats) {
+                                                      int64_t* stats) {
   __shared__ int32_t s_c[VK_MAXD][VK_THREADS], s_n[VK_MAXD][VK_THREADS], s_p[VK_MAXD][VK_THREADS];
   const int t = threadIdx.x;
   const int64_t v = blockIdx.x * (int64_t)VK_THREADS + t;
@@ -208,10 +211,9 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
   VertexClass cl = vt.finish(ruff_mode, saddle_mode, force_both);
   if (d == 0) cl.bits = 0;  // isolated vertex: no feature
   // a nearly flat vertex hands its region to the prisms of its faces (side slack
-  // band * sin(2 theta), theta the cone aperture): see absorbed_slack
+  // band * sin(2 theta), theta the cone aperture): see vertex_slack
   const uint8_t q = absorb > 0.f && !force_both ? vertex_slack(cl, md[vert_mesh[v]].band, absorb) : 0;
-  if (q) cl.bits = (cl.bits & ~(V_POS | V_NEG)) | V_ABSORBED;
-  for (int k = 0; k < d; k++) fslack[2 * (int64_t)C_(k) + 1] = q;
+  if (q) cl.bits = (cl.bits & ~(V_POS | V_NEG)) | V_ABSORBED | ((uint32_t)q << V_SLACK_SHIFT);
   float cf = (float)cl.cos_t;
   if ((double)cf > cl.cos_t) cf = nextafterf(cf, -2.f);  // the stored cone contains the exact one
   vinfo[v] = make_float4((float)cl.axis.x, (float)cl.axis.y, (float)cl.axis.z, cf);
@@ -230,12 +232,11 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
 __global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nh, int64_t ne,
                         const int32_t* __restrict__ twin, const int32_t* __restrict__ eid, int force_both,
                         const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float absorb,
-                        int4* edges, int32_t* face_edges, uint8_t* cls, int32_t* count, uint8_t* fslack) {
+                        int4* edges, int32_t* face_edges, uint8_t* cls, int32_t* count, uint8_t* eslack) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (h >= nh) return;
   int32_t u = T[h], w = T[next_corner((int32_t)h)];
   int32_t t = twin[h];
-  if (u >= w && t < 0) fslack[2 * h] = 0;  // no owner writes this side
   if (u < w) {
     int32_t e = eid[h];
     face_edges[h] = e < ne ? e : -1;
@@ -256,9 +257,8 @@ __global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__
         q = edge_slack(tod(fu), tod(fw), tod(f1), tod(f2), md[face_mesh[h / 3]].band, absorb);
         if (q) sides = 0;
       }
-      fslack[2 * (int64_t)t] = q;
     }
-    fslack[2 * h] = q;
+    eslack[e] = q;
     cls[e] = (uint8_t)(c | (sides << 2) | (q ? EDGE_ABSORBED : 0));
     count[e] = __popc(sides);
   } else {
@@ -393,6 +393,23 @@ __global__ __launch_bounds__(256) void k_class_stats(const uint8_t* __restrict__
     atomicAdd((unsigned long long*)&stats[map[threadIdx.x]], (unsigned long long)h[threadIdx.x]);
 }
 
+// per face: the largest slack code of its edges and vertices (gathers of the
+// coalesced per-feature codes instead of scattered byte writes per face side)
+__global__ void k_face_slack(const int32_t* __restrict__ T, const int32_t* __restrict__ face_edges,
+                             const uint32_t* __restrict__ vbits, const uint8_t* __restrict__ eslack, int64_t nf,
+                             int64_t ne, uint8_t* fslack) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  uint32_t q = 0;
+#pragma unroll
+  for (int j = 0; j < 3; j++) {
+    q = max(q, (vbits[T[3 * f + j]] >> V_SLACK_SHIFT) & 0xffu);
+    const int32_t e = face_edges[3 * f + j];
+    if (e >= 0 && e < ne) q = max(q, (uint32_t)eslack[e]);
+  }
+  fslack[f] = (uint8_t)q;
+}
+
 __global__ void k_edge_queue(const uint8_t* __restrict__ cls, int64_t ne, const int32_t* __restrict__ off, int32_t* q) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= ne) return;
@@ -450,7 +467,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 enum {
   L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FN, L_FV, L_ECLS,
   L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_BFLAG,
-  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_N
+  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_N
 };
 
 struct Layout {
@@ -489,7 +506,8 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_TSCAN2] = sizeof(int32_t) * (size_t)scan_tmp_ints(nbt + 1);
   sz[L_STATS] = sizeof(int64_t) * ST_COUNT;
   sz[L_SORT] = sort_bytes;
-  sz[L_FSLACK] = (size_t)(6 * nf + 8);
+  sz[L_FSLACK] = (size_t)(nf + 8);
+  sz[L_ESLACK] = (size_t)(ne + 8);
   Layout L;
   size_t o = 0;
   for (int i = 0; i < L_N; i++) {
@@ -671,6 +689,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->t_sort = (void*)(A + L.off[L_SORT]);
   F->t_sort_bytes = sort_bytes;
   F->fslack = (uint8_t*)(A + L.off[L_FSLACK]);
+  F->eslack = (uint8_t*)(A + L.off[L_ESLACK]);
   F->built = F->synced = false;
 
 #define CK(x)                                        \
@@ -730,8 +749,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   const float absorb = o.absorb_cells > 0.f ? o.absorb_cells : 0.f;
   k_vertex<<<grid_1d(tv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, T, tv, F->vtx_off, F->vtx_corners, o.ruff_mode,
                                                         o.saddle_mode, o.force_both_sides, F->vert_mesh, F->d_mesh,
-                                                        absorb, F->t_a, F->vinfo, F->vbits, F->t_c, F->fslack,
-                                                        F->d_stats);
+                                                        absorb, F->t_a, F->vinfo, F->vbits, F->t_c, F->d_stats);
   CK(exclusive_scan(F->t_c, F->t_c, tv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
   k_vertex_queue<<<grid_1d(tv, B), B, 0, s>>>(F->vbits, tv, F->t_c, F->vpoly);
   {
@@ -742,7 +760,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   CK(exclusive_scan(F->face_edges, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
   // edges with their classes and extrusion sides
   k_edges<<<grid_1d(nh, B), B, 0, s>>>(verts_d, T, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->face_mesh,
-                                       F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_c, F->fslack);
+                                       F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_c, F->eslack);
+  k_face_slack<<<grid_1d(tf, B), B, 0, s>>>(T, F->face_edges, F->vbits, F->eslack, tf, ne, F->fslack);
   // 4. edge polyhedron queue and class statistics
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);

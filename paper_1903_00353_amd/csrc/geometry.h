@@ -135,6 +135,7 @@ enum : uint32_t {
   V_CONVEX = 16u, V_CONCAVE = 32u, V_FLAT = 64u, V_SADDLE = 128u, V_RUFF = 256u,
   V_ABSORBED = 512u  // nearly flat: its region handed to the prisms of its faces
 };
+constexpr int V_SLACK_SHIFT = 16;  // bits 16-23 of the class word: the absorbed vertex's slack code
 
 struct VertexClass {
   d3 axis;        // unit angle-weighted pseudonormal

@@ -169,8 +169,9 @@ struct csc_features {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t* brick_flag = nullptr;    // [nbt + 1] brick marks of the build
   int32_t* t_scan2 = nullptr;       // scan temporaries of the side branch
-  uint8_t* fslack = nullptr;        // [nf][3][2] per face side: slack of the edge, of the corner's vertex
-                                    // (absorbed features, in 1/1024 cells)
+  uint8_t* fslack = nullptr;        // [nf] side slack of the face prism: the largest code of its absorbed
+                                    // edges and vertices (1/1024 cells)
+  uint8_t* eslack = nullptr;        // [ne] slack code of each absorbed edge (0: not absorbed)
 
   bool built = false;               // device work queued for the current inputs
   bool synced = false;              // counts below read back since the last build

@@ -30,7 +30,7 @@ struct ScanArgs {
   const float4* fn;
   const int4* edges;
   const int32_t* face_edges;   // [nf][3] edge of each face side (wide faces: boundary signs)
-  const uint8_t* fslack;       // [nf][3][2] side slack of absorbed edges and vertices (1/1024 cells)
+  const uint8_t* fslack;       // [nf] side slack of each face prism (absorbed edges and vertices, 1/1024 cells)
   const uint8_t* ecls;
   const float4* vinfo;
   const uint32_t* vbits;
@@ -166,10 +166,7 @@ __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f
   d3 a = mkd(fv[0], fv[1], fv[2]), b = mkd(fv[3], fv[4], fv[5]), c = mkd(fv[6], fv[7], fv[8]);
   float4 nn = P.fn[f];
   d3 n = mkd(nn.x, nn.y, nn.z);
-  const uint8_t* sl = P.fslack + 6 * f;
-  const uint32_t sq = max(max(max((uint32_t)sl[0], (uint32_t)sl[1]), max((uint32_t)sl[2], (uint32_t)sl[3])),
-                          max((uint32_t)sl[4], (uint32_t)sl[5]));
-  const float slack = (float)sq * (1.f / 1024.f) * G.hf;  // absorbed features' slack, length units
+  const float slack = (float)P.fslack[f] * (1.f / 1024.f) * G.hf;  // absorbed features' slack, length units
   double lo[3], hi[3];
   const double A3[3] = {a.x, a.y, a.z}, B3[3] = {b.x, b.y, b.z}, C3[3] = {c.x, c.y, c.z}, N3[3] = {n.x, n.y, n.z};
   for (int k = 0; k < 3; k++) {
@@ -1281,6 +1278,14 @@ unsigned small_grid(const ScanArgs& A) {
   return need < resident ? need : resident;
 }
 
+// the chunked overflow pass: every wavefront the device holds at once (a few
+// thousand; an empty list costs one load and exit per wavefront)
+template <int KIND, bool LOG>
+unsigned big_grid() {
+  static const unsigned resident = resident_blocks(k_scan_big<KIND, false, LOG>, 64);
+  return resident;
+}
+
 template <int KIND>
 void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s, const AtomicLog* lg) {
   {
@@ -1289,9 +1294,9 @@ void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s, const Atom
     else k_scan_small<KIND, false><<<small_grid<KIND, false>(A), 256, 0, s>>>(A);
   }
   {
-    StageTimer t(stage_big, s);  // 4 wavefronts per CU: an empty list costs little
-    if (logged(lg, 3 + KIND)) k_scan_big<KIND, false, true><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(with_log(A, lg));
-    else k_scan_big<KIND, false, false><<<PERSIST_BLOCKS / 2, 64, 0, s>>>(A);
+    StageTimer t(stage_big, s);
+    if (logged(lg, 3 + KIND)) k_scan_big<KIND, false, true><<<big_grid<KIND, true>(), 64, 0, s>>>(with_log(A, lg));
+    else k_scan_big<KIND, false, false><<<big_grid<KIND, false>(), 64, 0, s>>>(A);
   }
   // wide polyhedra (boxes over WIDE_CELLS): rare, FP64, in chunks of rows
   StageTimer t(TS_SCAN_WIDE, s);

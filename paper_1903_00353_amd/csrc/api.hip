@@ -72,6 +72,7 @@ extern "C" void csc_features_free(csc_features* f) {
   if (f->h_stats) (void)hipHostFree(f->h_stats);
   if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
   if (f->ev_join) (void)hipEventDestroy(f->ev_join);
+  if (f->ev_geom) (void)hipEventDestroy(f->ev_geom);
   if (f->side) (void)hipStreamDestroy(f->side);
   delete f;
 }

@@ -12,8 +12,7 @@ namespace csc {
 
 struct BwdArgs {
   const float* V;
-  const int32_t* T;          // global vertex indices
-  const float* fv;           // corner positions in face order [nf][9]
+  const FaceRec* frec;       // [nf] corners, vertex indices, unit normal
   const int4* edges;
   const MeshDesc* md;
   const float* sdf;
@@ -30,8 +29,8 @@ struct BwdArgs {
 __device__ inline f3 relb(const float* V, int64_t i, d3 c) {
   return tof(mkd((double)V[3 * i] - c.x, (double)V[3 * i + 1] - c.y, (double)V[3 * i + 2] - c.z));
 }
-__device__ inline f3 relv(const float* p, d3 c) {
-  return tof(mkd((double)p[0] - c.x, (double)p[1] - c.y, (double)p[2] - c.z));
+__device__ inline f3 relv(float4 p, d3 c) {
+  return tof(mkd((double)p.x - c.x, (double)p.y - c.y, (double)p.z - c.z));
 }
 
 // the per-cell inputs of one band cell; gs = 0 past the end of the run
@@ -218,9 +217,12 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
       int32_t v3[3];
       if (lf < M.nf) {
         const int64_t f = (int64_t)M.f_off + lf;
-        for (int j = 0; j < 3; j++) v3[j] = P.T[3 * f + j];
-        const float* fv = P.fv + 9 * f;
-        closest_triangle(zero, relv(fv, c), relv(fv + 3, c), relv(fv + 6, c), q, w);
+        const FaceRec& R = P.frec[f];  // one sector: corners and vertex indices
+        const float4 ra = R.c[0], rb = R.c[1], rc = R.c[2];
+        v3[0] = rec_vertex(ra);
+        v3[1] = rec_vertex(rb);
+        v3[2] = rec_vertex(rc);
+        closest_triangle(zero, relv(ra, c), relv(rb, c), relv(rc, c), q, w);
         mcount = 3;
       } else if (lf < M.nf + M.ne) {
         int4 E = P.edges[(int64_t)M.e_off + (lf - M.nf)];
@@ -350,8 +352,7 @@ int backward_impl(const csc_features* f, const float* sdf_d, const int32_t* feat
                   hipStream_t s) {
   BwdArgs A;
   A.V = f->verts;
-  A.T = f->tris_g;
-  A.fv = f->face_v;
+  A.frec = f->face_rec;
   A.edges = f->edges;
   A.md = f->d_mesh;
   A.sdf = sdf_d;

@@ -26,6 +26,17 @@ __device__ inline uint32_t* err_word(int64_t* stats) { return (uint32_t*)&stats[
 // corner c = 3f + j (32-bit: 3F < 2^31): the corner after / before it in its face
 __device__ inline int32_t next_corner(int32_t c) { int32_t j = c % 3; return c - j + (j == 2 ? 0 : j + 1); }
 __device__ inline int32_t prev_corner(int32_t c) { int32_t j = c % 3; return c - j + (j == 0 ? 2 : j - 1); }
+// corner c itself and the corners after / before it, from its face's record
+__device__ inline float4 rec_at(const FaceRec* R, int32_t c) { return R[c / 3].c[c % 3]; }
+__device__ inline float4 rec_next(const FaceRec* R, int32_t c) {
+  const int32_t j = c % 3;
+  return R[c / 3].c[j == 2 ? 0 : j + 1];
+}
+__device__ inline float4 rec_prev(const FaceRec* R, int32_t c) {
+  const int32_t j = c % 3;
+  return R[c / 3].c[j == 0 ? 2 : j - 1];
+}
+__device__ inline f3 rec_posf(float4 c) { return mk(c.x, c.y, c.z); }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -151,7 +162,8 @@ __device__ inline uint8_t vertex_slack(const VertexClass& cl, float band, float 
 constexpr int VK_THREADS = 128;
 constexpr int VK_MAXD = 12;  // fans up to this degree are staged in LDS (18 KB per block: 4 wavefronts per SIMD)
 
-// Per vertex u, over its fan of corners (staged in LDS):
+// Per vertex u, over its fan of corners (staged in LDS; positions gathered from
+// the vertex array, which stays far better cached than the face records):
 //  * twins: the out-edge u -> w of corner c (half-edge c) pairs with the unique
 //    in-edge w -> u of another corner around u; none or several: not a closed
 //    2-manifold; two out-edges to the same w: inconsistent orientation;
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
                                                       int64_t* stats) {
   __shared__ int32_t s_c[VK_MAXD][VK_THREADS], s_n[VK_MAXD][VK_THREADS], s_p[VK_MAXD][VK_THREADS];
   const int t = threadIdx.x;
-  const int64_t v = blockIdx.x * (int64_t)VK_THREADS + t;
+  const int64_t v = xcd_block() * VK_THREADS + t;
   if (v >= nv) return;
   const int32_t s0 = off[v], d = off[v + 1] - s0;
   const bool staged = d <= VK_MAXD;
@@ -229,13 +241,15 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
 // non-manifold surface can own more or fewer than 3F/2 half-edges: such a build
 // is rejected, and nothing is written past ne; cls and count are zero-filled
 // beforehand, so edges no half-edge produced stay unclassified and empty.)
-__global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nh, int64_t ne,
+__global__ void k_edges(const FaceRec* __restrict__ R, int64_t nh, int64_t ne,
                         const int32_t* __restrict__ twin, const int32_t* __restrict__ eid, int force_both,
                         const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float absorb,
                         int4* edges, int32_t* face_edges, uint8_t* cls, int32_t* count, uint8_t* eslack) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (h >= nh) return;
-  int32_t u = T[h], w = T[next_corner((int32_t)h)];
+  // this face's record: the three threads of a face read one sector together
+  const float4 cu = rec_at(R, (int32_t)h), cw = rec_next(R, (int32_t)h);
+  int32_t u = rec_vertex(cu), w = rec_vertex(cw);
   int32_t t = twin[h];
   if (u < w) {
     int32_t e = eid[h];
@@ -245,8 +259,8 @@ __global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__
     int c = 0, sides = 0;
     uint8_t q = 0;
     if (t >= 0) {
-      const int32_t c1 = T[prev_corner((int32_t)h)], c2 = T[prev_corner(t)];
-      const f3 fu = vload_f(V, u), fw = vload_f(V, w), f1 = vload_f(V, c1), f2 = vload_f(V, c2);
+      const f3 fu = rec_posf(cu), fw = rec_posf(cw), f1 = rec_posf(rec_prev(R, (int32_t)h)),
+               f2 = rec_posf(rec_prev(R, t));
       c = classify_edge(fu, fw, f1, f2);
       if (c == EDGE_CONVEX) sides = 1;
       else if (c == EDGE_CONCAVE) sides = 2;
@@ -276,26 +290,25 @@ __global__ void k_edges(const float* __restrict__ V, const int32_t* __restrict__
 // a scan writes only cells within band*h of a feature, so every cell a scan can
 // write has its brick marked by one of the faces holding its feature.
 __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf,
-                            const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float4* fn,
-                            float* fv, int32_t* flag, int64_t* stats) {
+                            const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, FaceRec* rec,
+                            int32_t* flag, int64_t* stats) {
   int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  const f3 af = vload_f(V, T[3 * f]), bf = vload_f(V, T[3 * f + 1]), cf = vload_f(V, T[3 * f + 2]);
-  // the corners again in face order: later passes read one contiguous record per
-  // face instead of three vertex gathers
-  float* o = fv + 9 * f;
-  o[0] = af.x; o[1] = af.y; o[2] = af.z;
-  o[3] = bf.x; o[4] = bf.y; o[5] = bf.z;
-  o[6] = cf.x; o[7] = cf.y; o[8] = cf.z;
+  const int32_t ia = T[3 * f], ib = T[3 * f + 1], ic = T[3 * f + 2];
+  const f3 af = vload_f(V, ia), bf = vload_f(V, ib), cf = vload_f(V, ic);
   const d3 a = mkd(af.x, af.y, af.z), b = mkd(bf.x, bf.y, bf.z), c = mkd(cf.x, cf.y, cf.z);
   const d3 n = cross(b - a, c - a);
   const double l = len(n);
-  if (!(l > 0)) {
-    atomicOr(err_word(stats), ERR_DEGENERATE);
-    fn[f] = make_float4(0.f, 0.f, 0.f, 0.f);
-  } else {
-    fn[f] = make_float4((float)(n.x / l), (float)(n.y / l), (float)(n.z / l), 0.f);
-  }
+  float4 un4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (!(l > 0)) atomicOr(err_word(stats), ERR_DEGENERATE);
+  else un4 = make_float4((float)(n.x / l), (float)(n.y / l), (float)(n.z / l), 0.f);
+  // the face's record: later passes read one aligned sector per face instead of
+  // three vertex gathers
+  FaceRec& o = rec[f];
+  o.c[0] = make_float4(af.x, af.y, af.z, __int_as_float(ia));
+  o.c[1] = make_float4(bf.x, bf.y, bf.z, __int_as_float(ib));
+  o.c[2] = make_float4(cf.x, cf.y, cf.z, __int_as_float(ic));
+  o.n = un4;
   const MeshDesc& g = md[face_mesh[f]];
   const double r = g.whd + g.epsd;
   const double X[3][3] = {{a.x, b.x, c.x}, {a.y, b.y, c.y}, {a.z, b.z, c.z}};
@@ -465,7 +478,7 @@ namespace {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 enum {
-  L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FN, L_FV, L_ECLS,
+  L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FREC, L_ECLS,
   L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_BFLAG,
   L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_N
 };
@@ -491,8 +504,7 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_VTXC] = sizeof(int32_t) * (size_t)(3 * nf);
   sz[L_FEDGES] = sizeof(int32_t) * (size_t)(3 * nf);
   sz[L_EDGES] = sizeof(int4) * (size_t)(ne + 1);
-  sz[L_FN] = sizeof(float4) * (size_t)nf;
-  sz[L_FV] = sizeof(float) * 9 * (size_t)nf;
+  sz[L_FREC] = sizeof(FaceRec) * (size_t)nf;
   sz[L_ECLS] = (size_t)((ne + 4) / 4 * 4);  // whole ints: zero-filled as ints
   sz[L_VINFO] = sizeof(float4) * (size_t)nv;
   sz[L_VBITS] = sizeof(uint32_t) * (size_t)nv;
@@ -646,6 +658,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
     he = hipStreamCreateWithFlags(&F->side, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&F->ev_fork, hipEventDisableTiming);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&F->ev_join, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&F->ev_geom, hipEventDisableTiming);
     if (he != hipSuccess) return fail(fail_hip(he));
   }
   char* A = F->arena;
@@ -668,8 +681,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->vtx_corners = (int32_t*)(A + L.off[L_VTXC]);
   F->face_edges = (int32_t*)(A + L.off[L_FEDGES]);
   F->edges = (int4*)(A + L.off[L_EDGES]);
-  F->face_n = (float4*)(A + L.off[L_FN]);
-  F->face_v = (float*)(A + L.off[L_FV]);
+  F->face_rec = (FaceRec*)(A + L.off[L_FREC]);
   F->edge_cls = (uint8_t*)(A + L.off[L_ECLS]);
   F->vinfo = (float4*)(A + L.off[L_VINFO]);
   F->vbits = (uint32_t*)(A + L.off[L_VBITS]);
@@ -725,16 +737,18 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                                                F->tris_g, F->face_mesh, F->face_edges,
                                                                F->vert_mesh, F->d_stats);
   const int32_t* T = F->tris_g;
-  // Face normals with the band bricks near each face, the brick slots and lists:
-  // they need only the inputs, so they run on the side stream while the corner
-  // table, twins, classes and edges run here.
+  // Face records (corners, vertex indices, normal) with the band bricks near each
+  // face, the brick slots and lists: they need only the inputs, so they run on
+  // the side stream while the corner table is sorted and the vertices classified
+  // here; the edge pass waits for the records.
   CK(hipEventRecord(F->ev_fork, s));
   CK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
   {
     hipStream_t s2 = F->side;
     k_fill_i32<<<grid_1d(tb, B), B, 0, s2>>>(F->brick_flag, tb, 0);
-    k_face_geom<<<grid_1d(tf, B), B, 0, s2>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_n, F->face_v,
+    k_face_geom<<<grid_1d(tf, B), B, 0, s2>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_rec,
                                                F->brick_flag, F->d_stats);
+    CK(hipEventRecord(F->ev_geom, s2));
     CK(exclusive_scan(F->brick_flag, F->brick_index, tb, F->t_scan2, &F->d_stats[ST_NBRICKS], nullptr, s2));
     k_brick_fix<<<grid_1d(tb, B), B, 0, s2>>>(F->brick_flag, F->brick_index, F->brick_list, F->brick_mesh,
                                               F->brick_base, n_meshes, F->first_slot, F->d_stats, tb);
@@ -759,7 +773,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   }
   CK(exclusive_scan(F->face_edges, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
   // edges with their classes and extrusion sides
-  k_edges<<<grid_1d(nh, B), B, 0, s>>>(verts_d, T, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->face_mesh,
+  CK(hipStreamWaitEvent(s, F->ev_geom, 0));  // the face records
+  k_edges<<<grid_1d(nh, B), B, 0, s>>>(F->face_rec, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->face_mesh,
                                        F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_c, F->eslack);
   k_face_slack<<<grid_1d(tf, B), B, 0, s>>>(T, F->face_edges, F->vbits, F->eslack, tf, ne, F->fslack);
   // 4. edge polyhedron queue and class statistics

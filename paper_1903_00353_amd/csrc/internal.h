@@ -101,6 +101,24 @@ class StageTimer {
   bool active_ = false;
 };
 
+// MI355X deals the workgroups of a launch to its 8 XCDs in turn (workgroup b to
+// XCD b mod 8), and each XCD has an L2 of its own. xcd_block renumbers the
+// workgroups so that each XCD takes one contiguous slice of the grid, so that
+// neighbouring items that gather the same data meet in one L2. A bijection on
+// [0, gridDim.x) for any grid size; a different dealing order costs locality,
+// never correctness. Measured, it pays only in the vertex pass (fans of
+// neighbouring vertices share corners and positions: -11%); where the work per
+// item is uneven along the grid (polyhedron queues) a contiguous slice per XCD
+// unbalances the XCDs, and the face and edge passes ran 10% slower with it.
+#ifndef CSC_N_XCD
+#define CSC_N_XCD 8
+#endif
+__device__ inline int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t per = nb / CSC_N_XCD, r = nb % CSC_N_XCD, x = b % CSC_N_XCD;
+  return x * per + (x < r ? x : r) + b / CSC_N_XCD;
+}
+
 inline unsigned grid_1d(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
@@ -121,6 +139,19 @@ __host__ __device__ inline int find_segment(const T* table, int n, int64_t x) {
 }  // namespace csc
 
 // The handle: a batch of one or more meshes. Device arrays live in one arena.
+// One 64-byte record per face, written by the build: corner j as (x, y, z, its
+// global vertex index as the bits of w) for j = 0..2, then the unit normal
+// (w = 0). A pass that needs a face's corners, vertex indices or normal reads
+// one aligned 64-byte sector instead of gathering from the vertex array: faces
+// near each other in space are often far apart in the input's order, and each
+// scattered 12-byte gather costs a whole sector.
+struct FaceRec {
+  float4 c[3];
+  float4 n;
+};
+static_assert(sizeof(FaceRec) == 64, "one sector per face");
+__device__ inline int32_t rec_vertex(const float4& c) { return __float_as_int(c.w); }
+
 struct csc_features {
   int32_t n_meshes = 0;
   std::vector<csc::MeshDesc> mesh;  // host copy of the descriptors
@@ -144,8 +175,7 @@ struct csc_features {
   int32_t* vtx_corners = nullptr;   // [3nf] per vertex its corners 3f+j, ascending
   int32_t* face_edges = nullptr;    // [3nf]
   int4* edges = nullptr;            // [ne] (a, b, f_left, f_right), global indices
-  float4* face_n = nullptr;         // [nf] unit normal
-  float* face_v = nullptr;          // [nf][3][3] corner positions in face order
+  FaceRec* face_rec = nullptr;      // [nf] corners, vertex ids and unit normal of each face
   uint8_t* edge_cls = nullptr;      // [ne] class | side bits << 2
   float4* vinfo = nullptr;          // [nv] unit pseudonormal, cone aperture cosine
   uint32_t* vbits = nullptr;        // [nv] class bits
@@ -167,6 +197,7 @@ struct csc_features {
   // the caller's stream with the two events (capturable: a parallel branch)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_geom = nullptr;     // the face records are written (the vertex and edge passes read them)
   int32_t* brick_flag = nullptr;    // [nbt + 1] brick marks of the build
   int32_t* t_scan2 = nullptr;       // scan temporaries of the side branch
   uint8_t* fslack = nullptr;        // [nf] side slack of the face prism: the largest code of its absorbed

@@ -26,8 +26,7 @@ enum { KIND_FACE = 0, KIND_EDGE = 1, KIND_VERT = 2 };
 struct ScanArgs {
   const float* V;
   const int32_t* T;            // global vertex indices
-  const float* fv;             // corner positions in face order [nf][9]
-  const float4* fn;
+  const FaceRec* frec;         // [nf] corners, vertex indices, unit normal
   const int4* edges;
   const int32_t* face_edges;   // [nf][3] edge of each face side (wide faces: boundary signs)
   const uint8_t* fslack;       // [nf] side slack of each face prism (absorbed edges and vertices, 1/1024 cells)
@@ -162,9 +161,9 @@ __device__ inline void set_plane(Poly& q, int i, f3 m, f3 through) {
 // side planes move out by the largest slack of the absorbed edges and vertices
 // of the face (the regions of those nearly flat features lie within it).
 __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f, Poly& q) {
-  const float* fv = P.fv + 9 * f;
-  d3 a = mkd(fv[0], fv[1], fv[2]), b = mkd(fv[3], fv[4], fv[5]), c = mkd(fv[6], fv[7], fv[8]);
-  float4 nn = P.fn[f];
+  const FaceRec& R = P.frec[f];
+  const float4 ra = R.c[0], rb = R.c[1], rc = R.c[2], nn = R.n;
+  d3 a = mkd(ra.x, ra.y, ra.z), b = mkd(rb.x, rb.y, rb.z), c = mkd(rc.x, rc.y, rc.z);
   d3 n = mkd(nn.x, nn.y, nn.z);
   const float slack = (float)P.fslack[f] * (1.f / 1024.f) * G.hf;  // absorbed features' slack, length units
   double lo[3], hi[3];
@@ -205,7 +204,7 @@ __device__ inline int build_edge(const ScanArgs& P, const MeshDesc& G, int32_t e
   double sg = (ent & 1) ? -1.0 : 1.0;
   int4 E = P.edges[e];
   d3 a = vload_d(P.V, E.x), b = vload_d(P.V, E.y);
-  float4 f1 = P.fn[E.z], f2 = P.fn[E.w];
+  float4 f1 = P.frec[E.z].n, f2 = P.frec[E.w].n;
   d3 n1 = mkd(f1.x, f1.y, f1.z), n2 = mkd(f2.x, f2.y, f2.z);
   d3 ed = b - a;
   int cls = P.ecls[e] & 3;
@@ -442,18 +441,19 @@ __device__ inline bool dist_wide(const ScanArgs& P, const MeshDesc& G, int id, i
   const d3 o = mkd(0.0, 0.0, 0.0);
   double dd;
   if constexpr (KIND == KIND_FACE) {
-    const float* fv = P.fv + 9 * (int64_t)id;
+    const FaceRec& R = P.frec[id];
+    const float4 ra = R.c[0], rb = R.c[1], rc = R.c[2];
     d3 qq;
     double w[3];
-    const int region = closest_triangle_t<d3, double>(o, mkd(fv[0], fv[1], fv[2]) - c, mkd(fv[3], fv[4], fv[5]) - c,
-                                                      mkd(fv[6], fv[7], fv[8]) - c, qq, w);
+    const int region = closest_triangle_t<d3, double>(o, mkd(ra.x, ra.y, ra.z) - c, mkd(rb.x, rb.y, rb.z) - c,
+                                                      mkd(rc.x, rc.y, rc.z) - c, qq, w);
     dd = len(qq);
     float4 n4;
     if (region == 0) {
-      n4 = P.fn[id];
+      n4 = R.n;
     } else if (region <= 3) {
       const int4 E = P.edges[P.face_edges[3 * (int64_t)id + region - 1]];
-      const float4 f1 = P.fn[E.z], f2 = P.fn[E.w];
+      const float4 f1 = P.frec[E.z].n, f2 = P.frec[E.w].n;
       n4 = make_float4(f1.x + f2.x, f1.y + f2.y, f1.z + f2.z, 0.f);
     } else {
       n4 = P.vinfo[P.T[3 * (int64_t)id + region - 4]];
@@ -470,7 +470,7 @@ __device__ inline bool dist_wide(const ScanArgs& P, const MeshDesc& G, int id, i
       const float4 vi = P.vinfo[tt <= 0.0 ? E.x : E.y];
       N = mkd(vi.x, vi.y, vi.z);
     } else {
-      const float4 f1 = P.fn[E.z], f2 = P.fn[E.w];
+      const float4 f1 = P.frec[E.z].n, f2 = P.frec[E.w].n;
       N = mkd((double)f1.x + f2.x, (double)f1.y + f2.y, (double)f1.z + f2.z);
     }
     code = dot(qq, N) <= 0.0 ? SIGN_POS : SIGN_NEG;
@@ -1029,8 +1029,7 @@ __global__ void k_band_offsets(const int32_t* __restrict__ first_slot, const int
 struct SignArgs {
   const float* V;
   const int32_t* T;
-  const float* fv;  // corner positions in face order
-  const float4* fn;
+  const FaceRec* frec;  // [nf] corners, vertex indices, unit normal
   const int4* edges;
   const int32_t* face_edges;
   const float4* vinfo;
@@ -1080,13 +1079,14 @@ __device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned 
   if (id < P.nf) {
     const int64_t f = id;
     float wt[3];
-    const float* fv = P.fv + 9 * f;
-    int r = closest_triangle(mk(0.f, 0.f, 0.f), tof(mkd(fv[0], fv[1], fv[2]) - c), tof(mkd(fv[3], fv[4], fv[5]) - c),
-                             tof(mkd(fv[6], fv[7], fv[8]) - c), qq, wt);
-    if (r == 0) N = xyz(P.fn[f]);
+    const FaceRec& R = P.frec[f];
+    const float4 ra = R.c[0], rb = R.c[1], rc = R.c[2];
+    int r = closest_triangle(mk(0.f, 0.f, 0.f), tof(mkd(ra.x, ra.y, ra.z) - c), tof(mkd(rb.x, rb.y, rb.z) - c),
+                             tof(mkd(rc.x, rc.y, rc.z) - c), qq, wt);
+    if (r == 0) N = xyz(R.n);
     else if (r <= 3) {
       int4 E = P.edges[P.face_edges[3 * f + r - 1]];
-      N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
+      N = xyz(P.frec[E.z].n) + xyz(P.frec[E.w].n);
     } else N = xyz(P.vinfo[P.T[3 * f + r - 4]]);
   } else if (id < P.nf + P.ne) {
     int4 E = P.edges[id - P.nf];
@@ -1094,7 +1094,7 @@ __device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned 
     qq = closest_segment(mk(0.f, 0.f, 0.f), rel(P.V, E.x, c), rel(P.V, E.y, c), tt);
     if (tt <= 0.f) N = xyz(P.vinfo[E.x]);
     else if (tt >= 1.f) N = xyz(P.vinfo[E.y]);
-    else N = xyz(P.fn[E.z]) + xyz(P.fn[E.w]);
+    else N = xyz(P.frec[E.z].n) + xyz(P.frec[E.w].n);
   } else {
     const int64_t v = id - P.nf - P.ne;
     qq = rel(P.V, v, c);
@@ -1204,8 +1204,7 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   ScanArgs A;
   A.V = f->verts;
   A.T = f->tris_g;
-  A.fv = f->face_v;
-  A.fn = f->face_n;
+  A.frec = f->face_rec;
   A.edges = f->edges;
   A.face_edges = f->face_edges;
   A.fslack = f->fslack;
@@ -1400,8 +1399,7 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
     SignArgs S;
     S.V = f->verts;
     S.T = f->tris_g;
-    S.fv = f->face_v;
-    S.fn = f->face_n;
+    S.frec = f->face_rec;
     S.edges = f->edges;
     S.face_edges = f->face_edges;
     S.vinfo = f->vinfo;

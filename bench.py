@@ -76,7 +76,7 @@ def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
     one-thread-per-polyhedron launches, then of the overflow launches."""
     F, E = info["n_faces"], info["n_edges"]
     if stage == "init_keys":
-        return 8 * info["n_bricks"] * 512
+        return 8 * info["max_band_cells"]  # every key of the allocated bricks
     if stage == "scan_faces":   # per face its corners and unit normal (36 + 12 B), one u64 per atomic
         return 48 * F + 8 * atomics[0]
     if stage == "scan_edges":   # per edge polyhedron its record, endpoints and two normals (16 + 24 + 24 B)
@@ -97,7 +97,12 @@ def popcount64(mask_np):
     return int(np.unpackbits(np.ascontiguousarray(mask_np).view(np.uint8)).sum())
 
 
-def atomic_rates(P, feats, ws, n_keys, nv, reps=10):
+def brick_cells(info):
+    """Keys per brick of the band store."""
+    return int(info["max_band_cells"]) // max(1, int(info["n_bricks"]))
+
+
+def atomic_rates(P, feats, ws, n_keys, nv, brick, reps=10):
     """Measured atomic peaks at the scan's own locality: the packed atomicMin
     instructions of each scan launch are logged (one round per wavefront
     instruction, with its lanes) and replayed by a kernel that does nothing
@@ -139,7 +144,7 @@ def atomic_rates(P, feats, ws, n_keys, nv, reps=10):
         rows = np.repeat(np.arange(addr.shape[0]), 64).reshape(-1, 64)[bits]
         a = addr[bits]
         lines = np.unique(rows * (1 << 32) + (a >> 4)).size / addr.shape[0]
-        bricks = np.unique(rows * (1 << 32) + (a >> 9)).size / addr.shape[0]
+        bricks = np.unique(rows * (1 << 32) + a // brick).size / addr.shape[0]
         srt = np.sort(a).astype(np.uint32)
         pad = (-srt.size) % 64
         slog = torch.from_numpy(np.concatenate([srt, np.zeros(pad, np.uint32)]).view(np.int32)).to(ws.device)
@@ -165,10 +170,12 @@ def atomic_rates(P, feats, ws, n_keys, nv, reps=10):
 
 def rooflines(avg, per_step, atomics, rates, alg_bytes, fwd_bytes):
     """Per single-kernel stage: T_roof = max(algorithmic bytes / 8 TB/s, atomics /
-    measured atomic rate of that launch) against its measured time; the dominant
-    (slowest) kernel's entry is the bench line's roofline. The forward pass (a5 +
-    a6 launches) gets the same bound from its total bytes and atomics against
-    the replay rate of all its launches together."""
+    measured atomic rate of that launch) against its measured time. The bench
+    line's roofline is the dominant (slowest) kernel of the forward scan, the
+    part of the method the roofline target is set on, with the whole forward
+    pass's fraction beside it and the slowest kernel of the step named too. The
+    forward pass (scan and sign launches) gets the same bound from its total
+    bytes and atomics against the replay rate of all its launches together."""
     per = {}
     for st in SINGLE_KERNEL_STAGES:
         t = avg.get(st, 0.0)
@@ -186,7 +193,8 @@ def rooflines(avg, per_step, atomics, rates, alg_bytes, fwd_bytes):
         ent["frac"] = max(ent["hbm_frac"], ent.get("atomic_frac", 0.0))
         ent["bound"] = "atomic" if ent.get("atomic_frac", 0.0) > ent["hbm_frac"] else "hbm"
         per[st] = ent
-    dom = max(per, key=lambda k: per[k]["ms"])
+    slowest = max(per, key=lambda k: per[k]["ms"])
+    dom = max((k for k in per if k in FORWARD_STAGES), key=lambda k: per[k]["ms"])
     d = per[dom]
     if d["bound"] == "atomic":
         main = {"bound": "atomic", "achieved": d["atomic_G_per_s"], "peak": d["atomic_peak_G_per_s"],
@@ -206,6 +214,9 @@ def rooflines(avg, per_step, atomics, rates, alg_bytes, fwd_bytes):
     fwd["t_roof_ms"] = max(fwd["t_hbm_ms"], fwd.get("t_atomic_ms", 0.0))
     fwd["frac"] = fwd["t_roof_ms"] / t_fwd if t_fwd > 0 else None
     fwd["bound"] = "atomic" if fwd.get("t_atomic_ms", 0.0) > fwd["t_hbm_ms"] else "hbm"
+    main["forward_frac"] = fwd["frac"]
+    main["slowest_kernel"] = {"kernel": KERNEL_SYMBOL[slowest], "ms": per[slowest]["ms"], "frac": per[slowest]["frac"],
+                              "bound": per[slowest]["bound"]}
     return main, per, dom, fwd
 
 
@@ -214,6 +225,63 @@ def forward_bytes(nv, nf, ne, atomics, band_cells):
     triangle, 16 B per edge record), 8 B per packed atomicMin, the key read by
     the sign pass and the band written (SDF and id), 8 B each per band cell."""
     return 12 * nv + 12 * nf + 16 * ne + 8 * sum(atomics) + 8 * band_cells + 8 * band_cells
+
+
+def host_info():
+    """The host the CPU baseline ran on: CPU model, logical CPUs, CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_single_thread(budget_s=5.0):
+    """The oracle on one thread: the cube on 64^3 (12 triangles, band 3) over the
+    whole grid, and the jittered icosphere L5 on 256^3 (band 4) over z-slabs
+    through the middle until about budget_s seconds. Runs in a child process,
+    since the oracle's OpenMP thread count is fixed when it loads."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-single-thread",
+                        "--cpu-budget", str(budget_s)], env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def _oracle_single_thread_child(budget_s):
+    import meshgen
+    import oracle
+    out = {}
+    for cfg, key in ((1, "cube_64"), (2, "icosphere5_jitter_256")):
+        name, meshes, grids = meshgen.make_config(cfg)
+        (v, f), g = meshes[0], grids[0]
+        om = oracle.OracleMesh(v, f)
+        n2, step = int(g.n[2]), 16
+        cells, spent, planes, threads, i = 0, 0.0, 0, 1, 0
+        while planes < n2 and (cfg == 1 or spent < budget_s):
+            off = ((i + 1) // 2) * step * (1 if i % 2 else -1)
+            k0 = max(0, min(n2 - step, n2 // 2 + off)) if cfg != 1 else i * step
+            t0 = time.perf_counter()
+            b = om.band(g, k0, k0 + step)
+            spent += time.perf_counter() - t0
+            cells += int(((b["flags"] & oracle.FLAG_IN_BAND) > 0).sum())
+            threads = b["threads"]
+            planes += step
+            i += 1
+        out[key] = {"value": cells / spent, "unit": "cells/s", "threads": threads, "band_cells": cells,
+                    "z_planes": planes, "of_z_planes": n2, "seconds": spent}
+    print(json.dumps(out))
 
 
 def cpu_baseline(v, f, grid, budget_s=15.0):
@@ -289,9 +357,9 @@ def parse_rows(text):
     return rows
 
 
-def batch_algorithmic_bytes(stage, nf, nv, n_epoly, n_vpoly, atomics, band_cells, vert_refs, n_bricks):
+def batch_algorithmic_bytes(stage, nf, nv, n_epoly, n_vpoly, atomics, band_cells, vert_refs, max_band_cells):
     info = {"n_faces": nf, "n_edges": 3 * nf // 2, "n_edge_polyhedra": n_epoly, "n_vertex_polyhedra": n_vpoly,
-            "n_bricks": n_bricks}
+            "max_band_cells": max_band_cells}
     return algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv)
 
 
@@ -343,12 +411,13 @@ def bench_batch(args):
     for _ in range(max(1, args.warmup)):
         B.step()
     avg, ms_eager, per_step = stage_averages(B.step, args.steps)
-    rates = atomic_rates(P, B.f, B.workspace, int(info["n_bricks"]) * 512, int(info["n_vertices"]))
+    rates = atomic_rates(P, B.f, B.workspace, int(info["max_band_cells"]), int(info["n_vertices"]),
+                         brick_cells(info))
     NF, NV = int(info["n_faces"]), int(info["n_vertices"])
     main, per, dom, fwd = rooflines(
         avg, per_step, atomics, rates,
         lambda st: batch_algorithmic_bytes(st, NF, NV, int(info["n_edge_polyhedra"]), int(info["n_vertex_polyhedra"]),
-                                           atomics, M, vert_refs, int(info["n_bricks"])),
+                                           atomics, M, vert_refs, int(info["max_band_cells"])),
         forward_bytes(NV, NF, int(info["n_edges"]), atomics, M))
     main["traffic"] = load_traffic("batch64", dom)
     main["measured_on"] = "eager batched steps, scan kinds one after another"
@@ -431,6 +500,8 @@ def bench_batch(args):
     del B2
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_batch(meshes, grids, args.cpu_budget)
+        res["cpu_baseline"]["host"] = host_info()
+        res["cpu_baseline"]["single_thread"] = oracle_single_thread()
     print(json.dumps(res))
 
 
@@ -554,7 +625,7 @@ def bench_single(args):
         step()
     ms_step, med_step, min_step = timed_steps(step, args.steps)
     avg, _, per_step = stage_averages(step, args.steps)
-    rates = atomic_rates(P, feats, ws, int(info["n_bricks"]) * 512, int(verts.shape[0]))
+    rates = atomic_rates(P, feats, ws, int(info["max_band_cells"]), int(verts.shape[0]), brick_cells(info))
     main, per, dom, fwd = rooflines(avg, per_step, atomics, rates,
                                     lambda st: algorithmic_bytes(st, info, atomics, M, vert_refs, verts.shape[0]),
                                     forward_bytes(int(verts.shape[0]), F, E, atomics, M))
@@ -595,6 +666,8 @@ def bench_single(args):
         res["ablation_per_cell_scan"] = bench_per_cell(P, verts, tris, g, schedule, ws, out, max(3, args.steps // 4))
         if not args.no_cpu_baseline:
             res["cpu_baseline"] = cpu_baseline(v, f, g, args.cpu_budget)
+            res["cpu_baseline"]["host"] = host_info()
+            res["cpu_baseline"]["single_thread"] = oracle_single_thread()
     print(json.dumps(res))
 
 
@@ -703,11 +776,15 @@ def main():
                     help="print a markdown summary of a rocprofv3 kernel_stats.csv (--trace-csv)")
     ap.add_argument("--trace-csv")
     ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--oracle-single-thread", action="store_true",
+                    help="(child process) time the oracle on one thread on the cube and icosphere configs")
     ap.add_argument("--fetch-csv")
     ap.add_argument("--write-csv")
     ap.add_argument("--copy-fetch-csv")
     ap.add_argument("--copy-write-csv")
     args = ap.parse_args()
+    if args.oracle_single_thread:
+        return _oracle_single_thread_child(args.cpu_budget)
     if args.summarize_counters:
         return summarize_counters(args)
     if args.summarize_trace:

@@ -329,18 +329,19 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
   // A brick is kept only if some cell centre in it can lie within r of the face's
   // plane: a cell within band*h of an edge or vertex is that close to a face
   // holding it, and no key is written farther out. The centres of brick (x, y, z)
-  // fill a box of half-width 3.5 h around origin + (8 x + 4) h, whose distance to
-  // the plane is at least |n.(c - a)| - 3.5 h |n|_1. The test gets 1e-3 h of slack
-  // over r against rounding; a degenerate face keeps its whole box.
+  // fill a box of half-width (BRICK - 1) h / 2 around origin + (BRICK x + BRICK / 2) h,
+  // whose distance to the plane is at least |n.(c - a)| - (BRICK - 1) h |n|_1 / 2.
+  // The test gets 1e-3 h of slack over r against rounding; a degenerate face
+  // keeps its whole box.
   const bool cull = l > 0;
   const d3 un = cull ? mkd(n.x / l, n.y / l, n.z / l) : mkd(0.0, 0.0, 0.0);
-  const double ext = 3.5 * g.h * (fabs(un.x) + fabs(un.y) + fabs(un.z)), lim = r + 1e-3 * g.h;
+  const double ext = 0.5 * (BRICK - 1) * g.h * (fabs(un.x) + fabs(un.y) + fabs(un.z)), lim = r + 1e-3 * g.h;
   for (int z = lo[2]; z <= hi[2]; z++)
     for (int y = lo[1]; y <= hi[1]; y++)
       for (int x = lo[0]; x <= hi[0]; x++) {
         if (cull) {
-          const d3 c = mkd(g.origin[0] + (8 * x + 4) * g.h, g.origin[1] + (8 * y + 4) * g.h,
-                           g.origin[2] + (8 * z + 4) * g.h);
+          const d3 c = mkd(g.origin[0] + (BRICK * x + BRICK / 2) * g.h, g.origin[1] + (BRICK * y + BRICK / 2) * g.h,
+                           g.origin[2] + (BRICK * z + BRICK / 2) * g.h);
           if (fabs(dot(un, c - a)) - ext > lim) continue;
         }
         flag[brick_pos(g, x, y, z)] = 1;  // plain stores: no read to wait for

@@ -55,6 +55,7 @@ struct ScanArgs {
   int32_t per_cell;             // 1: test every box cell by itself (Alg. 2) instead of row intervals
   int32_t grid_mode;            // one-polyhedron-per-lane pass: SCAN_GRID_* (how waves get their polyhedra)
   unsigned long long* head;     // SCAN_GRID_QUEUE: next group of 64 polyhedra to hand out
+  int32_t queue_chunk;          // SCAN_GRID_QUEUE: groups a wavefront takes per pop
   // diagnostics (null in normal runs): every packed atomicMin instruction of this
   // launch logged as one round, its lanes' key indices at log[64 r + lane] and
   // the mask of issuing lanes at log_mask[r]
@@ -562,7 +563,7 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
   }
   if (!(d < G.whf)) return;
   }
-  const int64_t bl = brick_pos(G, i >> 3, j >> 3, k >> 3);
+  const int64_t bl = brick_pos(G, i >> BRICK_SHIFT, j >> BRICK_SHIFT, k >> BRICK_SHIFT);
   if (bl != bc.bl) {
     bc.bl = bl;
     bc.slot = P.brick_index[bl];
@@ -570,7 +571,7 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
   const int32_t slot = bc.slot;
   if (slot >= 0 && slot < P.cap) {
     const unsigned long long key = ((unsigned long long)__float_as_uint(d) << 32) | (code << 30) | (uint32_t)id;
-    const int64_t at = (int64_t)slot * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
+    const int64_t at = (int64_t)slot * BRICK_CELLS + brick_local(i, j, k);
     if constexpr (LOG) log_atomic(P, (uint32_t)at);
     atomicMin(&P.keys[at], key);
     issued++;
@@ -928,17 +929,25 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t count = item_count(P), groups = (count + 63) >> 6;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const bool queue = P.grid_mode == SCAN_GRID_QUEUE;
-  auto pop = [&]() -> int64_t {  // the next group from the device counter
-    unsigned long long g = 0;
-    if (lane == 0) g = atomicAdd(P.head, 1ull);
-    return (int64_t)__builtin_amdgcn_readfirstlane((int)g);
-  };
   unsigned issued = 0;
-  // every wave leaves once its next group is past the last one
-  for (int64_t g = queue ? pop() : blockIdx.x * (int64_t)(blockDim.x >> 6) + w; g < groups;
-       g = queue ? pop() : (P.grid_mode == SCAN_GRID_STRIDE ? g + nw : groups))
-    scan_group<KIND, LOG>(P, 64 * g + lane, count, s_slot[w], s_mark[w], s_q[w], issued);
+  if (P.grid_mode == SCAN_GRID_QUEUE) {
+    // Same-address atomics serialise (about 10 ns each here), so a wavefront
+    // takes queue_chunk groups per pop: about two pops per wavefront in all.
+    const int64_t k = P.queue_chunk;
+    auto pop = [&]() -> int64_t {
+      unsigned long long g = 0;
+      if (lane == 0) g = atomicAdd(P.head, (unsigned long long)k);
+      return (int64_t)__builtin_amdgcn_readfirstlane((int)g);
+    };
+    // every wave leaves once its next chunk starts past the last group
+    for (int64_t g0 = pop(); g0 < groups; g0 = pop())
+      for (int64_t g = g0; g < g0 + k && g < groups; g++)
+        scan_group<KIND, LOG>(P, 64 * g + lane, count, s_slot[w], s_mark[w], s_q[w], issued);
+  } else {
+    for (int64_t g = blockIdx.x * (int64_t)(blockDim.x >> 6) + w; g < groups;
+         g = P.grid_mode == SCAN_GRID_STRIDE ? g + nw : groups)
+      scan_group<KIND, LOG>(P, 64 * g + lane, count, s_slot[w], s_mark[w], s_q[w], issued);
+  }
   add_issued(P, issued, 0);
 }
 
@@ -997,7 +1006,7 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 }
 
 // number of set keys per brick slot (0 for slots past the allocated bricks): one
-// wavefront per brick, every lane loading its 8 keys at once (lane + 64 r)
+// wavefront per brick, every lane loading its BRICK_ROUNDS keys at once (lane + 64 r)
 __global__ __launch_bounds__(256) void k_brick_count(const unsigned long long* __restrict__ keys,
                                                      const int64_t* __restrict__ stats, int64_t cap, int32_t* cnt) {
   const int lane = threadIdx.x & 63;
@@ -1007,11 +1016,11 @@ __global__ __launch_bounds__(256) void k_brick_count(const unsigned long long* _
     int c = 0;
     if (s < nb) {
       const unsigned long long* kp = keys + s * BRICK_CELLS + lane;
-      unsigned long long k[8];
+      unsigned long long k[BRICK_ROUNDS];
 #pragma unroll
-      for (int r = 0; r < 8; r++) k[r] = kp[64 * r];
+      for (int r = 0; r < BRICK_ROUNDS; r++) k[r] = kp[64 * r];
 #pragma unroll
-      for (int r = 0; r < 8; r++) c += __popcll(__ballot(k[r] != EMPTY_KEY));
+      for (int r = 0; r < BRICK_ROUNDS; r++) c += __popcll(__ballot(k[r] != EMPTY_KEY));
     }
     if (lane == 0) cnt[s] = c;
   }
@@ -1106,9 +1115,9 @@ __device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned 
 
 // Sign of every band cell (Section 4.1.3, Eq. 8) and the compact band list with
 // each mesh's own feature ids and cell indices. One wavefront per brick: lane l
-// holds cells l + 64 r (x = l & 7, y = l >> 3, z = r) for r = 0..7, loaded at
-// once; the output position is the brick's offset plus the rank among the set
-// cells in (r, lane) order. Most keys carry their sign from the scan; the rest
+// holds the cells of in-brick position l + 64 r for r < BRICK_ROUNDS (x fastest),
+// loaded at once; the output position is the brick's offset plus the rank among
+// the set cells in (r, lane) order, which is the in-brick position order. Most keys carry their sign from the scan; the rest
 // (SIGN_OPEN) are finished after the brick's decided cells.
 __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
   const int lane = threadIdx.x & 63;
@@ -1116,20 +1125,23 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t slot = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); slot < nb; slot += nw) {
     const unsigned long long* kp = P.keys + slot * BRICK_CELLS + lane;
-    unsigned long long key[8];
+    unsigned long long key[BRICK_ROUNDS];
 #pragma unroll
-    for (int r = 0; r < 8; r++) key[r] = kp[64 * r];
+    for (int r = 0; r < BRICK_ROUNDS; r++) key[r] = kp[64 * r];
     const MeshDesc& G = P.md[P.brick_mesh[slot]];
     int bx, by, bz;
     brick_coords(G, P.brick_list[slot], bx, by, bz);
-    const int i = bx * 8 + (lane & 7), j = by * 8 + (lane >> 3);
+    // cell of round r: in-brick position lane + 64 r
+    auto cell_i = [&](int r) { return bx * BRICK + ((lane + 64 * r) & (BRICK - 1)); };
+    auto cell_j = [&](int r) { return by * BRICK + (((lane + 64 * r) >> BRICK_SHIFT) & (BRICK - 1)); };
+    auto cell_k = [&](int r) { return bz * BRICK + ((lane + 64 * r) >> (2 * BRICK_SHIFT)); };
     const int64_t ob = P.boff[slot];
     int before = 0;
     unsigned open_bits = 0;
-    unsigned long long open_pos = 0;  // 9-bit in-brick positions of open cells r = 0..6
+    unsigned long long open_pos = 0;  // 9-bit band ranks within the brick of open cells r = 0..6
     uint32_t open_pos7 = 0;
 #pragma unroll
-    for (int r = 0; r < 8; r++) {
+    for (int r = 0; r < BRICK_ROUNDS; r++) {
       const bool valid = key[r] != EMPTY_KEY;
       const unsigned long long msk = __ballot(valid);
       if (valid) {
@@ -1142,8 +1154,8 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
           else open_pos7 = pos;
         } else {
           const float d = __uint_as_float((uint32_t)(key[r] >> 32));
-          put_cell(P, G, ob + pos, code == SIGN_NEG ? -d : d, local_id(P, G, (int32_t)(lo & ID_MASK)), i, j,
-                   bz * 8 + r);
+          put_cell(P, G, ob + pos, code == SIGN_NEG ? -d : d, local_id(P, G, (int32_t)(lo & ID_MASK)), cell_i(r),
+                   cell_j(r), cell_k(r));
         }
       }
       before += __popcll(msk);
@@ -1152,7 +1164,7 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
       const int r = __ffs(open_bits) - 1;
       open_bits &= open_bits - 1;
       const uint32_t pos = r < 7 ? (uint32_t)(open_pos >> (9 * r)) & 511u : open_pos7;
-      sign_open(P, G, kp[64 * r], i, j, bz * 8 + r, ob + pos);
+      sign_open(P, G, kp[64 * r], cell_i(r), cell_j(r), cell_k(r), ob + pos);
     }
   }
 }
@@ -1236,6 +1248,7 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.log_cap = 0;
   A.grid_mode = SCAN_GRID_STRIDE;
   A.head = nullptr;
+  A.queue_chunk = 1;
   return A;
 }
 
@@ -1285,12 +1298,27 @@ unsigned big_grid() {
   return resident;
 }
 
+// groups per pop of the group queue: about two pops per wavefront of the grid
+// (from the launch bound of the item count), at least 1, at most 64
+inline int32_t queue_chunk(const ScanArgs& A, unsigned blocks) {
+  const int64_t groups = (A.n_items + 63) / 64, waves = 4 * (int64_t)blocks;
+  const int64_t k = groups / (2 * waves);
+  return (int32_t)(k < 1 ? 1 : (k > 64 ? 64 : k));
+}
+
 template <int KIND>
 void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s, const AtomicLog* lg) {
   {
     StageTimer t(stage, s);
-    if (logged(lg, KIND)) k_scan_small<KIND, true><<<small_grid<KIND, true>(A), 256, 0, s>>>(with_log(A, lg));
-    else k_scan_small<KIND, false><<<small_grid<KIND, false>(A), 256, 0, s>>>(A);
+    if (logged(lg, KIND)) {
+      const unsigned g = small_grid<KIND, true>(A);
+      A.queue_chunk = queue_chunk(A, g);
+      k_scan_small<KIND, true><<<g, 256, 0, s>>>(with_log(A, lg));
+    } else {
+      const unsigned g = small_grid<KIND, false>(A);
+      A.queue_chunk = queue_chunk(A, g);
+      k_scan_small<KIND, false><<<g, 256, 0, s>>>(A);
+    }
   }
   {
     StageTimer t(stage_big, s);

@@ -408,20 +408,26 @@ __global__ __launch_bounds__(256) void k_class_stats(const uint8_t* __restrict__
 }
 
 // per face: the largest slack code of its edges and vertices (gathers of the
-// coalesced per-feature codes instead of scattered byte writes per face side)
+// coalesced per-feature codes instead of scattered byte writes per face side),
+// and which of them are absorbed (the face scan signs their cells itself)
 __global__ void k_face_slack(const int32_t* __restrict__ T, const int32_t* __restrict__ face_edges,
                              const uint32_t* __restrict__ vbits, const uint8_t* __restrict__ eslack, int64_t nf,
-                             int64_t ne, uint8_t* fslack) {
+                             int64_t ne, uint8_t* fslack, uint8_t* fabsorbed) {
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  uint32_t q = 0;
+  uint32_t q = 0, bits = 0;
 #pragma unroll
   for (int j = 0; j < 3; j++) {
-    q = max(q, (vbits[T[3 * f + j]] >> V_SLACK_SHIFT) & 0xffu);
+    const uint32_t qv = (vbits[T[3 * f + j]] >> V_SLACK_SHIFT) & 0xffu;
+    q = max(q, qv);
+    if (qv) bits |= 8u << j;
     const int32_t e = face_edges[3 * f + j];
-    if (e >= 0 && e < ne) q = max(q, (uint32_t)eslack[e]);
+    const uint32_t qe = e >= 0 && e < ne ? (uint32_t)eslack[e] : 0u;
+    q = max(q, qe);
+    if (qe) bits |= 1u << j;
   }
   fslack[f] = (uint8_t)q;
+  fabsorbed[f] = (uint8_t)bits;
 }
 
 __global__ void k_edge_queue(const uint8_t* __restrict__ cls, int64_t ne, const int32_t* __restrict__ off, int32_t* q) {
@@ -481,7 +487,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 enum {
   L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FREC, L_ECLS,
   L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_BFLAG,
-  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_N
+  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_FABS, L_N
 };
 
 struct Layout {
@@ -521,6 +527,7 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_SORT] = sort_bytes;
   sz[L_FSLACK] = (size_t)(nf + 8);
   sz[L_ESLACK] = (size_t)(ne + 8);
+  sz[L_FABS] = (size_t)(nf + 8);
   Layout L;
   size_t o = 0;
   for (int i = 0; i < L_N; i++) {
@@ -703,6 +710,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->t_sort_bytes = sort_bytes;
   F->fslack = (uint8_t*)(A + L.off[L_FSLACK]);
   F->eslack = (uint8_t*)(A + L.off[L_ESLACK]);
+  F->fabsorbed = (uint8_t*)(A + L.off[L_FABS]);
   F->built = F->synced = false;
 
 #define CK(x)                                        \
@@ -777,7 +785,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   CK(hipStreamWaitEvent(s, F->ev_geom, 0));  // the face records
   k_edges<<<grid_1d(nh, B), B, 0, s>>>(F->face_rec, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->face_mesh,
                                        F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_c, F->eslack);
-  k_face_slack<<<grid_1d(tf, B), B, 0, s>>>(T, F->face_edges, F->vbits, F->eslack, tf, ne, F->fslack);
+  k_face_slack<<<grid_1d(tf, B), B, 0, s>>>(T, F->face_edges, F->vbits, F->eslack, tf, ne, F->fslack,
+                                            F->fabsorbed);
   // 4. edge polyhedron queue and class statistics
   CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
   k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);

@@ -220,6 +220,7 @@ struct csc_features {
   uint8_t* fslack = nullptr;        // [nf] side slack of the face prism: the largest code of its absorbed
                                     // edges and vertices (1/1024 cells)
   uint8_t* eslack = nullptr;        // [ne] slack code of each absorbed edge (0: not absorbed)
+  uint8_t* fabsorbed = nullptr;     // [nf] bit j: the edge from corner j absorbed; bit 3 + j: corner j's vertex
 
   bool built = false;               // device work queued for the current inputs
   bool synced = false;              // counts below read back since the last build

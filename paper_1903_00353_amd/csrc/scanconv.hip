@@ -30,6 +30,7 @@ struct ScanArgs {
   const int4* edges;
   const int32_t* face_edges;   // [nf][3] edge of each face side (wide faces: boundary signs)
   const uint8_t* fslack;       // [nf] side slack of each face prism (absorbed edges and vertices, 1/1024 cells)
+  const uint8_t* fabsorbed;    // [nf] the face's absorbed edges (bits 0-2) and vertices (bits 3-5)
   const uint8_t* ecls;
   const float4* vinfo;
   const uint32_t* vbits;
@@ -89,6 +90,7 @@ struct Poly {
   int id;           // global feature id
   int mesh;
   int wide;         // box longer than WIDE_CELLS along some axis: distances in FP64
+  int absorbed;     // face: its absorbed edges (bits 0-2, from corner j) and vertices (bits 3-5)
 };
 
 // Local-frame FP32 distances carry a rounding error of about 1e-7 cells per cell
@@ -192,6 +194,7 @@ __device__ inline int build_face(const ScanArgs& P, const MeshDesc& G, int64_t f
   q.cone[0] = nf.x; q.cone[1] = nf.y; q.cone[2] = nf.z;
   q.side = 1.f;
   q.id = (int)f;
+  q.absorbed = P.fabsorbed[f];
   set_axes(q, major_axis(n.x, n.y, n.z));
   return q.dim.x * q.dim.y * q.dim.z;
 }
@@ -249,6 +252,7 @@ __device__ inline int build_edge(const ScanArgs& P, const MeshDesc& G, int32_t e
   q.g[3] = B.x; q.g[4] = B.y; q.g[5] = B.z;
   q.side = (float)sg;
   q.id = (int)(P.nf + e);
+  q.absorbed = 0;
   set_axes(q, us2 > 1e-12 ? major_axis(us.x, us.y, us.z) : major_axis(ed.x, ed.y, ed.z));
   return q.dim.x * q.dim.y * q.dim.z;
 }
@@ -297,6 +301,7 @@ __device__ inline int build_vertex(const ScanArgs& P, const MeshDesc& G, int32_t
   q.g[0] = A.x; q.g[1] = A.y; q.g[2] = A.z;
   q.side = (float)sg;
   q.id = (int)(P.nf + P.ne + v);
+  q.absorbed = 0;
   set_axes(q, major_axis(ax.x, ax.y, ax.z));
   return q.dim.x * q.dim.y * q.dim.z;
 }
@@ -510,7 +515,11 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
   const int L = valid ? (int)(ent >> 48) : 0;
   const int t = (int)((ent >> 32) & 0xffff), du = (int)((ent >> 16) & 0xffff), dv = (int)(ent & 0xffff);
   const int mesh = from_lane<UNI>(q.mesh, L), id = from_lane<UNI>(q.id, L);
-  const int axes = from_lane<UNI>(q.ra | (q.ua << 2), L);
+  // row axes, with the face's absorbed features above them (one lane move).
+  // Every pass decides the same cells: the packed key orders equal distances by
+  // sign code before feature id, so a face whose boundary cell one pass decided
+  // and another left open would win or lose a tie by schedule.
+  const int axes = from_lane<UNI>(q.ra | (q.ua << 2) | (q.absorbed << 4), L);
   const int ax = from_lane<UNI>(q.anc.x, L), ay = from_lane<UNI>(q.anc.y, L), az = from_lane<UNI>(q.anc.z, L);
   const f3 g0 = mk(from_lane<UNI>(q.g[0], L), from_lane<UNI>(q.g[1], L), from_lane<UNI>(q.g[2], L));
   f3 g1 = mk(0.f, 0.f, 0.f), g2 = mk(0.f, 0.f, 0.f), nn = mk(0.f, 0.f, 0.f);
@@ -529,7 +538,7 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
   }
   if (!valid) return;
   const MeshDesc& G = P.md[mesh];
-  const int ra = axes & 3, ua = axes >> 2;
+  const int ra = axes & 3, ua = (axes >> 2) & 3;
   const int di = ra == 0 ? t : (ua == 0 ? du : dv);
   const int dj = ra == 1 ? t : (ua == 1 ? du : dv);
   const int dk = ra == 2 ? t : (ua == 2 ? du : dv);
@@ -546,8 +555,16 @@ __device__ inline void finish_cand(const ScanArgs& P, const Poly& q, unsigned lo
     float w[3];
     const int region = closest_triangle(p, g0, g1, g2, qq, w);
     d = norm3(p - qq);
-    // interior closest point: the face normal is the pseudonormal
-    code = region != 0 ? SIGN_OPEN : (dot(p - qq, nn) >= 0.f ? SIGN_POS : SIGN_NEG);
+    // Interior closest point: the face normal is the pseudonormal. On the
+    // boundary, at an absorbed edge or vertex (region r: edge from corner r - 1,
+    // or corner r - 4; bit r - 1 either way), the face normal gives the same
+    // sign: such a cell sees the feature along a direction within 90 degrees of
+    // every incident face normal (the absorption bound, an angle under 45
+    // degrees, at most doubled), so its dot products with the face normal and
+    // with the feature's pseudonormal share their sign. Other boundary points
+    // are left to the sign pass.
+    const bool own = region == 0 || ((axes >> (3 + region)) & 1);
+    code = !own ? SIGN_OPEN : (dot(p - qq, nn) >= 0.f ? SIGN_POS : SIGN_NEG);
   } else if constexpr (KIND == KIND_EDGE) {
     float tt;
     const f3 qq = closest_segment(p, g0, g1, tt);
@@ -677,7 +694,7 @@ __device__ inline void scan_rows_wave(const ScanArgs& P, const Poly& q, const Ro
       ceps = from_lane<UNI>(r.eps, L);
       const int ax = from_lane<UNI>(q.ra | (q.ua << 2), L);
       cra = ax & 3;
-      cua = ax >> 2;
+      cua = (ax >> 2) & 3;
     }
     while (true) {
       const bool has = t <= t1;
@@ -1220,6 +1237,7 @@ ScanArgs scan_args(const csc_features* f, unsigned long long* keys, int64_t cap)
   A.edges = f->edges;
   A.face_edges = f->face_edges;
   A.fslack = f->fslack;
+  A.fabsorbed = f->fabsorbed;
   A.ecls = f->edge_cls;
   A.vinfo = f->vinfo;
   A.vbits = f->vbits;

@@ -275,7 +275,10 @@ int csc_scan_convert_batched(const csc_features* f, void* workspace_d, size_t ws
  * with q the closest point of the cell centre on feature feat_d[c] and w_k the
  * barycentric weights of q on the feature's vertices, SDF = s |c - q| and
  * dSDF/dx_k = -s w_k (c - q) / |c - q| (the closest feature is held fixed);
- * grad_verts_d[k] += grad_sdf_d[c] * dSDF/dx_k. Cells at zero distance add
+ * grad_verts_d[k] += grad_sdf_d[c] * dSDF/dx_k. grad_sdf_d: float32 per band
+ * cell, or NULL for the loss L = sum of SDF^2 over the band, whose upstream
+ * 2 SDF is then formed in the kernel from sdf_d (the same floats as an explicit
+ * 2 * sdf array, without writing or reading one). Cells at zero distance add
  * nothing. grad_verts_d: float32 [nv][3], accumulated (not cleared). Terms
  * are first summed per block in 64-bit fixed point (exactly, for terms within
  * 2^-17 .. 4 times the block's first chunk's largest |grad_sdf|); those sums

@@ -293,14 +293,16 @@ def csc_scan_convert(f: Features, workspace=None, out=None, dense=None, stream=N
 
 def csc_sdf_backward(f: Features, band: Band, grad_sdf, grad_verts=None, stream=None, n_band_d=None):
     """Accumulate d(sum grad_sdf * SDF)/d(verts) into grad_verts (new zeros if None).
+    ``grad_sdf`` None: the loss sum of SDF^2 (upstream 2 SDF formed in the kernel).
     With ``n_band_d`` (the device count from csc_scan_convert) the band size is read
     on the device and the band tensors may be the full-length outputs."""
     import torch
     if grad_verts is None:
         grad_verts = torch.zeros_like(f.verts)
     n = band.n_band if (band.n_band >= 0 and n_band_d is None) else band.sdf.numel()
+    gp = None if grad_sdf is None else _ptr(grad_sdf.contiguous())
     code = lib().csc_sdf_backward(f.handle, _ptr(band.sdf), _ptr(band.feat), _ptr(band.cell), int(n),
-                                  _ptr(n_band_d), _ptr(grad_sdf.contiguous()), _ptr(grad_verts), _stream(stream))
+                                  _ptr(n_band_d), gp, _ptr(grad_verts), _stream(stream))
     _check(code, "csc_sdf_backward")
     return grad_verts
 
@@ -410,7 +412,8 @@ def csc_scan_convert_batched(f: Features, workspace, out, band_off, stream=None)
 def csc_sdf_backward_batched(f: Features, out, band_off, grad_sdf, grad_verts, stream=None):
     sdf, feat, cell = out
     code = lib().csc_sdf_backward_batched(f.handle, _ptr(sdf), _ptr(feat), _ptr(cell), int(sdf.numel()),
-                                          _ptr(band_off), _ptr(grad_sdf), _ptr(grad_verts), _stream(stream))
+                                          _ptr(band_off), None if grad_sdf is None else _ptr(grad_sdf),
+                                          _ptr(grad_verts), _stream(stream))
     _check(code, "csc_sdf_backward_batched")
 
 
@@ -449,20 +452,18 @@ class Batch:
                     torch.empty(max(mx, 1), dtype=torch.int32, device=device))
         self.band_off = torch.zeros(len(self.grids) + 1, dtype=torch.int64, device=device)
         self.backward = backward
-        self.grad_sdf = torch.empty_like(self.out[0])
         self.grad_verts = torch.zeros_like(self.verts)
         self.graph = None
 
     def step(self):
-        """Build, scan conversion and (if enabled) the adjoint of sum SDF^2; queued only."""
-        import torch
+        """Build, scan conversion and (if enabled) the adjoint of sum SDF^2 (its
+        upstream 2 SDF formed inside the adjoint kernel); queued only."""
         csc_build_features_batched(self.verts, self.tris, self.nv, self.nf, self.grids, self.options,
                                    flags=self.flags | CSC_BUILD_NO_SYNC, reuse=self.f)
         csc_scan_convert_batched(self.f, self.workspace, self.out, self.band_off)
         if self.backward:
-            torch.mul(self.out[0], 2.0, out=self.grad_sdf)
             self.grad_verts.zero_()
-            csc_sdf_backward_batched(self.f, self.out, self.band_off, self.grad_sdf, self.grad_verts)
+            csc_sdf_backward_batched(self.f, self.out, self.band_off, None, self.grad_verts)
 
     def capture(self):
         import torch

@@ -18,7 +18,7 @@ struct BwdArgs {
   const float* sdf;
   const int32_t* feat;       // each mesh's own feature ids
   const int32_t* cell;       // each mesh's own linear cell index
-  const float* gsdf;
+  const float* gsdf;         // dL/dSDF per band cell; null: L = sum of SDF^2, so 2 SDF
   const int64_t* band_off;   // [n_meshes+1] band offsets, or null (one mesh)
   const int64_t* n_dev;      // one mesh: optional device band size
   float* grad;
@@ -42,8 +42,8 @@ struct BwCell {
 __device__ inline BwCell load_cell(const BwdArgs& P, int64_t i, int64_t end) {
   BwCell c = {0.f, 0.f, 0, 0};
   if (i < end) {
-    c.gs = P.gsdf[i];
     c.sd = P.sdf[i];
+    c.gs = P.gsdf ? P.gsdf[i] : 2.f * c.sd;  // fused loss: exactly torch's 2 * sdf
     c.lin = P.cell[i];
     c.lf = P.feat[i];
   }
@@ -178,7 +178,8 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
   // floats: the scale decides which terms are summed exactly and how fast, not
   // whether the sum is right.
   float gmax = 0.f;
-  if (c0 + threadIdx.x < c1) gmax = fmax_finite(0.f, P.gsdf[c0 + threadIdx.x]);
+  if (c0 + threadIdx.x < c1)
+    gmax = fmax_finite(0.f, P.gsdf ? P.gsdf[c0 + threadIdx.x] : 2.f * P.sdf[c0 + threadIdx.x]);
   gmax = wave_max(gmax);
   if ((threadIdx.x & 63) == 0) s_gmax[threadIdx.x >> 6] = gmax;
   __syncthreads();
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
         v3[0] = rec_vertex(ra);
         v3[1] = rec_vertex(rb);
         v3[2] = rec_vertex(rc);
-        closest_triangle(zero, relv(ra, c), relv(rb, c), relv(rc, c), q, w);
+        closest_triangle_t<f3, float, true>(zero, relv(ra, c), relv(rb, c), relv(rc, c), q, w);
         mcount = 3;
       } else if (lf < M.nf + M.ne) {
         int4 E = P.edges[(int64_t)M.e_off + (lf - M.nf)];
@@ -239,11 +240,12 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
         w[0] = 1.f;
         mcount = 1;
       }
-      const float d = norm3(q);
-      if (d > 0.f) {
+      const float dd = dot(q, q);
+      if (dd > 0.f) {
         const float s = cur.sd < 0.f ? -1.f : 1.f;
-        // c - q = -q in this frame; g = s (c - q) / |c - q|
-        const f3 g = q * (-s / d);
+        // c - q = -q in this frame; g = s (c - q) / |c - q| (hardware reciprocal
+        // square root, about 1 ulp: the pass is bound by its vector instructions)
+        const f3 g = q * (-s * rsqrtf(dd));
         for (int k = 0; k < 3; k++) {
           if (k < mcount) {
             vid[k] = v3[k];
@@ -377,7 +379,7 @@ extern "C" int csc_sdf_backward(const csc_features* f, const float* sdf_d, const
                                 const int32_t* cell_d, int64_t n_band, const int64_t* n_band_d,
                                 const float* grad_sdf_d, float* grad_verts_d, void* stream) {
   if (!f || !f->built || n_band < 0 || !grad_verts_d || f->n_meshes != 1) return CSC_INVALID_ARG;
-  if (n_band > 0 && (!sdf_d || !feat_d || !cell_d || !grad_sdf_d)) return CSC_INVALID_ARG;
+  if (n_band > 0 && (!sdf_d || !feat_d || !cell_d)) return CSC_INVALID_ARG;
   if (n_band == 0) return CSC_OK;
   return backward_impl(f, sdf_d, feat_d, cell_d, n_band, n_band_d, nullptr, grad_sdf_d, grad_verts_d,
                        (hipStream_t)stream);
@@ -387,7 +389,7 @@ extern "C" int csc_sdf_backward_batched(const csc_features* f, const float* sdf_
                                         const int32_t* cell_d, int64_t max_band, const int64_t* band_off_d,
                                         const float* grad_sdf_d, float* grad_verts_d, void* stream) {
   if (!f || !f->built || max_band < 0 || !grad_verts_d || !band_off_d) return CSC_INVALID_ARG;
-  if (max_band > 0 && (!sdf_d || !feat_d || !cell_d || !grad_sdf_d)) return CSC_INVALID_ARG;
+  if (max_band > 0 && (!sdf_d || !feat_d || !cell_d)) return CSC_INVALID_ARG;
   if (max_band == 0) return CSC_OK;
   return backward_impl(f, sdf_d, feat_d, cell_d, max_band, nullptr, band_off_d, grad_sdf_d, grad_verts_d,
                        (hipStream_t)stream);

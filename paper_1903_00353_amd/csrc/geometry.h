@@ -223,8 +223,15 @@ struct VertexTest {
 // of Ericson, Real-Time Collision Detection (2005), section 5.1.5. Returns the
 // region: 0 face, 1..3 local edge j-1 (corner j-1 to corner j mod 3), 4..6
 // corner j-4; writes the barycentric weights of q. V3 / S: f3 / float on the
-// scan path, d3 / double where the operands span many cells.
-template <typename V3, typename S>
+// scan path, d3 / double where the operands span many cells. RCP (float only):
+// quotients through the hardware reciprocal (about 1 ulp) instead of a correctly
+// rounded division, where weights feed a gradient rather than a distance.
+template <typename S, bool RCP>
+__host__ __device__ inline S tri_div(S a, S b) {
+  if constexpr (RCP) return a * __builtin_amdgcn_rcpf(b);  // instantiated in device code only
+  else return a / b;
+}
+template <typename V3, typename S, bool RCP = false>
 __host__ __device__ inline int closest_triangle_t(V3 p, V3 a, V3 b, V3 c, V3& q, S w[3]) {
   const S zero = 0, one = 1;
   V3 ab = b - a, ac = c - a, ap = p - a;
@@ -235,7 +242,7 @@ __host__ __device__ inline int closest_triangle_t(V3 p, V3 a, V3 b, V3 c, V3& q,
   if (d3v >= zero && d4 <= d3v) { w[0] = zero; w[1] = one; w[2] = zero; q = b; return 5; }
   S vc = d1 * d4 - d3v * d2;
   if (vc <= zero && d1 >= zero && d3v <= zero) {
-    S t = d1 / (d1 - d3v);
+    S t = tri_div<S, RCP>(d1, d1 - d3v);
     w[0] = one - t; w[1] = t; w[2] = zero; q = a + ab * t; return 1;
   }
   V3 cp = p - c;
@@ -243,15 +250,15 @@ __host__ __device__ inline int closest_triangle_t(V3 p, V3 a, V3 b, V3 c, V3& q,
   if (d6 >= zero && d5 <= d6) { w[0] = zero; w[1] = zero; w[2] = one; q = c; return 6; }
   S vb = d5 * d2 - d1 * d6;
   if (vb <= zero && d2 >= zero && d6 <= zero) {
-    S t = d2 / (d2 - d6);
+    S t = tri_div<S, RCP>(d2, d2 - d6);
     w[0] = one - t; w[1] = zero; w[2] = t; q = a + ac * t; return 3;
   }
   S va = d3v * d6 - d5 * d4;
   if (va <= zero && (d4 - d3v) >= zero && (d5 - d6) >= zero) {
-    S t = (d4 - d3v) / ((d4 - d3v) + (d5 - d6));
+    S t = tri_div<S, RCP>(d4 - d3v, (d4 - d3v) + (d5 - d6));
     w[0] = zero; w[1] = one - t; w[2] = t; q = b + (c - b) * t; return 2;
   }
-  S den = one / (va + vb + vc);
+  S den = tri_div<S, RCP>(one, va + vb + vc);
   S v = vb * den, ww = vc * den;
   w[0] = one - v - ww; w[1] = v; w[2] = ww;
   q = a + ab * v + ac * ww;

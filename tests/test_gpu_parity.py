@@ -239,6 +239,41 @@ def test_backward_matches_oracle_gradient(configs):
     assert np.abs(gv - ref).max() <= 1e-3 * np.abs(ref).max()
 
 
+def test_fused_loss_upstream_matches_explicit(configs):
+    """grad_sdf None (the loss sum of SDF^2, its upstream 2 SDF formed inside
+    the adjoint) accumulates the same terms as an explicit 2 * sdf upstream,
+    for one mesh and for a batch: equal up to the order of the float sums."""
+    name, meshes, grids = configs(2)
+    v, f = meshes[0]
+    g = grids[0]
+    feats, band = run_device(v, f, g)
+    cell, sdf, feat = to_np(band)
+    explicit = P.csc_sdf_backward(feats, band, torch.from_numpy(2.0 * sdf).cuda()).cpu().numpy()
+    fused = P.csc_sdf_backward(feats, band, None).cpu().numpy()
+    om = oracle.OracleMesh(v, f)
+    scale = vertex_term_scale(f, om.edges, v.shape[0], feat, 2.0 * sdf)
+    assert np.abs(fused).max() > 0
+    assert_same_sums(explicit, fused, scale, "single mesh")
+    specs = meshgen.batch_specs()[:4]
+    bm = [meshgen.batch_mesh(sp) for sp in specs]
+    bg = [meshgen.Grid.unit(sp["N"], sp["band"]) for sp in specs]
+    B = P.Batch(bm, bg)
+    B.step()
+    B.check()
+    off = B.band_off.cpu().tolist()
+    gs = torch.zeros_like(B.out[0])
+    gs[:off[-1]] = 2.0 * B.out[0][:off[-1]]
+    gv = torch.zeros_like(B.grad_verts)
+    P.csc_sdf_backward_batched(B.f, B.out, B.band_off, gs, gv)
+    torch.cuda.synchronize()
+    vo = 0
+    for m, (vm, fm) in enumerate(bm):
+        s_m, f_m, _ = (x.cpu().numpy() for x in B.band(m))
+        sc = vertex_term_scale(fm, oracle.OracleMesh(vm, fm).edges, vm.shape[0], f_m, 2.0 * s_m)
+        assert_same_sums(gv[vo:vo + vm.shape[0]].cpu().numpy(), B.grad(m).cpu().numpy(), sc, m)
+        vo += vm.shape[0]
+
+
 def test_backward_wide_range_upstream(configs):
     """The adjoint sums each block's terms in fixed point scaled to the block's
     largest |dL/dSDF|, and sends terms too small for that scale to the gradient

@@ -168,14 +168,16 @@ def atomic_rates(P, feats, ws, n_keys, nv, brick, reps=10):
     return out
 
 
-def rooflines(avg, per_step, atomics, rates, alg_bytes, fwd_bytes):
+def rooflines(avg, per_step, atomics, rates, alg_bytes, fwd_bytes, fwd_span_ms=None):
     """Per single-kernel stage: T_roof = max(algorithmic bytes / 8 TB/s, atomics /
     measured atomic rate of that launch) against its measured time. The bench
     line's roofline is the dominant (slowest) kernel of the forward scan, the
     part of the method the roofline target is set on, with the whole forward
     pass's fraction beside it and the slowest kernel of the step named too. The
     forward pass (scan and sign launches) gets the same bound from its total
-    bytes and atomics against the replay rate of all its launches together."""
+    bytes and atomics against the replay rate of all its launches together; its
+    time is the span of the scan-and-sign call as the timed step runs it
+    (fwd_span_ms), the sum of its stages timed one by one reported beside it."""
     per = {}
     for st in SINGLE_KERNEL_STAGES:
         t = avg.get(st, 0.0)
@@ -204,9 +206,10 @@ def rooflines(avg, per_step, atomics, rates, alg_bytes, fwd_bytes):
     main.update({"kernel": KERNEL_SYMBOL[dom], "frac": d["frac"], "avg_ms": d["ms"],
                  "algorithmic_bytes": d["algorithmic_bytes"], "hbm_frac": d["hbm_frac"],
                  "atomic_frac": d.get("atomic_frac")})
-    t_fwd = sum(per_step.get(st, 0.0) for st in FORWARD_STAGES)
+    t_stages = sum(per_step.get(st, 0.0) for st in FORWARD_STAGES)
+    t_fwd = fwd_span_ms if fwd_span_ms else t_stages
     a_all = sum(atomics)
-    fwd = {"ms": t_fwd, "algorithmic_bytes": fwd_bytes, "atomics": a_all,
+    fwd = {"ms": t_fwd, "ms_stages_one_by_one": t_stages, "algorithmic_bytes": fwd_bytes, "atomics": a_all,
            "t_hbm_ms": fwd_bytes / (PEAK_HBM_GBS * 1e9) * 1e3}
     if "all" in rates:
         fwd["atomic_peak_G_per_s"] = rates["all"]["rate_G_per_s"]
@@ -350,6 +353,28 @@ def stage_averages(fn, steps):
             {k: ms / steps for k, (ms, c) in stages.items()})
 
 
+def forward_span(steps, build, scan, finish):
+    """ms of the forward scan as the timed step runs it: HIP events on the
+    library's stream (torch's current stream) around the scan-and-sign call of
+    `steps` eager steps without stage timing, so that a batch's edge and vertex
+    kinds run beside its faces on the side stream as in the captured graph
+    (the call joins that stream before it returns)."""
+    import statistics
+
+    import torch
+    ev = []
+    for _ in range(steps):
+        build()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        band = scan()
+        e1.record()
+        finish(band)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    return statistics.mean(a.elapsed_time(b) for a, b in ev)
+
+
 def parse_rows(text):
     rows = tuple(int(x) for x in text.split(","))
     if len(rows) != 3 or min(rows) < 1:
@@ -411,6 +436,12 @@ def bench_batch(args):
     for _ in range(max(1, args.warmup)):
         B.step()
     avg, ms_eager, per_step = stage_averages(B.step, args.steps)
+    span = forward_span(
+        args.steps,
+        lambda: P.csc_build_features_batched(B.verts, B.tris, B.nv, B.nf, B.grids, B.options,
+                                             flags=B.flags | P.CSC_BUILD_NO_SYNC, reuse=B.f),
+        lambda: P.csc_scan_convert_batched(B.f, B.workspace, B.out, B.band_off),
+        lambda _: (B.grad_verts.zero_(), P.csc_sdf_backward_batched(B.f, B.out, B.band_off, None, B.grad_verts)))
     rates = atomic_rates(P, B.f, B.workspace, int(info["max_band_cells"]), int(info["n_vertices"]),
                          brick_cells(info))
     NF, NV = int(info["n_faces"]), int(info["n_vertices"])
@@ -418,7 +449,7 @@ def bench_batch(args):
         avg, per_step, atomics, rates,
         lambda st: batch_algorithmic_bytes(st, NF, NV, int(info["n_edge_polyhedra"]), int(info["n_vertex_polyhedra"]),
                                            atomics, M, vert_refs, int(info["max_band_cells"])),
-        forward_bytes(NV, NF, int(info["n_edges"]), atomics, M))
+        forward_bytes(NV, NF, int(info["n_edges"]), atomics, M), span)
     main["traffic"] = load_traffic("batch64", dom)
     main["measured_on"] = "eager batched steps, scan kinds one after another"
     res = {
@@ -622,10 +653,13 @@ def bench_single(args):
         step()
     ms_step, med_step, min_step = timed_steps(step, args.steps)
     avg, _, per_step = stage_averages(step, args.steps)
+    span = forward_span(args.steps, lambda: P.csc_build_features(verts, tris, g, opts, reuse=feats),
+                        lambda: P.csc_scan_convert(feats, ws, out, sync_count=False),
+                        lambda band: (gv.zero_(), P.csc_sdf_backward(feats, band, None, gv, n_band_d=out[3])))
     rates = atomic_rates(P, feats, ws, int(info["max_band_cells"]), int(verts.shape[0]), brick_cells(info))
     main, per, dom, fwd = rooflines(avg, per_step, atomics, rates,
                                     lambda st: algorithmic_bytes(st, info, atomics, M, vert_refs, verts.shape[0]),
-                                    forward_bytes(int(verts.shape[0]), F, E, atomics, M))
+                                    forward_bytes(int(verts.shape[0]), F, E, atomics, M), span)
     main["traffic"] = load_traffic(args.workload, dom)
     res = {
         "metric": METRIC,

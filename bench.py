@@ -87,8 +87,8 @@ def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
         return 8 * atomics[3 + ["scan_faces_big", "scan_edges_big", "scan_vertices_big"].index(stage)]
     if stage == "sign":         # one key read and (sdf, id, cell) written per band cell
         return 20 * band_cells
-    if stage == "backward":     # (sdf, id, cell, dL/dSDF) read, 3 floats added per weighted vertex
-        return 16 * band_cells + 12 * vert_refs
+    if stage == "backward":     # (sdf, id, cell) read (the loss's 2*SDF formed inside), 3 floats per weighted vertex
+        return 12 * band_cells + 12 * vert_refs
     raise KeyError(stage)
 
 

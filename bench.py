@@ -422,7 +422,7 @@ def bench_batch(args):
         F, E = f.shape[0], 3 * f.shape[0] // 2
         vert_refs += int(3 * (fe < F).sum() + 2 * ((fe >= F) & (fe < F + E)).sum() + (fe >= F + E).sum())
 
-    # the timed step: one replay of the captured batched graph (build, scan, sign, 2*SDF, adjoint)
+    # the timed step: one replay of the captured batched graph (build, scan, sign, gradient zeroing, adjoint)
     run = B.step
     if not args.no_graph:
         B.capture()
@@ -712,9 +712,7 @@ def summarize_trace(args):
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:args.top]:
         name = r["Name"].split("(")[0].replace("void ", "")
         if name.startswith("at::native::"):
-            name = "torch " + name.split("<")[0].split("::")[-1] + " (2*SDF, zero fill)"
-        if "rocprim" in name:
-            name = "rocprim radix sort (" + name.split("::")[-1][:40] + ")"
+            name = "torch " + name.split("<")[0].split("::")[-1] + " (gradient zero fill)"
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / tot * 100:.1f} |")

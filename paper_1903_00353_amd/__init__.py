@@ -430,7 +430,8 @@ class Batch:
     most every brick of the grids), so that steps on moved vertices that reach
     new bricks still fit. Bricks past that capacity are dropped and flagged:
     ``check()`` (or ``overflowed()``) after a step or replay whose vertices moved
-    tells whether that happened."""
+    tells whether that happened; call it before the next step, whose build
+    clears the flag."""
 
     def __init__(self, meshes, grids, options=None, device="cuda", backward=True, graph_safe=True, headroom=1.25):
         import torch

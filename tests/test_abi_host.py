@@ -46,7 +46,7 @@ def _grid(n=(8, 8, 8), h=0.125, band=2.0, origin=(0.0, 0.0, 0.0)):
 
 @pytest.mark.parametrize("case", ["null", "nv0", "nf0", "odd_faces", "grid_n", "grid_h", "band", "origin_nan",
                                   "too_many_cells", "long_axis", "bad_option",
-                                  "bad_scan_mode"])
+                                  "bad_scan_mode", "absorb_too_wide", "absorb_nan", "bad_scan_grid"])
 def test_host_argument_checks(case):
     """Checked on the host before any device call: these never need a GPU."""
     L = P.lib()
@@ -79,6 +79,12 @@ def test_host_argument_checks(case):
         opt.saddle_mode = 7
     elif case == "bad_scan_mode":
         opt.scan_mode = 2
+    elif case == "absorb_too_wide":  # the absorption proof needs the slack below a quarter cell
+        opt.absorb_cells = 0.3
+    elif case == "absorb_nan":
+        opt.absorb_cells = float("nan")
+    elif case == "bad_scan_grid":
+        opt.scan_grid = 4
     code = L.csc_build_features(v, nv, t, nf, C.byref(g), C.byref(opt), None, C.byref(out))
     expect = {"odd_faces": 2, "too_many_cells": 5, "long_axis": 5}.get(case, 1)
     assert code == expect

@@ -137,6 +137,7 @@ def atomic_rates(P, feats, ws, n_keys, nv, brick, reps=10):
         ms_read = timed(lambda: P.csc_atomic_replay(log, mask, keys, 1))
         ms_wg = timed(lambda: P.csc_atomic_replay(log, mask, keys, 2))
         ms_st = timed(lambda: P.csc_atomic_replay(log, mask, keys, 3))
+        ms_batched = timed(lambda: P.csc_atomic_replay(log, mask, keys, 4))
         # locality: distinct 128-byte lines (16 keys) and bricks per instruction, and
         # the rate of the same atomics issued in address order (64 per instruction)
         bits = np.unpackbits(m.view(np.uint8).reshape(-1, 8), axis=1, bitorder="little").astype(bool)
@@ -157,7 +158,8 @@ def atomic_rates(P, feats, ws, n_keys, nv, brick, reps=10):
                       "lines_per_instruction": lines, "bricks_per_instruction": bricks,
                       "replay_ms": ms, "log_read_ms": ms_read, "workgroup_scope_ms": ms_wg, "plain_store_ms": ms_st,
                       "rate_G_per_s": n / (ms * 1e-3) / 1e9, "sorted_replay_ms": ms_sorted,
-                      "sorted_rate_G_per_s": n / (ms_sorted * 1e-3) / 1e9}
+                      "sorted_rate_G_per_s": n / (ms_sorted * 1e-3) / 1e9, "batched_replay_ms": ms_batched,
+                      "batched_rate_G_per_s": n / (ms_batched * 1e-3) / 1e9}
         del log, mask, slog, smask
     g = torch.zeros(max(1, nv), 3, dtype=torch.float32, device=ws.device)
     nadd = 1 << 23

@@ -326,7 +326,10 @@ int csc_scan_convert_count(const csc_features* f, void* workspace_d, size_t ws_b
  * as one instruction of one wavefront with the same lanes, and nothing else
  * (mode 0), or only reads the log (mode 1), or issues them at workgroup scope
  * (mode 2: in the issuing XCD's L2 only, so the values are meaningless; a rate
- * measurement) or as plain stores (mode 3): keys_d is any device array of n_keys
+ * measurement) or as plain stores (mode 3), or in blocks of 8 rounds per
+ * wavefront, the block's addresses loaded before its atomics are issued back to
+ * back (mode 4: one wait for completion per block instead of per round, since
+ * stores and atomics complete in order with loads): keys_d is any device array of n_keys
  * uint64 (indices at or past n_keys are skipped); rounds must not exceed the
  * rounds logged. csc_fadd_rate queues n float atomicAdds of 1 to the x, y and z
  * of pseudo-random vertices of grad_d (float32 [nv][3], device): the scattered

@@ -11,7 +11,13 @@ namespace csc {
 // the scan issues it), or only reads the log (mode 1, the cost of the replay's
 // own reads), or issues the atomicMin at workgroup scope (mode 2: performed in
 // the issuing XCD's L2, without cross-XCD coherence; a rate measurement only),
-// or a plain store instead (mode 3)
+// or a plain store instead (mode 3), or (mode 4) the rounds in blocks of
+// REPLAY_BATCH per wavefront: every address of the block loaded first, then the
+// block's atomics issued back to back. Vector memory operations complete in
+// order on this ISA (stores and atomics without return count in the same
+// counter as loads), so in modes 0-3 each round's load also waits for the
+// previous round's atomics; mode 4 waits once per block.
+constexpr int REPLAY_BATCH = 8;
 __global__ __launch_bounds__(256) void k_atomic_replay(const uint32_t* __restrict__ log,
                                                        const unsigned long long* __restrict__ mask, int64_t rounds,
                                                        unsigned long long* keys, int64_t n_keys, int mode,
@@ -19,6 +25,23 @@ __global__ __launch_bounds__(256) void k_atomic_replay(const uint32_t* __restric
   const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   unsigned acc = 0;
+  if (mode == 4) {
+    for (int64_t r0 = (blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6)) * REPLAY_BATCH; r0 < rounds;
+         r0 += nw * REPLAY_BATCH) {
+      uint32_t a[REPLAY_BATCH];
+      bool on[REPLAY_BATCH];
+#pragma unroll
+      for (int b = 0; b < REPLAY_BATCH; b++) {
+        const int64_t r = r0 + b;
+        on[b] = r < rounds && ((mask[r < rounds ? r : 0] >> lane) & 1ull);
+        a[b] = on[b] ? log[r * 64 + lane] : 0u;
+      }
+#pragma unroll
+      for (int b = 0; b < REPLAY_BATCH; b++)
+        if (on[b] && (int64_t)a[b] < n_keys) atomicMin(&keys[a[b]], (unsigned long long)((r0 + b) * 64 + lane));
+    }
+    return;
+  }
   for (int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < rounds; r += nw) {
     const unsigned long long m = mask[r];
     if ((m >> lane) & 1ull) {
@@ -58,7 +81,7 @@ using namespace csc;
 
 extern "C" int csc_atomic_replay(const uint32_t* log_d, const unsigned long long* mask_d, int64_t rounds,
                                  unsigned long long* keys_d, int64_t n_keys, int32_t mode, void* stream) {
-  if (!log_d || !mask_d || !keys_d || rounds < 0 || n_keys <= 0 || mode < 0 || mode > 3)
+  if (!log_d || !mask_d || !keys_d || rounds < 0 || n_keys <= 0 || mode < 0 || mode > 4)
     return CSC_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   k_atomic_replay<<<2048, 256, 0, s>>>(log_d, mask_d, rounds, keys_d, n_keys, mode, (unsigned*)keys_d);

@@ -968,12 +968,21 @@ __global__ __launch_bounds__(256) void k_scan_small(ScanArgs P) {
   add_issued(P, issued, 0);
 }
 
-// The overflow list, one chunk of OV_CHUNK rows of one polyhedron per wavefront
-// and step (a persistent grid striding over the chunks), the chunk's rows dealt
-// out to the lanes. WIDE: the back of the list (wide polyhedra), with FP64
+// first chunk of overflow entry e (list order; the wide list fills from the back)
+template <bool WIDE>
+__device__ inline int64_t ov_first_chunk(const ScanArgs& P, int64_t e) {
+  return P.ov_chunk0[WIDE ? P.ov_cap - 1 - e : e];
+}
+
+// The overflow list in chunks of OV_CHUNK rows of one polyhedron per wavefront
+// and step (a persistent grid striding over the chunks: the list follows face
+// order, so neighbouring chunks are alike in cost), the chunk's rows dealt out
+// to the lanes. WIDE: the back of the list (wide polyhedra), with FP64
 // distances; otherwise the front. Every lane holds the same polyhedron. The
-// chunk's entry is the last whose first chunk is at or before it (binary
-// search: chunk numbers grow along the list).
+// chunk's entry is the last whose first chunk is at or before it, found by a
+// 64-way search (lane j tests the j-th of 64 evenly spaced entries; chunk
+// numbers grow along the list): a few vector loads in place of a chain of
+// dependent ones, starting from the previous chunk's entry.
 template <int KIND, bool WIDE, bool LOG>
 __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
   __shared__ unsigned long long s_q[QCAP];
@@ -981,12 +990,17 @@ __global__ __launch_bounds__(64) void k_scan_big(ScanArgs P) {
   const unsigned long long ctr = P.ov_ctr[WIDE ? 1 : 0];
   const int64_t n = (int64_t)(ctr >> 36), total = (int64_t)(ctr & OV_MASK);
   unsigned issued = 0;
+  int64_t lo = 0;  // entry 0 starts at chunk 0; later chunks lie at or after the previous one's entry
   for (int64_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
-    int64_t lo = 0, hi = n - 1;
+    int64_t hi = n - 1;
     while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (P.ov_chunk0[WIDE ? P.ov_cap - 1 - mid : mid] <= ch) lo = mid;
-      else hi = mid - 1;
+      const int64_t step = (hi - lo + 64) >> 6;  // ceil((hi - lo + 1) / 64)
+      const int64_t at = lo + lane * step;
+      const bool le = at <= hi && ov_first_chunk<WIDE>(P, at) <= ch;
+      const int last = 63 - __clzll((long long)__ballot(le));  // lane 0 always holds
+      const int64_t nlo = lo + last * step;
+      hi = nlo + step - 1 < hi ? nlo + step - 1 : hi;
+      lo = nlo;
     }
     const int64_t slot = WIDE ? P.ov_cap - 1 - lo : lo;
     Poly q = {};

@@ -399,7 +399,7 @@ def bench_batch(args):
     cfg, desc = WORKLOADS["batch64"]
     name, meshes, grids = meshgen.make_config(cfg)
     dev = torch.device("cuda:0")
-    B = P.Batch(meshes, grids, device=dev, backward=True, graph_safe=True)
+    B = P.Batch(meshes, grids, device=dev, backward=True, graph_safe=True, face_order=not args.input_order)
     from paper_1903_00353_amd import autotune
     tune_ms = None
     if args.small_rows:
@@ -625,6 +625,8 @@ def bench_single(args):
         schedule, tune_ms = autotune.tune_single(verts, tris, g)  # (small_rows, scan_grid, absorb_cells)
     opts = autotune.options_for(schedule)
     feats = P.csc_build_features(verts, tris, g, opts)
+    if args.face_order:
+        P.csc_features_order_faces(feats)
     info = feats.info()
     nbytes, mx = P.csc_scan_convert_workspace(feats)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -796,6 +798,8 @@ def main():
     ap.add_argument("--small-rows", help="fixed schedule faces,edges,vertices instead of the autotuned one")
     ap.add_argument("--scan-grid", type=int, default=2, help="with --small-rows: scan_grid (1, 2, 3)")
     ap.add_argument("--absorb", type=float, default=0.05, help="with --small-rows: absorb_cells (negative: off)")
+    ap.add_argument("--face-order", action="store_true", help="single mesh: scan the faces in spatial order")
+    ap.add_argument("--input-order", action="store_true", help="batch64: scan the faces in input order")
     ap.add_argument("--timed-only", action="store_true",
                     help="only the timed fwd+bwd steps (for profiling: no forward-only, per-mesh or CPU legs)")
     ap.add_argument("--no-graph", action="store_true", help="batch64: time eager steps instead of graph replays")

@@ -163,6 +163,25 @@ int csc_build_features_batched(const float* verts_d, const int32_t* tris_d, cons
  * too small for the bricks: CSC_WORKSPACE_TOO_SMALL). */
 int csc_features_sync(csc_features* f, void* stream);
 
+/* Spatial processing order of the face pass (a schedule, not a result: every
+ * output is bit for bit the same with or without it). The paper sorts its
+ * triangle soup by the Morton code of the vertices (Section 7.1); here the faces
+ * keep their input ids and only the order in which the scan conversion takes
+ * them changes: by the Morton code of each face's centroid in its own grid, per
+ * mesh. Neighbouring faces then share wavefronts, and their atomic minima share
+ * cache lines, where an input numbered by subdivision or by mesh generator
+ * scatters them.
+ *   enable 1: compute the order from the face positions of the handle's last
+ *     build (call after a build; allocates, queues on `stream` and waits for
+ *     it). Later builds into the same handle with the same total face count keep
+ *     it: in a loop where the vertices move and the connectivity does not, one
+ *     call serves every step (a stale order is only slower, never wrong).
+ *   enable 0: drop the order (the input order again).
+ * Errors: CSC_INVALID_ARG (null or unbuilt handle, enable not 0 or 1),
+ * CSC_OUT_OF_MEMORY, CSC_HIP_ERROR. The handle owns the order; csc_features_free
+ * releases it. */
+int csc_features_order_faces(csc_features* f, int32_t enable, void* stream);
+
 /* Copy the counts of a built and synchronised handle into *info. */
 int csc_features_info(const csc_features* f, csc_feature_info* info);
 

@@ -64,7 +64,8 @@ EXPORTS = ["csc_build_features", "csc_features_info", "csc_scan_convert_workspac
            "csc_timing_reset", "csc_timing_read", "csc_timing_stage_name", "csc_build_features_batched",
            "csc_features_sync", "csc_scan_convert_batched", "csc_sdf_backward_batched", "csc_interior_fill",
            "csc_weld_soup", "csc_scan_record_atomics", "csc_atomic_replay", "csc_fadd_rate",
-           "csc_weld_soup_noalloc", "csc_weld_soup_noalloc_max_faces", "csc_scan_convert_workspace_for"]
+           "csc_weld_soup_noalloc", "csc_weld_soup_noalloc_max_faces", "csc_scan_convert_workspace_for",
+           "csc_features_order_faces"]
 CSC_BUILD_NO_SYNC = 1
 CSC_BUILD_GRAPH_SAFE = 2
 N_STAGES = 13
@@ -94,6 +95,8 @@ def lib():
     L.csc_scan_convert.argtypes = [P, P, C.c_size_t, P, P, P, P, P, P]
     L.csc_sdf_backward.restype = C.c_int
     L.csc_sdf_backward.argtypes = [P, P, P, P, C.c_int64, P, P, P, P]
+    L.csc_features_order_faces.restype = C.c_int
+    L.csc_features_order_faces.argtypes = [P, C.c_int32, P]
     L.csc_scan_convert_count.restype = C.c_int
     L.csc_scan_convert_count.argtypes = [P, P, C.c_size_t, P, P]
     L.csc_timing_enable.restype = C.c_int
@@ -378,6 +381,15 @@ def csc_features_sync(f: Features, stream=None):
     _check(lib().csc_features_sync(f.handle, _stream(stream)), "csc_features_sync")
 
 
+def csc_features_order_faces(f: Features, enable: bool = True, stream=None):
+    """Set (or with ``enable=False`` drop) the spatial processing order of the
+    face pass, computed from the face positions of the handle's last build and
+    kept by later builds into the same handle. A schedule only: the outputs are
+    bit for bit the same either way."""
+    _check(lib().csc_features_order_faces(f.handle, 1 if enable else 0, _stream(stream)),
+           "csc_features_order_faces")
+
+
 def csc_build_features_batched(verts, tris, nv, nf, grids, options=None, flags=0, stream=None,
                                reuse: Features | None = None) -> Features:
     """verts: [sum nv, 3] float32, tris: [sum nf, 3] int32 (each mesh's own indices),
@@ -431,9 +443,14 @@ class Batch:
     new bricks still fit. Bricks past that capacity are dropped and flagged:
     ``check()`` (or ``overflowed()``) after a step or replay whose vertices moved
     tells whether that happened; call it before the next step, whose build
-    clears the flag."""
+    clears the flag.
 
-    def __init__(self, meshes, grids, options=None, device="cuda", backward=True, graph_safe=True, headroom=1.25):
+    With ``face_order`` the face pass takes the faces in the spatial order of
+    that first build (``csc_features_order_faces``), kept by every later step: a
+    schedule only, the results are the same bit for bit."""
+
+    def __init__(self, meshes, grids, options=None, device="cuda", backward=True, graph_safe=True, headroom=1.25,
+                 face_order=True):
         import torch
         self.grids = list(grids)
         self.nv = [int(m[0].shape[0]) for m in meshes]
@@ -445,6 +462,8 @@ class Batch:
         self.flags = CSC_BUILD_GRAPH_SAFE if graph_safe else 0
         self.f = csc_build_features_batched(self.verts, self.tris, self.nv, self.nf, self.grids, options,
                                             flags=self.flags)
+        if face_order:
+            csc_features_order_faces(self.f)
         nb = int(self.f.info()["n_bricks"])
         nbytes, mx = csc_scan_convert_workspace_for(self.f, int(nb * float(headroom)) + 1)
         self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)

@@ -69,6 +69,7 @@ extern "C" void csc_features_free(csc_features* f) {
   if (!f) return;
   if (f->side) (void)hipStreamSynchronize(f->side);
   if (f->arena) (void)hipFree(f->arena);
+  if (f->face_order) (void)hipFree(f->face_order);
   if (f->h_stats) (void)hipHostFree(f->h_stats);
   if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
   if (f->ev_join) (void)hipEventDestroy(f->ev_join);

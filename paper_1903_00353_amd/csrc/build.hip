@@ -476,9 +476,78 @@ int status_from_errors(uint64_t err, int64_t ne_found, int64_t ne_expected) {
   return CSC_OK;
 }
 
+// Key of the spatial processing order of the faces: the Morton code of each
+// face's centroid in its own grid, at `axis_bits` bits per axis, with its mesh
+// above it (the paper orders its triangle soup by Morton code as well, Section
+// 7.1; here the order only schedules the face pass and changes no result).
+__global__ void k_face_order_keys(const FaceRec* __restrict__ R, const int32_t* __restrict__ face_mesh,
+                                  const MeshDesc* __restrict__ md, int64_t nf, int axis_bits, uint32_t* key) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint32_t top = (1u << axis_bits) - 1u;
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf; f += stride) {
+    const int m = face_mesh[f];
+    const MeshDesc& G = md[m];
+    const float4 a = R[f].c[0], b = R[f].c[1], c = R[f].c[2];
+    const double x[3] = {((double)a.x + b.x + c.x) / 3.0, ((double)a.y + b.y + c.y) / 3.0,
+                         ((double)a.z + b.z + c.z) / 3.0};
+    uint32_t code = 0;
+    for (int k = 0; k < 3; k++) {
+      const double u = (x[k] - G.origin[k]) * G.inv_h / G.n[k] * (double)(1u << axis_bits);
+      const uint32_t qk = u <= 0.0 ? 0u : (u >= (double)top ? top : (uint32_t)u);  // NaN-free: finite inputs
+      for (int bit = 0; bit < axis_bits; bit++) code |= ((qk >> bit) & 1u) << (3 * bit + k);
+    }
+    key[f] = ((uint32_t)m << (3 * axis_bits)) | code;
+  }
+}
+
 }  // namespace csc
 
 using namespace csc;
+
+extern "C" int csc_features_order_faces(csc_features* F, int32_t enable, void* stream) {
+  if (!F || !F->built || (enable != 0 && enable != 1)) return CSC_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (!enable || F->nf == 0) {
+    if (F->face_order) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(F->face_order);
+      F->face_order = nullptr;
+      F->face_order_n = 0;
+    }
+    return CSC_OK;
+  }
+  const int64_t nf = F->nf;
+  int mesh_bits = 0;
+  while ((1 << mesh_bits) < F->n_meshes) mesh_bits++;
+  int axis_bits = (32 - mesh_bits) / 3;
+  if (axis_bits > 10) axis_bits = 10;
+  const int bits = mesh_bits + 3 * axis_bits;
+  const size_t sort_bytes = sort_pairs_tmp_bytes(nf, bits);
+  if (sort_bytes == 0) return CSC_INVALID_ARG;
+  const size_t key_bytes = ((size_t)nf * sizeof(uint32_t) + 255) & ~(size_t)255;
+  if (!F->face_order) {
+    hipError_t he = hipMalloc((void**)&F->face_order, sizeof(int32_t) * (size_t)nf);
+    if (he != hipSuccess) {
+      F->face_order = nullptr;
+      return he == hipErrorOutOfMemory ? CSC_OUT_OF_MEMORY : fail_hip(he);
+    }
+  }
+  F->face_order_n = 0;  // not valid until the sort below has run
+  char* tmp = nullptr;
+  hipError_t he = hipMalloc((void**)&tmp, 2 * key_bytes + sort_bytes);
+  if (he != hipSuccess) return he == hipErrorOutOfMemory ? CSC_OUT_OF_MEMORY : fail_hip(he);
+  uint32_t* key = (uint32_t*)tmp;
+  uint32_t* key_sorted = (uint32_t*)(tmp + key_bytes);
+  k_face_order_keys<<<grid_1d(nf, 256), 256, 0, s>>>(F->face_rec, F->face_mesh, F->d_mesh, nf, axis_bits, key);
+  he = hipGetLastError();
+  if (he == hipSuccess)
+    he = sort_pairs(tmp + 2 * key_bytes, sort_bytes, key, key_sorted, nullptr, F->face_order, nf, bits, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (he != hipSuccess) return fail_hip(he);
+  F->face_order_n = nf;
+  return CSC_OK;
+}
 
 namespace {
 
@@ -633,6 +702,12 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
     else F->built = F->synced = false;
     return code;
   };
+  if (F->face_order && F->face_order_n != tf) {  // an order of another face count is dropped
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(F->face_order);
+    F->face_order = nullptr;
+    F->face_order_n = 0;
+  }
   int sort_bits = 1;
   while (sort_bits < 31 && ((int64_t)1 << sort_bits) < tv) sort_bits++;
   const size_t sort_bytes = sort_pairs_tmp_bytes(3 * tf, sort_bits);

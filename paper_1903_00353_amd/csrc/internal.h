@@ -221,6 +221,8 @@ struct csc_features {
                                     // edges and vertices (1/1024 cells)
   uint8_t* eslack = nullptr;        // [ne] slack code of each absorbed edge (0: not absorbed)
   uint8_t* fabsorbed = nullptr;     // [nf] bit j: the edge from corner j absorbed; bit 3 + j: corner j's vertex
+  int32_t* face_order = nullptr;    // [face_order_n] optional processing order of the face pass (own allocation)
+  int64_t face_order_n = 0;
 
   bool built = false;               // device work queued for the current inputs
   bool synced = false;              // counts below read back since the last build

@@ -310,8 +310,9 @@ template <int KIND>
 __device__ inline int build_poly(const ScanArgs& P, int64_t item, Poly& q) {
   int nc;
   if constexpr (KIND == KIND_FACE) {
-    q.mesh = P.face_mesh[item];
-    nc = build_face(P, P.md[q.mesh], item, q);
+    const int64_t f = P.items ? P.items[item] : item;  // the face order, if one is set
+    q.mesh = P.face_mesh[f];
+    nc = build_face(P, P.md[q.mesh], f, q);
   } else if constexpr (KIND == KIND_EDGE) {
     const int32_t ent = P.items[item];
     q.mesh = P.face_mesh[P.edges[ent >> 1].z];
@@ -1397,6 +1398,7 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   A.ov_chunk0 = ov + f->nf;
   A.counter = counters;
   A.n_items = f->nf;
+  A.items = f->face_order_n == f->nf ? f->face_order : nullptr;
   A.small_rows = f->opt.small_rows[0];
   A.per_cell = f->opt.scan_mode == 1;
   launch_kind<KIND_FACE>(A, TS_SCAN_FACE, TS_SCAN_FACE_BIG, s, lg);

@@ -202,3 +202,39 @@ def test_headroom_covers_moved_vertices():
     for m in range(len(meshes)):
         a, b = batch_band(roomy, m), batch_band(fresh, m)
         assert all(np.array_equal(x, y) for x, y in zip(a, b)), m
+
+
+def test_face_order_does_not_change_results():
+    """The spatial face order is a schedule: a batch scanned in that order and one
+    scanned in input order give the same band bit for bit and the same gradient
+    sums, also after the vertices moved (a stale order), and a single mesh with
+    its order set and dropped again matches its input-order run."""
+    meshes, grids = small_batch(6)
+    print("[case] face order: batch of", len(meshes), flush=True)
+    A = P.Batch(meshes, grids, face_order=True)
+    B = P.Batch(meshes, grids, face_order=False)
+    edges = [oracle.OracleMesh(v, f).edges for v, f in meshes]
+    for it in range(2):
+        if it == 1:
+            for X in (A, B):
+                X.verts.sub_(0.5).mul_(0.98).add_(0.5)
+        for X in (A, B):
+            X.step()
+            X.check()
+        for m, (v, f) in enumerate(meshes):
+            a, b = batch_band(A, m), batch_band(B, m)
+            assert all(np.array_equal(x, y) for x, y in zip(a, b)), (it, m)
+        scale = np.concatenate([vertex_term_scale(f, edges[m], v.shape[0], batch_band(B, m)[2],
+                                                  2.0 * batch_band(B, m)[1]) for m, (v, f) in enumerate(meshes)])
+        assert_same_sums(A.grad_verts.cpu().numpy(), B.grad_verts.cpu().numpy(), scale, it)
+    v, f = meshgen.icosphere(4, 0.35, 1e-3, 7)
+    grid = meshgen.Grid.unit(128, 3)
+    ref = single(v, f, grid)
+    verts, tris = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    feats = P.csc_build_features(verts, tris, grid)
+    for enable in (True, False):
+        P.csc_features_order_faces(feats, enable)
+        band = P.csc_scan_convert(feats)
+        torch.cuda.synchronize()
+        got = (band.cell.cpu().numpy(), band.sdf.cpu().numpy(), band.feat.cpu().numpy())
+        assert all(np.array_equal(x, y) for x, y in zip(ref[:3], got)), enable

@@ -556,7 +556,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 enum {
   L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FREC, L_ECLS,
   L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_BFLAG,
-  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_FABS, L_N
+  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_FABS, L_EID, L_ECNT, L_N
 };
 
 struct Layout {
@@ -591,12 +591,14 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_TA] = sz[L_TB] = sz[L_TC] = sizeof(int32_t) * (size_t)(big + 1);
   sz[L_TSCAN] = sizeof(int32_t) * (size_t)scan_tmp_ints(big + 1);
   sz[L_BFLAG] = sizeof(int32_t) * (size_t)(nbt + 1);
-  sz[L_TSCAN2] = sizeof(int32_t) * (size_t)scan_tmp_ints(nbt + 1);
+  sz[L_TSCAN2] = sizeof(int32_t) * (size_t)scan_tmp_ints(big + 1);  // the brick flags and the edge numbering
   sz[L_STATS] = sizeof(int64_t) * ST_COUNT;
   sz[L_SORT] = sort_bytes;
   sz[L_FSLACK] = (size_t)(nf + 8);
   sz[L_ESLACK] = (size_t)(ne + 8);
   sz[L_FABS] = (size_t)(nf + 8);
+  sz[L_EID] = sizeof(int32_t) * (size_t)(3 * nf + 1);
+  sz[L_ECNT] = sizeof(int32_t) * (size_t)(ne + 1);
   Layout L;
   size_t o = 0;
   for (int i = 0; i < L_N; i++) {
@@ -786,6 +788,8 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->fslack = (uint8_t*)(A + L.off[L_FSLACK]);
   F->eslack = (uint8_t*)(A + L.off[L_ESLACK]);
   F->fabsorbed = (uint8_t*)(A + L.off[L_FABS]);
+  F->t_eid = (int32_t*)(A + L.off[L_EID]);
+  F->t_ecnt = (int32_t*)(A + L.off[L_ECNT]);
   F->built = F->synced = false;
 
 #define CK(x)                                        \
@@ -822,9 +826,10 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                                                F->vert_mesh, F->d_stats);
   const int32_t* T = F->tris_g;
   // Face records (corners, vertex indices, normal) with the band bricks near each
-  // face, the brick slots and lists: they need only the inputs, so they run on
-  // the side stream while the corner table is sorted and the vertices classified
-  // here; the edge pass waits for the records.
+  // face, the brick slots and lists, the cleared edge tables and the edge
+  // numbering: they need only the inputs, so they run on the side stream while
+  // the corner table is sorted and the vertices classified here; the edge pass
+  // waits for the records, the tables and the numbering.
   CK(hipEventRecord(F->ev_fork, s));
   CK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
   {
@@ -832,6 +837,13 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
     k_fill_i32<<<grid_1d(tb, B), B, 0, s2>>>(F->brick_flag, tb, 0);
     k_face_geom<<<grid_1d(tf, B), B, 0, s2>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_rec,
                                                F->brick_flag, F->d_stats);
+    {
+      const FillJob a = {(int32_t*)F->edges, 4 * (ne + 1), -1}, b = {F->t_ecnt, ne, 0},
+                    c = {(int32_t*)F->edge_cls, (ne + 3) / 4, 0};
+      k_fill3<<<grid_1d(a.n + b.n + c.n, B), B, 0, s2>>>(a, b, c);
+    }
+    // edge ids: a prefix sum over the owned half-edge flags that k_inputs left in face_edges
+    CK(exclusive_scan(F->face_edges, F->t_eid, nh, F->t_scan2, &F->d_stats[ST_NE], nullptr, s2));
     CK(hipEventRecord(F->ev_geom, s2));
     CK(exclusive_scan(F->brick_flag, F->brick_index, tb, F->t_scan2, &F->d_stats[ST_NBRICKS], nullptr, s2));
     k_brick_fix<<<grid_1d(tb, B), B, 0, s2>>>(F->brick_flag, F->brick_index, F->brick_list, F->brick_mesh,
@@ -850,21 +862,16 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                                         absorb, F->t_a, F->vinfo, F->vbits, F->t_c, F->d_stats);
   CK(exclusive_scan(F->t_c, F->t_c, tv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
   k_vertex_queue<<<grid_1d(tv, B), B, 0, s>>>(F->vbits, tv, F->t_c, F->vpoly);
-  {
-    const FillJob a = {(int32_t*)F->edges, 4 * (ne + 1), -1}, b = {F->t_c, ne, 0},
-                  c = {(int32_t*)F->edge_cls, (ne + 3) / 4, 0};
-    k_fill3<<<grid_1d(a.n + b.n + c.n, B), B, 0, s>>>(a, b, c);
-  }
-  CK(exclusive_scan(F->face_edges, F->t_b, nh, F->t_scan, &F->d_stats[ST_NE], nullptr, s));
   // edges with their classes and extrusion sides
-  CK(hipStreamWaitEvent(s, F->ev_geom, 0));  // the face records
-  k_edges<<<grid_1d(nh, B), B, 0, s>>>(F->face_rec, nh, ne, F->t_a, F->t_b, o.force_both_sides, F->face_mesh,
-                                       F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_c, F->eslack);
+  CK(hipStreamWaitEvent(s, F->ev_geom, 0));  // the face records, cleared edge tables and edge ids
+  k_edges<<<grid_1d(nh, B), B, 0, s>>>(F->face_rec, nh, ne, F->t_a, F->t_eid, o.force_both_sides, F->face_mesh,
+                                       F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_ecnt,
+                                       F->eslack);
   k_face_slack<<<grid_1d(tf, B), B, 0, s>>>(T, F->face_edges, F->vbits, F->eslack, tf, ne, F->fslack,
                                             F->fabsorbed);
   // 4. edge polyhedron queue and class statistics
-  CK(exclusive_scan(F->t_c, F->t_c, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
-  k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_c, F->epoly);
+  CK(exclusive_scan(F->t_ecnt, F->t_ecnt, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
+  k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_ecnt, F->epoly);
   {
     const int64_t items = (ne / 16 > tv / 4 ? ne / 16 : tv / 4) + 1;
     k_class_stats<<<grid_1d(items < 1024 * 256 ? items : 1024 * 256, 256), 256, 0, s>>>(F->edge_cls, ne, F->vbits,

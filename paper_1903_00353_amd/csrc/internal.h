@@ -217,6 +217,8 @@ struct csc_features {
   hipEvent_t ev_geom = nullptr;     // the face records are written (the vertex and edge passes read them)
   int32_t* brick_flag = nullptr;    // [nbt + 1] brick marks of the build
   int32_t* t_scan2 = nullptr;       // scan temporaries of the side branch
+  int32_t* t_eid = nullptr;         // [3nf + 1] edge id of each owned half-edge (prefix sum, side branch)
+  int32_t* t_ecnt = nullptr;        // [ne + 1] polyhedra per edge, then their queue offsets
   uint8_t* fslack = nullptr;        // [nf] side slack of the face prism: the largest code of its absorbed
                                     // edges and vertices (1/1024 cells)
   uint8_t* eslack = nullptr;        // [ne] slack code of each absorbed edge (0: not absorbed)

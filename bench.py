@@ -403,7 +403,7 @@ def bench_batch(args):
     from paper_1903_00353_amd import autotune
     tune_ms = None
     if args.small_rows:
-        schedule = (parse_rows(args.small_rows), args.scan_grid, args.absorb)
+        schedule = (parse_rows(args.small_rows), args.scan_grid, args.absorb, args.geom_blocks)
         B.options = autotune.options_for(schedule)
         B.f = P.csc_build_features_batched(B.verts, B.tris, B.nv, B.nf, B.grids, B.options, flags=B.flags,
                                            reuse=B.f)
@@ -477,6 +477,7 @@ def bench_batch(args):
         "step_ms": {"median": med_graph, "min": min_graph, "launch": "eager" if args.no_graph else "graph replay"},
         "batched_eager": {"value": M / (ms_eager * 1e-3), "ms_per_step": ms_eager},
         "schedule": {"small_rows": list(schedule[0]), "scan_grid": schedule[1], "absorb_cells": schedule[2],
+                     "geom_blocks": schedule[3],
                      "tuning_ms": tune_ms or None},
         "stages_ms": {k: round(x, 4) for k, x in avg.items()},
         "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
@@ -620,7 +621,7 @@ def bench_single(args):
     from paper_1903_00353_amd import autotune
     tune_ms = None
     if args.small_rows:
-        schedule = (parse_rows(args.small_rows), args.scan_grid, args.absorb)
+        schedule = (parse_rows(args.small_rows), args.scan_grid, args.absorb, args.geom_blocks)
     else:
         schedule, tune_ms = autotune.tune_single(verts, tris, g)  # (small_rows, scan_grid, absorb_cells)
     opts = autotune.options_for(schedule)
@@ -689,6 +690,7 @@ def bench_single(args):
         "atomics": {"faces": atomics[0], "edges": atomics[1], "vertices": atomics[2], "faces_big": atomics[3],
                     "edges_big": atomics[4], "vertices_big": atomics[5]},
         "schedule": {"small_rows": list(schedule[0]), "scan_grid": schedule[1], "absorb_cells": schedule[2],
+                     "geom_blocks": schedule[3],
                      "tuning_ms": tune_ms or None},
         "features": info,
         "kernel_source_sha": kernel_source_sha(),
@@ -798,6 +800,7 @@ def main():
     ap.add_argument("--small-rows", help="fixed schedule faces,edges,vertices instead of the autotuned one")
     ap.add_argument("--scan-grid", type=int, default=2, help="with --small-rows: scan_grid (1, 2, 3)")
     ap.add_argument("--absorb", type=float, default=0.05, help="with --small-rows: absorb_cells (negative: off)")
+    ap.add_argument("--geom-blocks", type=int, default=0, help="with --small-rows: geom_blocks (0: one thread per face)")
     ap.add_argument("--face-order", action="store_true", help="single mesh: scan the faces in spatial order")
     ap.add_argument("--input-order", action="store_true", help="batch64: scan the faces in input order")
     ap.add_argument("--timed-only", action="store_true",

@@ -96,6 +96,12 @@ typedef struct csc_options {
                                striding over the groups of 64; 3 that grid taking the groups from a
                                device counter in the order the wavefronts ask. 0 = default (2). Only
                                the speed depends on it (the autotuner in the binding picks one). */
+  int32_t geom_blocks;      /* schedule of the build's face pass (face records and band bricks), which runs
+                               beside the corner sort: 0 (default) one thread per face; n > 0 a grid of
+                               at most n blocks of 256 striding over the faces, which leaves the sort
+                               compute units of its own (a batch of many small meshes gains, one large
+                               mesh loses). Only the speed depends on it (the binding's autotuner picks
+                               it for a batch). */
 } csc_options;
 
 typedef struct csc_features csc_features; /* opaque, library-owned, device resident */

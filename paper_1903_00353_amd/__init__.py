@@ -44,7 +44,8 @@ class csc_grid(C.Structure):
 class csc_options(C.Structure):
     _fields_ = [("eps_rel", C.c_float), ("ruff_mode", C.c_int32), ("saddle_mode", C.c_int32),
                 ("force_both_sides", C.c_int32), ("small_rows", C.c_int32 * 3),
-                ("scan_mode", C.c_int32), ("absorb_cells", C.c_float), ("scan_grid", C.c_int32)]
+                ("scan_mode", C.c_int32), ("absorb_cells", C.c_float), ("scan_grid", C.c_int32),
+                ("geom_blocks", C.c_int32)]
 
 
 class csc_feature_info(C.Structure):
@@ -165,15 +166,17 @@ def make_grid(grid) -> csc_grid:
 
 
 def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0, small_rows=(0, 0, 0),
-                 scan_mode=0, absorb_cells=0.0, scan_grid=0) -> csc_options:
+                 scan_mode=0, absorb_cells=0.0, scan_grid=0, geom_blocks=0) -> csc_options:
     """absorb_cells: 0 the library's default, negative to give every non-flat
-    feature its own polyhedron; scan_grid: 0 the default schedule (see csc.h)."""
+    feature its own polyhedron; scan_grid, geom_blocks: 0 the default schedule
+    (see csc.h)."""
     o = csc_options(float(eps_rel), int(ruff_mode), int(saddle_mode), int(force_both_sides))
     for k in range(3):
         o.small_rows[k] = int(small_rows[k])
     o.scan_mode = int(scan_mode)
     o.absorb_cells = float(absorb_cells)
     o.scan_grid = int(scan_grid)
+    o.geom_blocks = int(geom_blocks)
     return o
 
 

@@ -8,13 +8,16 @@ The scan conversion has three schedule choices, none of which changes a value:
     a launch sized to the items, a persistent grid striding over them, or a
     persistent grid taking groups from a device counter);
   * the largest side slack a face prism takes on to absorb the extrusions of
-    nearly flat edges and vertices (``absorb_cells``; negative: none absorbed).
+    nearly flat edges and vertices (``absorb_cells``; negative: none absorbed);
+  * for a batch, the grid of the build's face pass, which runs beside the
+    corner sort (``geom_blocks``: 0 one thread per face, or a capped grid that
+    leaves the sort compute units of its own).
 The tuner times candidates on the caller's own workload with the library's stage
 events (HIP events on the working stream): first ``small_rows`` per kind (each
 kind's one-lane launch plus its overflow launch), then ``scan_grid`` and
 ``absorb_cells`` one after the other on the time of the whole forward pass
-(scans and sign). It caches the choice as JSON keyed by the device and the
-workload's shape.
+(scans and sign), then (batches) ``geom_blocks`` on the build's time. It caches
+the choice as JSON keyed by the device and the workload's shape.
 """
 from __future__ import annotations
 
@@ -25,6 +28,7 @@ import os
 CANDIDATES = (8, 16, 32, 64, 128, 1 << 24)
 GRID_CANDIDATES = (1, 2, 3)
 ABSORB_CANDIDATES = (-1.0, 0.02, 0.05, 0.1, 0.2)
+GEOM_CANDIDATES = (0, 128, 256, 512)
 KIND_STAGES = ("scan_faces", "scan_edges", "scan_vertices")
 FORWARD_STAGES = ("init_keys", "scan_faces", "scan_edges", "scan_vertices", "scan_faces_big", "scan_edges_big",
                   "scan_vertices_big", "scan_wide", "brick_count", "sign")
@@ -45,14 +49,15 @@ def signature(nf_list, grids) -> str:
     tri_cells = faces / max(1.0, cells ** (2.0 / 3.0))  # triangles per cell of surface area (rough)
     return (f"{getattr(dev, 'gcnArchName', dev.name)}|n={len(grids)}|F=2^{round(math.log2(max(faces, 1)))}"
             f"|cells=2^{round(math.log2(max(cells, 1)))}|band={band:g}|tpc=2^{round(math.log2(max(tri_cells, 1e-9)))}"
-            f"|v2")
+            f"|v3")
 
 
 def load(sig: str):
     try:
         with open(cache_path()) as fh:
             rec = json.load(fh).get(sig)
-        return (tuple(rec["small_rows"]), int(rec["scan_grid"]), float(rec["absorb_cells"])) if rec else None
+        return ((tuple(rec["small_rows"]), int(rec["scan_grid"]), float(rec["absorb_cells"]), int(rec["geom_blocks"]))
+                if rec else None)
     except (OSError, ValueError, KeyError, TypeError):
         return None
 
@@ -67,7 +72,7 @@ def save(sig: str, choice, timings):
         except (OSError, ValueError):
             data = {}
         data[sig] = {"small_rows": list(choice[0]), "scan_grid": choice[1], "absorb_cells": choice[2],
-                     "ms": timings}
+                     "geom_blocks": choice[3], "ms": timings}
         with open(path + ".tmp", "w") as fh:
             json.dump(data, fh, indent=1)
         os.replace(path + ".tmp", path)
@@ -99,8 +104,9 @@ def _forward_time(t):
     return sum(t[k] for k in FORWARD_STAGES)
 
 
-def _search(measure, base, reps):
-    """measure(options) -> per-stage ms per call; returns (choice, timings)."""
+def _search(measure, base, reps, build=False):
+    """measure(options) -> per-stage ms per call; returns (choice, timings).
+    build: measure also times the build (its stage), and geom_blocks is tuned."""
     timings = {}
     for c in CANDIDATES:
         timings[f"rows={c}"] = measure(_with(base, rows=(c, c, c)), reps)
@@ -117,13 +123,21 @@ def _search(measure, base, reps):
         timings[f"absorb={a}"] = t
         if best_t is None or t < best_t:
             best_absorb, best_t = a, t
-    return (rows, best_grid, best_absorb), timings
+    best_geom = base.geom_blocks
+    if build:
+        best_t = None
+        for gb in GEOM_CANDIDATES:
+            t = measure(_with(base, rows=rows, grid=best_grid, absorb=best_absorb, geom=gb), reps)["build_features"]
+            timings[f"geom={gb}"] = t
+            if best_t is None or t < best_t:
+                best_geom, best_t = gb, t
+    return (rows, best_grid, best_absorb, best_geom), timings
 
 
 def tune_batch(batch, reps=3, use_cache=True):
     """Pick the schedule for a paper_1903_00353_amd.Batch; rebuilds it with the
     choice (before any graph capture). Returns ((small_rows, scan_grid,
-    absorb_cells), timings)."""
+    absorb_cells, geom_blocks), timings)."""
     import paper_1903_00353_amd as P
     sig = signature(batch.nf, batch.grids)
     base = batch.options if batch.options is not None else P.make_options()
@@ -139,9 +153,9 @@ def tune_batch(batch, reps=3, use_cache=True):
         def measure(opt, reps):
             rebuild(opt)
             return _stage_times(batch.step, reps)
-        choice, timings = _search(measure, base, reps)
+        choice, timings = _search(measure, base, reps, build=True)
         save(sig, choice, timings)
-    rebuild(_with(base, rows=choice[0], grid=choice[1], absorb=choice[2]))
+    rebuild(options_for(choice, base))
     return choice, timings
 
 
@@ -172,15 +186,17 @@ def tune_single(verts, tris, grid, options=None, reps=3, use_cache=True):
 
 
 def options_for(choice, base=None):
-    """csc_options with a tuner choice applied."""
+    """csc_options with a tuner choice (small_rows, scan_grid, absorb_cells[,
+    geom_blocks]) applied."""
     import paper_1903_00353_amd as P
     base = base if base is not None else P.make_options()
-    return _with(base, rows=choice[0], grid=choice[1], absorb=choice[2])
+    return _with(base, rows=choice[0], grid=choice[1], absorb=choice[2], geom=choice[3] if len(choice) > 3 else None)
 
 
-def _with(opt, rows=None, grid=None, absorb=None):
+def _with(opt, rows=None, grid=None, absorb=None, geom=None):
     import paper_1903_00353_amd as P
     return P.make_options(opt.eps_rel, opt.ruff_mode, opt.saddle_mode, opt.force_both_sides,
                           tuple(opt.small_rows) if rows is None else rows, opt.scan_mode,
                           opt.absorb_cells if absorb is None else absorb,
-                          opt.scan_grid if grid is None else grid)
+                          opt.scan_grid if grid is None else grid,
+                          opt.geom_blocks if geom is None else geom)

@@ -289,11 +289,9 @@ __global__ void k_edges(const FaceRec* __restrict__ R, int64_t nh, int64_t ne,
 // axis, edge wedges and vertex cones within band*h + eps of their feature), and
 // a scan writes only cells within band*h of a feature, so every cell a scan can
 // write has its brick marked by one of the faces holding its feature.
-__global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf,
-                            const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, FaceRec* rec,
-                            int32_t* flag, int64_t* stats) {
-  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (f >= nf) return;
+__device__ inline void face_geom_one(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t f,
+                                     const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md,
+                                     FaceRec* rec, int32_t* flag, int64_t* stats) {
   const int32_t ia = T[3 * f], ib = T[3 * f + 1], ic = T[3 * f + 2];
   const f3 af = vload_f(V, ia), bf = vload_f(V, ib), cf = vload_f(V, ic);
   const d3 a = mkd(af.x, af.y, af.z), b = mkd(bf.x, bf.y, bf.z), c = mkd(cf.x, cf.y, cf.z);
@@ -346,6 +344,16 @@ __global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restri
         }
         flag[brick_pos(g, x, y, z)] = 1;  // plain stores: no read to wait for
       }
+}
+
+// a grid striding over the faces (geom_blocks: sized below the device, so
+// that the corner sort, which it runs beside, keeps compute units of its own)
+__global__ void k_face_geom(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t nf,
+                            const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, FaceRec* rec,
+                            int32_t* flag, int64_t* stats) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < nf; f += stride)
+    face_geom_one(V, T, f, face_mesh, md, rec, flag, stats);
 }
 
 // class statistics (and absorbed features): each thread counts 16 edge-class bytes and 4 vertex words per
@@ -634,9 +642,9 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                const csc_grid* grids, int32_t n_meshes, const csc_options* opt, int32_t flags, void* stream,
                csc_features** out) {
   if (!verts_d || !tris_d || !nv || !nf || !grids || !out || n_meshes <= 0) return CSC_INVALID_ARG;
-  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}, 0, 0.f, 0};
+  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}, 0, 0.f, 0, 0};
   if (opt) o = *opt;
-  if (o.scan_grid < 0 || o.scan_grid > 3) return CSC_INVALID_ARG;
+  if (o.scan_grid < 0 || o.scan_grid > 3 || o.geom_blocks < 0) return CSC_INVALID_ARG;
   if (o.scan_grid == 0) o.scan_grid = 2;  // default: persistent grid striding over the groups
   if (!(o.absorb_cells <= 0.24f) || o.absorb_cells != o.absorb_cells) return CSC_INVALID_ARG;
   // 0: the default; negative: every non-flat feature keeps its own polyhedron
@@ -835,8 +843,11 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   {
     hipStream_t s2 = F->side;
     k_fill_i32<<<grid_1d(tb, B), B, 0, s2>>>(F->brick_flag, tb, 0);
-    k_face_geom<<<grid_1d(tf, B), B, 0, s2>>>(verts_d, T, tf, F->face_mesh, F->d_mesh, F->face_rec,
-                                               F->brick_flag, F->d_stats);
+    {
+      const unsigned need = grid_1d(tf, B), cap = (unsigned)o.geom_blocks;
+      k_face_geom<<<cap > 0 && need > cap ? cap : need, B, 0, s2>>>(verts_d, T, tf, F->face_mesh, F->d_mesh,
+                                                                    F->face_rec, F->brick_flag, F->d_stats);
+    }
     {
       const FillJob a = {(int32_t*)F->edges, 4 * (ne + 1), -1}, b = {F->t_ecnt, ne, 0},
                     c = {(int32_t*)F->edge_cls, (ne + 3) / 4, 0};

@@ -142,11 +142,11 @@ def test_batch_rejects_bad_mesh():
 
 
 def test_schedule_does_not_change_results():
-    """The schedule only changes the speed: the wavefront/thread threshold and the
+    """The schedule only changes the speed: the wavefront/thread threshold, the
     three grids of the one-polyhedron-per-lane pass (a launch sized to the items,
     a persistent grid striding over them, a persistent grid taking them from a
-    device counter) give the same band bit for bit; the autotuner picks one of
-    its candidates per kind."""
+    device counter) and the build's face-pass grid give the same band bit for
+    bit; the autotuner picks one of its candidates per kind."""
     meshes, grids = small_batch(6)
     ref = None
     for rows, grid in (((1 << 30,) * 3, 1), ((0, 0, 0), 1), ((4, 8, 2), 2), ((1, 1, 1), 3), ((0, 0, 0), 2),
@@ -163,11 +163,19 @@ def test_schedule_does_not_change_results():
     # distance to its triangle or the edge's own): equal within the tolerance, not
     # bit for bit, so the tuned batch is compared with a default-schedule batch
     # built with the same cap
+    # the build's face pass on a capped grid striding over the faces
+    for geom in (1, 64):
+        B = P.Batch(meshes, grids, options=P.make_options(geom_blocks=geom), backward=False)
+        B.step()
+        B.check()
+        for a, b in zip(ref, [batch_band(B, m) for m in range(len(meshes))]):
+            assert all(np.array_equal(x, y) for x, y in zip(a, b)), geom
     from paper_1903_00353_amd import autotune
     B = P.Batch(meshes, grids, backward=True)
-    (rows, grid, absorb), timings = autotune.tune_batch(B, use_cache=False, reps=1)
+    (rows, grid, absorb, geom), timings = autotune.tune_batch(B, use_cache=False, reps=1)
     assert len(rows) == 3 and all(b in autotune.CANDIDATES for b in rows)
     assert grid in autotune.GRID_CANDIDATES and absorb in autotune.ABSORB_CANDIDATES
+    assert geom in autotune.GEOM_CANDIDATES
     B.step()
     B.check()
     R = P.Batch(meshes, grids, options=P.make_options(absorb_cells=absorb), backward=False)

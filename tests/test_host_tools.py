@@ -22,6 +22,7 @@ def fake_stage_times(opt):
     t["scan_vertices"] = 0.2 if rows[2] == 1 << 24 else 0.3
     t["sign"] = {1: 0.4, 2: 0.3, 3: 0.5}.get(opt.scan_grid, 0.4)  # 0: the library default
     t["init_keys"] = abs(opt.absorb_cells - 0.1) if opt.absorb_cells > 0 else 0.5
+    t["build_features"] = {0: 0.5, 128: 0.45, 256: 0.4, 512: 0.42}[opt.geom_blocks]
     for k in ("scan_faces", "scan_edges", "scan_vertices"):
         t[k + "_big"] = 0.0
     return t
@@ -30,21 +31,26 @@ def fake_stage_times(opt):
 def test_search_picks_each_minimum_in_turn():
     base = P.make_options()
     choice, timings = autotune._search(lambda opt, reps: fake_stage_times(opt), base, 1)
-    rows, grid, absorb = choice
+    rows, grid, absorb, geom = choice
     assert rows == (32, 8, 1 << 24)
     assert grid == 2
     assert absorb == 0.1
+    assert geom == 0  # not tuned without the build's time (single meshes)
     assert set(timings) >= {f"rows={c}" for c in autotune.CANDIDATES}
     opt = autotune.options_for(choice)
     assert tuple(opt.small_rows) == rows and opt.scan_grid == 2 and abs(opt.absorb_cells - 0.1) < 1e-7
+    choice, timings = autotune._search(lambda opt, reps: fake_stage_times(opt), base, 1, build=True)
+    assert choice[:3] == (rows, grid, absorb) and choice[3] == 256
+    assert set(timings) >= {f"geom={g}" for g in autotune.GEOM_CANDIDATES}
+    assert autotune.options_for(choice).geom_blocks == 256
 
 
 def test_cache_round_trip(tmp_path, monkeypatch):
     path = tmp_path / "tune.json"
     monkeypatch.setenv("CSC_AUTOTUNE_CACHE", str(path))
     assert autotune.load("sig") is None
-    autotune.save("sig", ((32, 8, 16), 3, 0.02), {"grid=3": 1.0})
-    assert autotune.load("sig") == ((32, 8, 16), 3, 0.02)
+    autotune.save("sig", ((32, 8, 16), 3, 0.02, 256), {"grid=3": 1.0})
+    assert autotune.load("sig") == ((32, 8, 16), 3, 0.02, 256)
     rec = json.loads(path.read_text())
     assert rec["sig"]["ms"] == {"grid=3": 1.0}
     path.write_text("not json")

@@ -839,6 +839,13 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   // the corner table is sorted and the vertices classified here; the edge pass
   // waits for the records, the tables and the numbering.
   CK(hipEventRecord(F->ev_fork, s));
+  // 2. vertex -> corner table: corners sorted by vertex (stable: each vertex's
+  // corners in ascending order), then the segment starts
+  CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, nullptr, F->vtx_corners, nh,
+                sort_bits, s));
+  k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, tv, F->vtx_off);
+  // the side branch (forked right after the inputs, issued after the sort so
+  // that the sort's launches reach the device first)
   CK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
   {
     hipStream_t s2 = F->side;
@@ -861,11 +868,6 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                               F->brick_base, n_meshes, F->first_slot, F->d_stats, tb);
     CK(hipEventRecord(F->ev_join, s2));
   }
-  // 2. vertex -> corner table: corners sorted by vertex (stable: each vertex's
-  // corners in ascending order), then the segment starts
-  CK(sort_pairs(F->t_sort, F->t_sort_bytes, (const uint32_t*)T, (uint32_t*)F->t_b, nullptr, F->vtx_corners, nh,
-                sort_bits, s));
-  k_offsets<<<grid_1d(nh, B), B, 0, s>>>((const uint32_t*)F->t_b, nh, tv, F->vtx_off);
   // 3. per vertex: twins, pseudonormal, class, cone; then edge numbering
   const float absorb = o.absorb_cells > 0.f ? o.absorb_cells : 0.f;
   k_vertex<<<grid_1d(tv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, T, tv, F->vtx_off, F->vtx_corners, o.ruff_mode,

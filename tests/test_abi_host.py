@@ -103,6 +103,8 @@ def test_null_handle_calls():
     assert L.csc_scan_convert_count(None, None, 0, None, None) == 1
     assert L.csc_features_info(None, None) == 1
     assert L.csc_interior_fill(None, None, None) == 1
+    assert L.csc_features_order_faces(None, 1, None) == 1
+    assert L.csc_features_order_faces(None, 0, None) == 1
     n = C.c_int64()
     assert L.csc_weld_soup(None, 1, None, None, C.byref(n), None) == 1
     assert L.csc_weld_soup(C.c_void_p(0x1000), 0, C.c_void_p(0x1000), C.c_void_p(0x1000), C.byref(n), None) == 1

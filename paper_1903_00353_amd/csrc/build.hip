@@ -14,6 +14,7 @@
 
 #include "geometry.h"
 #include "internal.h"
+#include "wave.h"
 
 namespace csc {
 
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
                                                       const int32_t* __restrict__ vc, int ruff_mode, int saddle_mode,
                                                       int force_both, const int32_t* __restrict__ vert_mesh,
                                                       const MeshDesc* __restrict__ md, float absorb, int32_t* twin,
-                                                      float4* vinfo, uint32_t* vbits, int32_t* count,
+                                                      float4* vinfo, uint32_t* vbits,
                                                       int64_t* stats) {
   __shared__ int32_t s_c[VK_MAXD][VK_THREADS], s_n[VK_MAXD][VK_THREADS], s_p[VK_MAXD][VK_THREADS];
   const int t = threadIdx.x;
@@ -230,7 +231,6 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
   if ((double)cf > cl.cos_t) cf = nextafterf(cf, -2.f);  // the stored cone contains the exact one
   vinfo[v] = make_float4((float)cl.axis.x, (float)cl.axis.y, (float)cl.axis.z, cf);
   vbits[v] = cl.bits;
-  count[v] = ((cl.bits & V_POS) ? 1 : 0) + ((cl.bits & V_NEG) ? 1 : 0);
 }
 
 // Edge records from the owned half-edges (u -> w with u < w) and, for each edge,
@@ -239,12 +239,12 @@ __global__ __launch_bounds__(VK_THREADS) void k_vertex(const float* __restrict__
 // extrude. The third corner of the owning face precedes u in that face; the
 // third corner of the twin's face precedes the twin's start. (An open or
 // non-manifold surface can own more or fewer than 3F/2 half-edges: such a build
-// is rejected, and nothing is written past ne; cls and count are zero-filled
+// is rejected, and nothing is written past ne; cls is zero-filled
 // beforehand, so edges no half-edge produced stay unclassified and empty.)
 __global__ void k_edges(const FaceRec* __restrict__ R, int64_t nh, int64_t ne,
                         const int32_t* __restrict__ twin, const int32_t* __restrict__ eid, int force_both,
                         const int32_t* __restrict__ face_mesh, const MeshDesc* __restrict__ md, float absorb,
-                        int4* edges, int32_t* face_edges, uint8_t* cls, int32_t* count, uint8_t* eslack) {
+                        int4* edges, int32_t* face_edges, uint8_t* cls, uint8_t* eslack) {
   int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (h >= nh) return;
   // this face's record: the three threads of a face read one sector together
@@ -274,7 +274,6 @@ __global__ void k_edges(const FaceRec* __restrict__ R, int64_t nh, int64_t ne,
     }
     eslack[e] = q;
     cls[e] = (uint8_t)(c | (sides << 2) | (q ? EDGE_ABSORBED : 0));
-    count[e] = __popc(sides);
   } else {
     int32_t e = t >= 0 ? eid[t] : -1;
     face_edges[h] = e < ne ? e : -1;
@@ -438,22 +437,96 @@ __global__ void k_face_slack(const int32_t* __restrict__ T, const int32_t* __res
   fabsorbed[f] = (uint8_t)bits;
 }
 
-__global__ void k_edge_queue(const uint8_t* __restrict__ cls, int64_t ne, const int32_t* __restrict__ off, int32_t* q) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= ne) return;
-  int sides = cls[e] >> 2;
-  int32_t p = off[e];
-  if (sides & 1) q[p++] = (int32_t)(e << 1);
-  if (sides & 2) q[p++] = (int32_t)((e << 1) | 1);
+// The extrusion lists in one compaction: item i (an edge or a vertex) has 0-2
+// polyhedra, bit 0 of its side mask the outward one (entry i << 1) and bit 1
+// the inward one ((i << 1) | 1); the entries follow item order. Pass 1 counts
+// the polyhedra of each tile of QTILE items; pass 2 gives every tile its offset
+// (the sum of the tile counts before it, added up by the block itself when the
+// tiles are few, else scanned beforehand) and writes its entries, ranked inside
+// the tile by a block scan. The side masks come straight from the classes, so
+// no count array and no separate queue launch are needed.
+struct VertexSides {
+  const uint32_t* bits;
+  __device__ int operator()(int64_t i) const { return (int)(bits[i] & (V_POS | V_NEG)); }
+};
+struct EdgeSides {
+  const uint8_t* cls;
+  __device__ int operator()(int64_t i) const { return (cls[i] >> 2) & 3; }
+};
+constexpr int QB = 256, QITEMS = 8, QTILE = QB * QITEMS;
+constexpr int64_t Q_SHORT_TILES = 4096;
+
+template <class S>
+__global__ __launch_bounds__(QB) void k_queue_sums(S sides, int64_t n, int32_t* sums) {
+  const int64_t base = (int64_t)blockIdx.x * QTILE;
+  int c = 0;
+  for (int i = threadIdx.x; i < QTILE; i += QB) {
+    const int64_t idx = base + i;
+    if (idx < n) c += __popc(sides(idx));
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  __shared__ int ws[QB / 64];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < QB / 64; w++) t += ws[w];
+    sums[blockIdx.x] = t;
+  }
 }
 
-__global__ void k_vertex_queue(const uint32_t* __restrict__ vbits, int64_t nv, const int32_t* __restrict__ off, int32_t* q) {
-  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  uint32_t b = vbits[v];
-  int32_t p = off[v];
-  if (b & V_POS) q[p++] = (int32_t)(v << 1);
-  if (b & V_NEG) q[p++] = (int32_t)((v << 1) | 1);
+template <class S>
+__global__ __launch_bounds__(QB) void k_queue_write(S sides, int64_t n, const int32_t* __restrict__ sums, int scanned,
+                                                    int32_t* q, int64_t* total) {
+  __shared__ int ws[QB / 64];
+  __shared__ int wx[QB / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // this tile's offset
+  int pre = 0;
+  if (!scanned)
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += QB) pre += sums[j];
+  for (int o = 32; o > 0; o >>= 1) pre += __shfl_down(pre, o, 64);
+  if (lane == 0) ws[w] = pre;
+  // this thread's QITEMS consecutive items
+  const int64_t first = (int64_t)blockIdx.x * QTILE + (int64_t)threadIdx.x * QITEMS;
+  int m[QITEMS], c = 0;
+#pragma unroll
+  for (int k = 0; k < QITEMS; k++) {
+    m[k] = first + k < n ? sides(first + k) : 0;
+    c += __popc(m[k]);
+  }
+  const int incl = wave_prefix_sum(c);
+  if (lane == 63) wx[w] = incl;
+  __syncthreads();
+  int offset = scanned ? sums[blockIdx.x] : 0, before = 0, tile = 0;
+#pragma unroll
+  for (int u = 0; u < QB / 64; u++) {
+    if (!scanned) offset += ws[u];
+    before += u < w ? wx[u] : 0;
+    tile += wx[u];
+  }
+  int p = offset + before + incl - c;
+#pragma unroll
+  for (int k = 0; k < QITEMS; k++) {
+    const int32_t id = (int32_t)(first + k);
+    if (m[k] & 1) q[p++] = id << 1;
+    if (m[k] & 2) q[p++] = (id << 1) | 1;
+  }
+  if (!scanned && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = offset + tile;
+}
+
+template <class S>
+hipError_t queue_compact(S sides, int64_t n, int32_t* q, int64_t* total, int32_t* tmp, hipStream_t s) {
+  int64_t nb = (n + QTILE - 1) / QTILE;
+  if (nb < 1) nb = 1;
+  k_queue_sums<S><<<(unsigned)nb, QB, 0, s>>>(sides, n, tmp);
+  const bool few = nb <= Q_SHORT_TILES;
+  if (!few) {
+    hipError_t e = scan_sums_inplace(tmp, nb, total, s);
+    if (e != hipSuccess) return e;
+  }
+  k_queue_write<S><<<(unsigned)nb, QB, 0, s>>>(sides, n, tmp, few ? 0 : 1, q, total);
+  return hipGetLastError();
 }
 
 // slots of the flagged bricks (index = exclusive prefix of the flags), their
@@ -564,7 +637,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 enum {
   L_MESH, L_FOFF, L_VOFF, L_BBASE, L_TRIS, L_FMESH, L_VMESH, L_VTXOFF, L_VTXC, L_FEDGES, L_EDGES, L_FREC, L_ECLS,
   L_VINFO, L_VBITS, L_EPOLY, L_VPOLY, L_BINDEX, L_BLIST, L_BMESH, L_FIRST, L_TA, L_TB, L_TC, L_TSCAN, L_BFLAG,
-  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_FABS, L_EID, L_ECNT, L_N
+  L_TSCAN2, L_STATS, L_SORT, L_FSLACK, L_ESLACK, L_FABS, L_EID, L_N
 };
 
 struct Layout {
@@ -606,7 +679,6 @@ Layout layout(int n_meshes, int64_t nv, int64_t nf, int64_t nbt, size_t sort_byt
   sz[L_ESLACK] = (size_t)(ne + 8);
   sz[L_FABS] = (size_t)(nf + 8);
   sz[L_EID] = sizeof(int32_t) * (size_t)(3 * nf + 1);
-  sz[L_ECNT] = sizeof(int32_t) * (size_t)(ne + 1);
   Layout L;
   size_t o = 0;
   for (int i = 0; i < L_N; i++) {
@@ -797,7 +869,6 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   F->eslack = (uint8_t*)(A + L.off[L_ESLACK]);
   F->fabsorbed = (uint8_t*)(A + L.off[L_FABS]);
   F->t_eid = (int32_t*)(A + L.off[L_EID]);
-  F->t_ecnt = (int32_t*)(A + L.off[L_ECNT]);
   F->built = F->synced = false;
 
 #define CK(x)                                        \
@@ -856,7 +927,7 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                                                     F->face_rec, F->brick_flag, F->d_stats);
     }
     {
-      const FillJob a = {(int32_t*)F->edges, 4 * (ne + 1), -1}, b = {F->t_ecnt, ne, 0},
+      const FillJob a = {(int32_t*)F->edges, 4 * (ne + 1), -1}, b = {nullptr, 0, 0},
                     c = {(int32_t*)F->edge_cls, (ne + 3) / 4, 0};
       k_fill3<<<grid_1d(a.n + b.n + c.n, B), B, 0, s2>>>(a, b, c);
     }
@@ -872,19 +943,16 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
   const float absorb = o.absorb_cells > 0.f ? o.absorb_cells : 0.f;
   k_vertex<<<grid_1d(tv, VK_THREADS), VK_THREADS, 0, s>>>(verts_d, T, tv, F->vtx_off, F->vtx_corners, o.ruff_mode,
                                                         o.saddle_mode, o.force_both_sides, F->vert_mesh, F->d_mesh,
-                                                        absorb, F->t_a, F->vinfo, F->vbits, F->t_c, F->d_stats);
-  CK(exclusive_scan(F->t_c, F->t_c, tv, F->t_scan, &F->d_stats[ST_NVPOLY], nullptr, s));
-  k_vertex_queue<<<grid_1d(tv, B), B, 0, s>>>(F->vbits, tv, F->t_c, F->vpoly);
+                                                        absorb, F->t_a, F->vinfo, F->vbits, F->d_stats);
+  CK(queue_compact(VertexSides{F->vbits}, tv, F->vpoly, &F->d_stats[ST_NVPOLY], F->t_scan, s));
   // edges with their classes and extrusion sides
   CK(hipStreamWaitEvent(s, F->ev_geom, 0));  // the face records, cleared edge tables and edge ids
   k_edges<<<grid_1d(nh, B), B, 0, s>>>(F->face_rec, nh, ne, F->t_a, F->t_eid, o.force_both_sides, F->face_mesh,
-                                       F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->t_ecnt,
-                                       F->eslack);
+                                       F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->eslack);
   k_face_slack<<<grid_1d(tf, B), B, 0, s>>>(T, F->face_edges, F->vbits, F->eslack, tf, ne, F->fslack,
                                             F->fabsorbed);
   // 4. edge polyhedron queue and class statistics
-  CK(exclusive_scan(F->t_ecnt, F->t_ecnt, ne, F->t_scan, &F->d_stats[ST_NEPOLY], nullptr, s));
-  k_edge_queue<<<grid_1d(ne, B), B, 0, s>>>(F->edge_cls, ne, F->t_ecnt, F->epoly);
+  CK(queue_compact(EdgeSides{F->edge_cls}, ne, F->epoly, &F->d_stats[ST_NEPOLY], F->t_scan, s));
   {
     const int64_t items = (ne / 16 > tv / 4 ? ne / 16 : tv / 4) + 1;
     k_class_stats<<<grid_1d(items < 1024 * 256 ? items : 1024 * 256, 256), 256, 0, s>>>(F->edge_cls, ne, F->vbits,

@@ -80,6 +80,8 @@ __host__ __device__ inline void brick_coords(const MeshDesc& G, int64_t pos, int
 // null the sum is stored there; if total_i32 is not null, also there. tmp must
 // hold scan_tmp_ints(n) ints. Kernels only (safe inside a captured graph).
 int64_t scan_tmp_ints(int64_t n);
+// exclusive scan, in place, of nb tile sums by one block; *total_i64 gets the total
+hipError_t scan_sums_inplace(int32_t* sums, int64_t nb, int64_t* total_i64, hipStream_t s);
 hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t* total_i64,
                           int32_t* total_i32, hipStream_t s);
 
@@ -218,7 +220,6 @@ struct csc_features {
   int32_t* brick_flag = nullptr;    // [nbt + 1] brick marks of the build
   int32_t* t_scan2 = nullptr;       // scan temporaries of the side branch
   int32_t* t_eid = nullptr;         // [3nf + 1] edge id of each owned half-edge (prefix sum, side branch)
-  int32_t* t_ecnt = nullptr;        // [ne + 1] polyhedra per edge, then their queue offsets
   uint8_t* fslack = nullptr;        // [nf] side slack of the face prism: the largest code of its absorbed
                                     // edges and vertices (1/1024 cells)
   uint8_t* eslack = nullptr;        // [ne] slack code of each absorbed edge (0: not absorbed)

@@ -152,6 +152,11 @@ __global__ __launch_bounds__(SB) void k_scan_tiles_short(const int32_t* in, int3
 
 int64_t scan_tmp_ints(int64_t n) { return (n + STILE - 1) / STILE + 1; }
 
+hipError_t scan_sums_inplace(int32_t* sums, int64_t nb, int64_t* total_i64, hipStream_t s) {
+  k_scan_sums<<<1, 1024, 0, s>>>(sums, nb, total_i64, nullptr);
+  return hipGetLastError();
+}
+
 hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t* total_i64,
                           int32_t* total_i32, hipStream_t s) {
   int64_t nb = (n + STILE - 1) / STILE;

@@ -951,13 +951,10 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                                        F->d_mesh, absorb, F->edges, F->face_edges, F->edge_cls, F->eslack);
   k_face_slack<<<grid_1d(tf, B), B, 0, s>>>(T, F->face_edges, F->vbits, F->eslack, tf, ne, F->fslack,
                                             F->fabsorbed);
-  // 4. edge polyhedron queue and class statistics
+  // 4. edge polyhedron queue (the class statistics, which only the feature
+  // counts report, are taken by csc_features_sync when it reads them back)
   CK(queue_compact(EdgeSides{F->edge_cls}, ne, F->epoly, &F->d_stats[ST_NEPOLY], F->t_scan, s));
-  {
-    const int64_t items = (ne / 16 > tv / 4 ? ne / 16 : tv / 4) + 1;
-    k_class_stats<<<grid_1d(items < 1024 * 256 ? items : 1024 * 256, 256), 256, 0, s>>>(F->edge_cls, ne, F->vbits,
-                                                                                       tv, F->d_stats);
-  }
+  F->classes_counted = false;
   // 5. join the side stream
   CK(hipStreamWaitEvent(s, F->ev_join, 0));
   CK(hipGetLastError());
@@ -973,6 +970,12 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
 extern "C" int csc_features_sync(csc_features* F, void* stream) {
   if (!F || !F->built || !F->h_stats) return CSC_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
+  if (!F->classes_counted) {  // once per build: the classes stay until the next one
+    const int64_t items = (F->ne / 16 > F->nv / 4 ? F->ne / 16 : F->nv / 4) + 1;
+    k_class_stats<<<grid_1d(items < 1024 * 256 ? items : 1024 * 256, 256), 256, 0, s>>>(F->edge_cls, F->ne,
+                                                                                       F->vbits, F->nv, F->d_stats);
+    F->classes_counted = true;
+  }
   hipError_t he = hipMemcpyAsync(F->h_stats, F->d_stats, sizeof(int64_t) * ST_COUNT, hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return fail_hip(he);

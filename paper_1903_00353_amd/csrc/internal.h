@@ -229,6 +229,7 @@ struct csc_features {
 
   bool built = false;               // device work queued for the current inputs
   bool synced = false;              // counts below read back since the last build
+  bool classes_counted = false;     // the class statistics of the last build are in d_stats
   int64_t n_epoly = 0, n_vpoly = 0, n_bricks = 0;
   csc_feature_info info{};
 };

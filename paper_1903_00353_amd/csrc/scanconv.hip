@@ -1024,8 +1024,11 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-// every key of the allocated bricks (device count, capped) set to empty
-__global__ void k_init_keys(unsigned long long* keys, const int64_t* __restrict__ stats, int64_t cap) {
+// every key of the allocated bricks (device count, capped) set to empty; block 0
+// also clears the zn counters at zero
+__global__ void k_init_keys(unsigned long long* keys, const int64_t* __restrict__ stats, int64_t cap,
+                            unsigned long long* zero, int zn) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < zn) zero[threadIdx.x] = 0;
   const int64_t nb = stats[ST_NBRICKS] < cap ? stats[ST_NBRICKS] : cap;
   const int64_t n = nb * BRICK_CELLS;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1381,8 +1384,8 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
   int32_t* ov = big + 64;  // past the 256 bytes of counters
   {
     StageTimer t(TS_INIT, s);
-    k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap);
-    k_zero_u64<<<1, 64, 0, s>>>(ov_ctr, 9);  // two list counters and a group head per kind
+    // with the overflow lists' two counters and group head per kind
+    k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap, ov_ctr, 9);
   }
   // a fork that cannot be set up leaves everything on the caller's stream
   bool fork = f->n_meshes > 1 && !stage_timing_on() && f->side && !lg;
@@ -1451,7 +1454,8 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
   hipError_t e;
   {
     StageTimer t(TS_COUNT, s);
-    if (cap > 0) k_brick_count<<<PERSIST_BLOCKS, 256, 0, s>>>(keys, f->d_stats, cap, cnt);
+    static const unsigned count_blocks = resident_blocks(k_brick_count, 256);
+    if (cap > 0) k_brick_count<<<count_blocks, 256, 0, s>>>(keys, f->d_stats, cap, cnt);
     e = exclusive_scan(cnt, cnt, cap, tmp, n_band_d, cnt + cap, s);
     k_band_offsets<<<1, 64, 0, s>>>(f->first_slot, cnt, f->n_meshes, cap, boff64);
   }
@@ -1478,7 +1482,9 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
     S.cap = cap;
     S.nf = f->nf;
     S.ne = f->ne;
-    k_sign<<<PERSIST_BLOCKS, 256, 0, s>>>(S);
+    // every block resident at once (the persistent loop strides over the bricks)
+    static const unsigned sign_blocks = resident_blocks(k_sign, 256);
+    k_sign<<<sign_blocks, 256, 0, s>>>(S);
   }
   e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);

@@ -698,6 +698,17 @@ def bench_single(args):
     if not args.timed_only:
         ms_fwd, med_fwd, min_fwd = timed_steps(forward, args.steps)
         res["fwd"] = {"value": M / (ms_fwd * 1e-3), "ms_per_step": ms_fwd, "median": med_fwd, "min": min_fwd}
+        # the same fwd+bwd step through the batched entry points for one mesh, captured as one graph
+        B1 = P.Batch([(v, f)], [g], options=opts, device=dev, backward=True, graph_safe=True, face_order=False)
+        B1.capture()
+        for _ in range(args.warmup):
+            B1.replay()
+        ms_g, med_g, min_g = timed_steps(B1.replay, args.steps)
+        B1.check()
+        M1 = int(B1.band_off[-1].item())
+        res["one_mesh_batch_graph"] = {"value": M1 / (ms_g * 1e-3), "ms_per_step": ms_g, "median": med_g,
+                                       "min": min_g, "band_size": M1}
+        del B1
         res["interior_fill"] = bench_interior_fill(P, feats, ws, out, g, max(3, args.steps // 4))
         res["weld"] = bench_weld(P, verts, tris, 5)
         res["ablation_per_cell_scan"] = bench_per_cell(P, verts, tris, g, schedule, ws, out, max(3, args.steps // 4))

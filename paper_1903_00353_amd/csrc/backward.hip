@@ -113,13 +113,16 @@ constexpr int BW_FLUSH = 256;                 // flush once more slots than this
 constexpr int BW_PROBES = 16;                 // a vertex not placed within this many slots goes to HBM
 constexpr int BW_BLOCKS = 2048;               // persistent grid: 8 resident blocks of 256 per CU
 // LDS adds of floats are slow on this chip where 64-bit integer adds are not,
-// so the table sums in fixed point: c * 2^fx goes in as an integer when that is
-// exact (magnitude at least 2^23, so the float is integer-valued) and below 2^42
-// (no overflow), otherwise c goes straight to the gradient
+// so the table sums in fixed point: c * 2^fx, rounded to an integer, when its
+// magnitude is below 2^42 (no overflow; the rounding is at most 2^-41 of the
+// block's largest term), otherwise (a term far larger than the block's first
+// chunk's, or not finite) c goes straight to the gradient. Terms that round to
+// zero add nothing.
 __device__ inline void add_fixed(unsigned long long* slot, float c, int fx, float* direct) {
   const float v = ldexpf(c, fx);
-  if (fabsf(v) >= 8388608.f && fabsf(v) < 4398046511104.f) {  // 2^23 <= |v| < 2^42
-    atomicAdd(slot, (unsigned long long)(long long)v);
+  if (fabsf(v) < 4398046511104.f) {  // |v| < 2^42
+    const long long iv = (long long)rintf(v);
+    if (iv != 0) atomicAdd(slot, (unsigned long long)iv);
   } else if (c != 0.f) {
     atomicAdd(direct, c);
   }
@@ -171,12 +174,12 @@ __global__ __launch_bounds__(BW_THREADS, BW_WAVES_PER_SIMD) void k_backward(BwdA
   // Fixed-point scale of this block: 2^fx, with fx such that the largest finite
   // |dL/dSDF| of the block's first chunk scales to just below 2^40. Every term is
   // bounded by its cell's |dL/dSDF| (|g| = 1, 0 <= w <= 1). A scaled term of
-  // magnitude in [2^23, 2^42) is an integer-valued float, converted exactly, and
-  // summed exactly in 64-bit integers (a slot gets fewer than 2^20 terms between
-  // flushes: no overflow), in any order. Terms outside that window (tiny, much
-  // larger than the first chunk's, or non-finite) are added to the gradient as
-  // floats: the scale decides which terms are summed exactly and how fast, not
-  // whether the sum is right.
+  // magnitude below 2^42 is rounded to an integer (at most 2^-41 of the largest
+  // term; exact from 2^23 up, where the float is integer-valued) and summed
+  // exactly in 64-bit integers (a slot gets fewer than 2^20 terms between
+  // flushes: no overflow), in any order. Larger terms (much larger than the first
+  // chunk's, or non-finite) are added to the gradient as floats: the scale decides
+  // how fast the sum goes, not whether it is right.
   float gmax = 0.f;
   if (c0 + threadIdx.x < c1)
     gmax = fmax_finite(0.f, P.gsdf ? P.gsdf[c0 + threadIdx.x] : 2.f * P.sdf[c0 + threadIdx.x]);

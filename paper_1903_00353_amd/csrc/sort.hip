@@ -4,7 +4,11 @@
 // triangle corners by vertex (stable, so each vertex's corners come out in
 // ascending order) and orders soup corners by coordinate.
 //
-// Each pass runs three launches over tiles of RsCfg::TILE pairs:
+// Each pass runs three launches over tiles of RsCfg::TILE pairs (16 pairs per
+// thread: 4096 pairs in blocks of 256 threads, or 8192 in blocks of 512 once
+// the input fills at least 1536 such tiles, three for each block slot of the
+// device at two 75 KB blocks per CU; below that the longer tiles leave slots
+// idle and the shorter ones win):
 //  * k_rs_hist: the digit histogram of every tile, stored digit-major
 //    (hist[d * ntiles + tile]), counted with LDS integer atomics;
 //  * an exclusive scan of that array: the output offset of (digit, tile);
@@ -22,36 +26,37 @@
 
 namespace csc {
 
-constexpr int RS_THREADS = 256;
-constexpr int RS_WAVES = RS_THREADS / 64;
-
-// digit width and tile length: 8-bit digits in tiles of 4096 pairs
-template <int RB>
+// digit width RB and block size TH: the tile is 16 pairs per thread
+template <int RB, int TH>
 struct RsCfg {
   static constexpr int BINS = 1 << RB;
+  static constexpr int THREADS = TH;
+  static constexpr int WAVES = TH / 64;
   static constexpr int ROUNDS = 16;
-  static constexpr int TILE = RS_THREADS * ROUNDS;
-  static constexpr int PER = BINS / RS_THREADS;  // digits per thread in the per-tile tables
-  static_assert(BINS % RS_THREADS == 0, "whole digits per thread");
+  static constexpr int TILE = TH * ROUNDS;
+  // digits per thread in the per-tile tables (threads past the digits hold none)
+  static constexpr int PER = BINS >= TH ? BINS / TH : 1;
+  static_assert(BINS % TH == 0 || TH % BINS == 0, "whole digits per thread");
 };
 
-template <int RB>
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
-                                                        int64_t ntiles, int32_t* hist) {
-  using C = RsCfg<RB>;
+template <int RB, int TH>
+__global__ __launch_bounds__(TH) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                int64_t ntiles, int32_t* hist) {
+  using C = RsCfg<RB, TH>;
   __shared__ int s_h[C::BINS];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int b = t; b < C::BINS; b += RS_THREADS) s_h[b] = 0;
+  for (int b = t; b < C::BINS; b += TH) s_h[b] = 0;
   __syncthreads();
   const int64_t base = blockIdx.x * (int64_t)C::TILE + w * (C::ROUNDS * 64) + lane;
 #pragma unroll 8
   for (int r = 0; r < C::ROUNDS; r++)
     if (base + r * 64 < n) atomicAdd(&s_h[(keys[base + r * 64] >> shift) & (C::BINS - 1)], 1);
   __syncthreads();
-  for (int b = t; b < C::BINS; b += RS_THREADS) hist[(int64_t)b * ntiles + blockIdx.x] = s_h[b];
+  for (int b = t; b < C::BINS; b += TH) hist[(int64_t)b * ntiles + blockIdx.x] = s_h[b];
 }
 
-// exclusive scan of one value per thread across the block
+// exclusive scan of one value per thread across the block of WAVES wavefronts
+template <int WAVES>
 __device__ inline int rs_block_excl(int v, int* s_w) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int inc = v;
@@ -64,26 +69,25 @@ __device__ inline int rs_block_excl(int v, int* s_w) {
   __syncthreads();
   int before = 0;
 #pragma unroll
-  for (int u = 0; u < RS_WAVES; u++) before += u < w ? s_w[u] : 0;
+  for (int u = 0; u < WAVES; u++) before += u < w ? s_w[u] : 0;
   return before + inc - v;
 }
 
 // vin may be null: the values are then the input positions
-template <int RB>
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
-                                                           const int32_t* __restrict__ vin, uint32_t* kout,
-                                                           int32_t* vout, int64_t n, int shift, int64_t ntiles,
-                                                           const int32_t* __restrict__ off) {
-  using C = RsCfg<RB>;
-  __shared__ int s_cnt[RS_WAVES][C::BINS];  // running, then starting, tile position of each digit per wave
+template <int RB, int TH>
+__global__ __launch_bounds__(TH) void k_rs_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                   uint32_t* kout, int32_t* vout, int64_t n, int shift,
+                                                   int64_t ntiles, const int32_t* __restrict__ off) {
+  using C = RsCfg<RB, TH>;
+  __shared__ int s_cnt[C::WAVES][C::BINS];  // running, then starting, tile position of each digit per wave
   __shared__ int s_delta[C::BINS];          // output offset of each digit's run minus its tile start
-  __shared__ int s_w[RS_WAVES];
+  __shared__ int s_w[C::WAVES];
   __shared__ uint32_t s_k[C::TILE];
   __shared__ int32_t s_v[C::TILE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int b = t; b < C::BINS; b += RS_THREADS) {
+  for (int b = t; b < C::BINS; b += TH) {
 #pragma unroll
-    for (int u = 0; u < RS_WAVES; u++) s_cnt[u][b] = 0;
+    for (int u = 0; u < C::WAVES; u++) s_cnt[u][b] = 0;
   }
   __syncthreads();
   const int64_t tile0 = blockIdx.x * (int64_t)C::TILE;
@@ -120,21 +124,23 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
   {
     // digits t * PER .. t * PER + PER - 1: their starts in the tile (digit
     // order), each wave's start, and where their runs go
+    const bool holds = t * C::PER < C::BINS;
     int tot[C::PER], sum = 0;
 #pragma unroll
     for (int q = 0; q < C::PER; q++) {
       tot[q] = 0;
 #pragma unroll
-      for (int u = 0; u < RS_WAVES; u++) tot[q] += s_cnt[u][t * C::PER + q];
+      for (int u = 0; u < C::WAVES; u++) tot[q] += holds ? s_cnt[u][t * C::PER + q] : 0;
       sum += tot[q];
     }
-    int acc = rs_block_excl(sum, s_w);
+    int acc = rs_block_excl<C::WAVES>(sum, s_w);
 #pragma unroll
     for (int q = 0; q < C::PER; q++) {
       const int d = t * C::PER + q;
+      if (!holds) break;
       s_delta[d] = off[(int64_t)d * ntiles + blockIdx.x] - acc;
 #pragma unroll
-      for (int u = 0; u < RS_WAVES; u++) {
+      for (int u = 0; u < C::WAVES; u++) {
         const int c = s_cnt[u][d];
         s_cnt[u][d] = acc;
         acc += c;
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
   __syncthreads();
   // the tile in digit order: position j of digit d goes to that digit's run
   const int tn = (int)(n - tile0 < C::TILE ? n - tile0 : C::TILE);
-  for (int j = t; j < tn; j += RS_THREADS) {
+  for (int j = t; j < tn; j += TH) {
     const uint32_t key = s_k[j];
     const int64_t p = (int64_t)s_delta[(key >> shift) & (C::BINS - 1)] + j;
     kout[p] = key;
@@ -171,7 +177,14 @@ void rs_plan(int bits, int& passes, int& rb) {
   passes = (bits + RS_RB - 1) / RS_RB;
 }
 
-int64_t rs_tile(int) { return RsCfg<RS_RB>::TILE; }
+using RsNarrow = RsCfg<RS_RB, 256>;
+using RsWide = RsCfg<RS_RB, 512>;
+constexpr int64_t RS_WIDE_MIN_TILES = 1536;
+
+// the tile length used for n pairs
+int64_t rs_tile(int64_t n) {
+  return n >= RS_WIDE_MIN_TILES * RsWide::TILE ? RsWide::TILE : RsNarrow::TILE;
+}
 }  // namespace
 
 // temporary storage: the other key and value buffers, the digit-major tile
@@ -180,7 +193,7 @@ size_t sort_pairs_tmp_bytes(int64_t n, int bits) {
   if (n < 0 || bits <= 0 || bits > 32) return 0;
   int passes, rb;
   rs_plan(bits, passes, rb);
-  const int64_t h = ((int64_t)1 << rb) * ((n + rs_tile(rb) - 1) / rs_tile(rb));
+  const int64_t h = ((int64_t)1 << rb) * ((n + rs_tile(n) - 1) / rs_tile(n));
   return al(sizeof(uint32_t) * (size_t)n) + al(sizeof(int32_t) * (size_t)n) + al(sizeof(int32_t) * (size_t)h) +
          al(sizeof(int32_t) * (size_t)scan_tmp_ints(h)) + 256;
 }
@@ -195,7 +208,8 @@ hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint
     return hipErrorInvalidValue;
   int passes, rb;
   rs_plan(bits, passes, rb);
-  const int64_t ntiles = (n + rs_tile(rb) - 1) / rs_tile(rb), h = ((int64_t)1 << rb) * ntiles;
+  const bool wide = rs_tile(n) == RsWide::TILE;
+  const int64_t ntiles = (n + rs_tile(n) - 1) / rs_tile(n), h = ((int64_t)1 << rb) * ntiles;
   char* p = (char*)tmp;
   uint32_t* kalt = (uint32_t*)p;
   p += al(sizeof(uint32_t) * (size_t)n);
@@ -214,10 +228,15 @@ hipError_t sort_pairs(void* tmp, size_t tmp_bytes, const uint32_t* keys_in, uint
     int32_t* vd = to_out ? vals_out : valt;
     const int shift = rb * q;
     const unsigned g = (unsigned)ntiles;
-    k_rs_hist<RS_RB><<<g, RS_THREADS, 0, s>>>(ks, n, shift, ntiles, hist);
+    if (wide) k_rs_hist<RS_RB, RsWide::THREADS><<<g, RsWide::THREADS, 0, s>>>(ks, n, shift, ntiles, hist);
+    else k_rs_hist<RS_RB, RsNarrow::THREADS><<<g, RsNarrow::THREADS, 0, s>>>(ks, n, shift, ntiles, hist);
     hipError_t e = exclusive_scan(hist, hist, h, scan_tmp, nullptr, nullptr, s);
     if (e != hipSuccess) return e;
-    k_rs_scatter<RS_RB><<<g, RS_THREADS, 0, s>>>(ks, vs, kd, vd, n, shift, ntiles, hist);
+    if (wide)
+      k_rs_scatter<RS_RB, RsWide::THREADS><<<g, RsWide::THREADS, 0, s>>>(ks, vs, kd, vd, n, shift, ntiles, hist);
+    else
+      k_rs_scatter<RS_RB, RsNarrow::THREADS><<<g, RsNarrow::THREADS, 0, s>>>(ks, vs, kd, vd, n, shift, ntiles,
+                                                                             hist);
     ks = kd;
     vs = vd;
   }

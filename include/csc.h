@@ -215,7 +215,9 @@ int csc_scan_convert_workspace_for(const csc_features* f, int64_t n_bricks, size
  * workspace_d: ws_bytes >= csc_scan_convert_workspace() bytes of device memory.
  * sdf_d (float32), feat_d (int32), cell_d (int32 linear index): arrays of
  * max_band_cells entries; the first *n_band_d entries are written, ordered by
- * brick and within a brick by linear cell index (deterministic).
+ * brick and within a brick in Morton order of the cell's position in its 8^3
+ * brick (the bits of its in-brick x, y, z interleaved, x lowest): a fixed,
+ * deterministic order.
  * n_band_d: device int64 scalar receiving the band size.
  * dense_d: NULL, or float32 [n[2]][n[1]][n[0]] receiving the dense field with
  * +infinity off the band (Alg. 1 initial value).

@@ -1150,9 +1150,10 @@ __device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned 
 
 // Sign of every band cell (Section 4.1.3, Eq. 8) and the compact band list with
 // each mesh's own feature ids and cell indices. One wavefront per brick: lane l
-// holds the cells of in-brick position l + 64 r for r < BRICK_ROUNDS (x fastest),
-// loaded at once; the output position is the brick's offset plus the rank among
-// the set cells in (r, lane) order, which is the in-brick position order. Most keys carry their sign from the scan; the rest
+// holds the cells of in-brick position l + 64 r for r < BRICK_ROUNDS (Morton
+// order, brick_local), loaded at once; the output position is the brick's
+// offset plus the rank among the set cells in (r, lane) order, which is the
+// in-brick position order. Most keys carry their sign from the scan; the rest
 // (SIGN_OPEN) are finished after the brick's decided cells.
 __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
   const int lane = threadIdx.x & 63;
@@ -1167,9 +1168,9 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
     int bx, by, bz;
     brick_coords(G, P.brick_list[slot], bx, by, bz);
     // cell of round r: in-brick position lane + 64 r
-    auto cell_i = [&](int r) { return bx * BRICK + ((lane + 64 * r) & (BRICK - 1)); };
-    auto cell_j = [&](int r) { return by * BRICK + (((lane + 64 * r) >> BRICK_SHIFT) & (BRICK - 1)); };
-    auto cell_k = [&](int r) { return bz * BRICK + ((lane + 64 * r) >> (2 * BRICK_SHIFT)); };
+    auto cell_i = [&](int r) { int i, j, k; brick_cell(lane + 64 * r, i, j, k); return bx * BRICK + i; };
+    auto cell_j = [&](int r) { int i, j, k; brick_cell(lane + 64 * r, i, j, k); return by * BRICK + j; };
+    auto cell_k = [&](int r) { int i, j, k; brick_cell(lane + 64 * r, i, j, k); return bz * BRICK + k; };
     const int64_t ob = P.boff[slot];
     int before = 0;
     unsigned open_bits = 0;

@@ -102,6 +102,13 @@ typedef struct csc_options {
                                compute units of its own (a batch of many small meshes gains, one large
                                mesh loses). Only the speed depends on it (the binding's autotuner picks
                                it for a batch). */
+  int32_t keep_store_empty; /* 1: the caller keeps the key store of the scan workspace empty between
+                               scans: the workspace is filled with 0xFF bytes once, before its first
+                               scan, and used for nothing else; every scan then skips filling the
+                               store (the largest write of the pass) and its sign pass returns each
+                               key it read to empty. After an error return, fill it again. 0
+                               (default): every scan fills the store itself. Only the speed depends
+                               on it. */
 } csc_options;
 
 typedef struct csc_features csc_features; /* opaque, library-owned, device resident */

@@ -45,7 +45,7 @@ class csc_options(C.Structure):
     _fields_ = [("eps_rel", C.c_float), ("ruff_mode", C.c_int32), ("saddle_mode", C.c_int32),
                 ("force_both_sides", C.c_int32), ("small_rows", C.c_int32 * 3),
                 ("scan_mode", C.c_int32), ("absorb_cells", C.c_float), ("scan_grid", C.c_int32),
-                ("geom_blocks", C.c_int32)]
+                ("geom_blocks", C.c_int32), ("keep_store_empty", C.c_int32)]
 
 
 class csc_feature_info(C.Structure):
@@ -166,10 +166,11 @@ def make_grid(grid) -> csc_grid:
 
 
 def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0, small_rows=(0, 0, 0),
-                 scan_mode=0, absorb_cells=0.0, scan_grid=0, geom_blocks=0) -> csc_options:
+                 scan_mode=0, absorb_cells=0.0, scan_grid=0, geom_blocks=0, keep_store_empty=0) -> csc_options:
     """absorb_cells: 0 the library's default, negative to give every non-flat
-    feature its own polyhedron; scan_grid, geom_blocks: 0 the default schedule
-    (see csc.h)."""
+    feature its own polyhedron; scan_grid, geom_blocks: 0 the default schedule;
+    keep_store_empty: 1 only for a scan workspace filled with 0xFF bytes once
+    and used for nothing else (see csc.h)."""
     o = csc_options(float(eps_rel), int(ruff_mode), int(saddle_mode), int(force_both_sides))
     for k in range(3):
         o.small_rows[k] = int(small_rows[k])
@@ -177,6 +178,7 @@ def make_options(eps_rel=1e-3, ruff_mode=0, saddle_mode=0, force_both_sides=0, s
     o.absorb_cells = float(absorb_cells)
     o.scan_grid = int(scan_grid)
     o.geom_blocks = int(geom_blocks)
+    o.keep_store_empty = int(keep_store_empty)
     return o
 
 
@@ -450,7 +452,11 @@ class Batch:
 
     With ``face_order`` the face pass takes the faces in the spatial order of
     that first build (``csc_features_order_faces``), kept by every later step: a
-    schedule only, the results are the same bit for bit."""
+    schedule only, the results are the same bit for bit.
+
+    The batch's workspace is filled with empty keys once and its builds set
+    ``keep_store_empty`` (whatever ``options`` says), so that no scan fills the
+    key store itself; scan it with nothing but this workspace."""
 
     def __init__(self, meshes, grids, options=None, device="cuda", backward=True, graph_safe=True, headroom=1.25,
                  face_order=True):
@@ -461,7 +467,7 @@ class Batch:
         self.verts = torch.cat([torch.as_tensor(m[0], dtype=torch.float32).reshape(-1, 3) for m in meshes]).to(device)
         self.tris = torch.cat([torch.as_tensor(m[1], dtype=torch.int32).reshape(-1, 3) for m in meshes]).to(device)
         self.verts, self.tris = self.verts.contiguous(), self.tris.contiguous()
-        self.options = options
+        self._options = options
         self.flags = CSC_BUILD_GRAPH_SAFE if graph_safe else 0
         self.f = csc_build_features_batched(self.verts, self.tris, self.nv, self.nf, self.grids, options,
                                             flags=self.flags)
@@ -469,7 +475,8 @@ class Batch:
             csc_features_order_faces(self.f)
         nb = int(self.f.info()["n_bricks"])
         nbytes, mx = csc_scan_convert_workspace_for(self.f, int(nb * float(headroom)) + 1)
-        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        # every key empty (all ones) before the first scan; each scan's sign pass leaves it so
+        self.workspace = torch.full((max(nbytes, 1),), 255, dtype=torch.uint8, device=device)
         self.out = (torch.empty(max(mx, 1), dtype=torch.float32, device=device),
                     torch.empty(max(mx, 1), dtype=torch.int32, device=device),
                     torch.empty(max(mx, 1), dtype=torch.int32, device=device))
@@ -477,6 +484,21 @@ class Batch:
         self.backward = backward
         self.grad_verts = torch.zeros_like(self.verts)
         self.graph = None
+
+    @property
+    def options(self):
+        """The build options (the given ones, or the defaults) with keep_store_empty set."""
+        o = csc_options()
+        if self._options is not None:
+            C.memmove(C.byref(o), C.byref(self._options), C.sizeof(csc_options))
+        else:
+            o = make_options()
+        o.keep_store_empty = 1
+        return o
+
+    @options.setter
+    def options(self, value):
+        self._options = value
 
     def step(self):
         """Build, scan conversion and (if enabled) the adjoint of sum SDF^2 (its

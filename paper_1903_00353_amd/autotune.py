@@ -199,4 +199,4 @@ def _with(opt, rows=None, grid=None, absorb=None, geom=None):
                           tuple(opt.small_rows) if rows is None else rows, opt.scan_mode,
                           opt.absorb_cells if absorb is None else absorb,
                           opt.scan_grid if grid is None else grid,
-                          opt.geom_blocks if geom is None else geom)
+                          opt.geom_blocks if geom is None else geom, opt.keep_store_empty)

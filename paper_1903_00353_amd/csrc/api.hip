@@ -86,7 +86,7 @@ extern "C" int csc_classify_edge(const float a[3], const float b[3], const float
 extern "C" int csc_classify_vertex(const float v[3], const float* ring, int32_t n_faces, const csc_options* opt,
                                    double axis[3], double* cos_t) {
   if (!v || !ring || n_faces <= 0 || !axis || !cos_t) return -CSC_INVALID_ARG;
-  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}, 0, 0.f, 0, 0};
+  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}, 0, 0.f, 0, 0, 0};
   if (opt) o = *opt;
   d3 pv = mkd(v[0], v[1], v[2]);
   VertexAccum acc;

@@ -714,9 +714,9 @@ int build_impl(const float* verts_d, const int32_t* tris_d, const int64_t* nv, c
                const csc_grid* grids, int32_t n_meshes, const csc_options* opt, int32_t flags, void* stream,
                csc_features** out) {
   if (!verts_d || !tris_d || !nv || !nf || !grids || !out || n_meshes <= 0) return CSC_INVALID_ARG;
-  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}, 0, 0.f, 0, 0};
+  csc_options o = {1e-3f, 0, 0, 0, {0, 0, 0}, 0, 0.f, 0, 0, 0};
   if (opt) o = *opt;
-  if (o.scan_grid < 0 || o.scan_grid > 3 || o.geom_blocks < 0) return CSC_INVALID_ARG;
+  if (o.scan_grid < 0 || o.scan_grid > 3 || o.geom_blocks < 0 || (o.keep_store_empty & ~1)) return CSC_INVALID_ARG;
   if (o.scan_grid == 0) o.scan_grid = 2;  // default: persistent grid striding over the groups
   if (!(o.absorb_cells <= 0.24f) || o.absorb_cells != o.absorb_cells) return CSC_INVALID_ARG;
   // 0: the default; negative: every non-flat feature keeps its own polyhedron

@@ -1080,7 +1080,7 @@ struct SignArgs {
   const int32_t* brick_list;
   const int32_t* brick_mesh;
   const MeshDesc* md;
-  const unsigned long long* keys;
+  unsigned long long* keys;  // read; with RESET, every set key is returned to empty
   const int32_t* boff;
   const int64_t* stats;
   float* sdf;
@@ -1154,13 +1154,17 @@ __device__ inline void sign_open(const SignArgs& P, const MeshDesc& G, unsigned 
 // order, brick_local), loaded at once; the output position is the brick's
 // offset plus the rank among the set cells in (r, lane) order, which is the
 // in-brick position order. Most keys carry their sign from the scan; the rest
-// (SIGN_OPEN) are finished after the brick's decided cells.
+// (SIGN_OPEN) are finished after the brick's decided cells. With RESET each set
+// key is stored back as empty once its cell is written, so that the store is
+// empty for the next scan without a pass of its own (its stores take the pass
+// from 70 to 74 registers, hence a kernel of its own).
+template <bool RESET>
 __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
   const int lane = threadIdx.x & 63;
   const int64_t nb = P.stats[ST_NBRICKS] < P.cap ? P.stats[ST_NBRICKS] : P.cap;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t slot = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); slot < nb; slot += nw) {
-    const unsigned long long* kp = P.keys + slot * BRICK_CELLS + lane;
+    unsigned long long* kp = P.keys + slot * BRICK_CELLS + lane;
     unsigned long long key[BRICK_ROUNDS];
 #pragma unroll
     for (int r = 0; r < BRICK_ROUNDS; r++) key[r] = kp[64 * r];
@@ -1192,6 +1196,7 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
           const float d = __uint_as_float((uint32_t)(key[r] >> 32));
           put_cell(P, G, ob + pos, code == SIGN_NEG ? -d : d, local_id(P, G, (int32_t)(lo & ID_MASK)), cell_i(r),
                    cell_j(r), cell_k(r));
+          if (RESET) kp[64 * r] = EMPTY_KEY;
         }
       }
       before += __popcll(msk);
@@ -1201,6 +1206,7 @@ __global__ __launch_bounds__(256) void k_sign(SignArgs P) {
       open_bits &= open_bits - 1;
       const uint32_t pos = r < 7 ? (uint32_t)(open_pos >> (9 * r)) & 511u : open_pos7;
       sign_open(P, G, kp[64 * r], cell_i(r), cell_j(r), cell_k(r), ob + pos);
+      if (RESET) kp[64 * r] = EMPTY_KEY;
     }
   }
 }
@@ -1379,14 +1385,17 @@ void launch_kind(ScanArgs A, int stage, int stage_big, hipStream_t s, const Atom
 // contention (1024^3 sphere: 3.43 -> 3.47 ms), so it stays on one stream.
 // With stage timing on, the kinds also run one after another, so that each
 // timed stage is one kernel running alone.
+// fill_store: every key of the allocated bricks set to empty first; else the
+// caller keeps the store empty between scans (csc_options.keep_store_empty).
 void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, unsigned long long* counters,
-               int32_t* big, hipStream_t s, const AtomicLog* lg = nullptr) {
+               int32_t* big, hipStream_t s, bool fill_store, const AtomicLog* lg = nullptr) {
   unsigned long long* ov_ctr = (unsigned long long*)big;
   int32_t* ov = big + 64;  // past the 256 bytes of counters
   {
     StageTimer t(TS_INIT, s);
     // with the overflow lists' two counters and group head per kind
-    k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap, ov_ctr, 9);
+    if (fill_store) k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap, ov_ctr, 9);
+    else k_init_keys<<<1, 64, 0, s>>>(keys, f->d_stats, 0, ov_ctr, 9);
   }
   // a fork that cannot be set up leaves everything on the caller's stream
   bool fork = f->n_meshes > 1 && !stage_timing_on() && f->side && !lg;
@@ -1436,6 +1445,12 @@ void run_scans(const csc_features* f, unsigned long long* keys, int64_t cap, uns
     (void)hipStreamSynchronize(s2);  // no join on the device: finish the side branch from the host
 }
 
+// after scans with no sign pass: the store left empty again for a caller that
+// keeps it so
+void empty_store_again(const csc_features* f, unsigned long long* keys, int64_t cap, hipStream_t s) {
+  if (f->opt.keep_store_empty) k_init_keys<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(keys, f->d_stats, cap, nullptr, 0);
+}
+
 int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes, float* sdf_d, int32_t* feat_d,
                       int32_t* cell_d, int64_t* n_band_d, int64_t* band_off_d, float* dense_d, hipStream_t s) {
   WsLayout L;
@@ -1451,7 +1466,7 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
     int64_t nd = (int64_t)G.n[0] * G.n[1] * G.n[2];
     k_fill_f32<<<PERSIST_BLOCKS * 4, 256, 0, s>>>(dense_d, nd, __builtin_inff());
   }
-  run_scans(f, keys, cap, nullptr, (int32_t*)(W + L.big), s);
+  run_scans(f, keys, cap, nullptr, (int32_t*)(W + L.big), s, !f->opt.keep_store_empty);
   hipError_t e;
   {
     StageTimer t(TS_COUNT, s);
@@ -1484,8 +1499,13 @@ int scan_convert_impl(const csc_features* f, void* workspace_d, size_t ws_bytes,
     S.nf = f->nf;
     S.ne = f->ne;
     // every block resident at once (the persistent loop strides over the bricks)
-    static const unsigned sign_blocks = resident_blocks(k_sign, 256);
-    k_sign<<<sign_blocks, 256, 0, s>>>(S);
+    if (f->opt.keep_store_empty) {
+      static const unsigned sign_blocks = resident_blocks(k_sign<true>, 256);
+      k_sign<true><<<sign_blocks, 256, 0, s>>>(S);
+    } else {
+      static const unsigned sign_blocks = resident_blocks(k_sign<false>, 256);
+      k_sign<false><<<sign_blocks, 256, 0, s>>>(S);
+    }
   }
   e = hipGetLastError();
   return e == hipSuccess ? CSC_OK : fail_hip(e);
@@ -1534,7 +1554,8 @@ extern "C" int csc_scan_convert_count(const csc_features* f, void* workspace_d, 
   char* W = (char*)workspace_d;
   unsigned long long* ctr = (unsigned long long*)(W + L.ctr);
   k_zero_u64<<<1, 64, 0, s>>>(ctr, 6);
-  run_scans(f, (unsigned long long*)(W + L.keys), L.cap, ctr, (int32_t*)(W + L.big), s);
+  run_scans(f, (unsigned long long*)(W + L.keys), L.cap, ctr, (int32_t*)(W + L.big), s, true);
+  empty_store_again(f, (unsigned long long*)(W + L.keys), L.cap, s);
   unsigned long long h[6];
   hipError_t e = hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1561,7 +1582,8 @@ extern "C" int csc_scan_record_atomics(const csc_features* f, void* workspace_d,
   lg.rounds = (unsigned*)(ctr + 7);
   lg.cap = max_rounds;
   lg.select = launch;
-  run_scans(f, (unsigned long long*)(W + L.keys), L.cap, nullptr, (int32_t*)(W + L.big), s, &lg);
+  run_scans(f, (unsigned long long*)(W + L.keys), L.cap, nullptr, (int32_t*)(W + L.big), s, true, &lg);
+  empty_store_again(f, (unsigned long long*)(W + L.keys), L.cap, s);
   unsigned h = 0;
   hipError_t e = hipMemcpyAsync(&h, ctr + 7, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

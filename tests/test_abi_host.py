@@ -47,7 +47,7 @@ def _grid(n=(8, 8, 8), h=0.125, band=2.0, origin=(0.0, 0.0, 0.0)):
 @pytest.mark.parametrize("case", ["null", "nv0", "nf0", "odd_faces", "grid_n", "grid_h", "band", "origin_nan",
                                   "too_many_cells", "long_axis", "bad_option",
                                   "bad_scan_mode", "absorb_too_wide", "absorb_nan", "bad_scan_grid",
-                                  "bad_geom_blocks"])
+                                  "bad_geom_blocks", "bad_keep_store_empty"])
 def test_host_argument_checks(case):
     """Checked on the host before any device call: these never need a GPU."""
     L = P.lib()
@@ -88,6 +88,8 @@ def test_host_argument_checks(case):
         opt.scan_grid = 4
     elif case == "bad_geom_blocks":
         opt.geom_blocks = -1
+    elif case == "bad_keep_store_empty":
+        opt.keep_store_empty = 2
     code = L.csc_build_features(v, nv, t, nf, C.byref(g), C.byref(opt), None, C.byref(out))
     expect = {"odd_faces": 2, "too_many_cells": 5, "long_axis": 5}.get(case, 1)
     assert code == expect

@@ -246,3 +246,37 @@ def test_face_order_does_not_change_results():
         torch.cuda.synchronize()
         got = (band.cell.cpu().numpy(), band.sdf.cpu().numpy(), band.feat.cpu().numpy())
         assert all(np.array_equal(x, y) for x, y in zip(ref[:3], got)), enable
+
+
+def test_kept_empty_store_across_steps_and_diagnostics():
+    """A batch keeps its key store empty between scans (keep_store_empty: the sign
+    pass empties the keys it read, and no scan fills the store). Steps after the
+    count and atomic-log diagnostics (which scan without signing), after the
+    vertices shrank (fewer bricks) and after they grew again each equal, bit for
+    bit, single-mesh runs that fill their own store."""
+    meshes, grids = small_batch(5)
+    print("[case] kept-empty store: batch of", len(meshes), flush=True)
+    B = P.Batch(meshes, grids)
+    assert B.options.keep_store_empty == 1
+
+    def check_against_single(tag):
+        B.step()
+        B.check()
+        for m, (_, f) in enumerate(meshes):
+            a = sum(B.nv[:m])
+            v = B.verts[a:a + B.nv[m]].cpu().numpy()
+            c1, s1, f1, _ = single(v, f, grids[m])
+            c2, s2, f2 = batch_band(B, m)
+            assert np.array_equal(c1, c2) and np.array_equal(s1, s2) and np.array_equal(f1, f2), (tag, m)
+
+    check_against_single("first")
+    P.csc_scan_convert_count(B.f, B.workspace)
+    P.csc_scan_record_atomics(B.f, B.workspace, -1)
+    torch.cuda.synchronize()
+    check_against_single("after diagnostics")
+    nb0 = int(B.f.info()["n_bricks"])
+    B.verts.sub_(0.5).mul_(0.9).add_(0.5)
+    check_against_single("shrunk")
+    assert int(B.f.info()["n_bricks"]) < nb0
+    B.verts.sub_(0.5).mul_(1.0 / 0.9 * 1.01).add_(0.5)
+    check_against_single("grown")

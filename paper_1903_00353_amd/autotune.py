@@ -16,7 +16,9 @@ The tuner times candidates on the caller's own workload with the library's stage
 events (HIP events on the working stream): first ``small_rows`` per kind (each
 kind's one-lane launch plus its overflow launch), then ``scan_grid`` and
 ``absorb_cells`` one after the other on the time of the whole forward pass
-(scans and sign), then (batches) ``geom_blocks`` on the build's time. It caches
+(scans and sign; for a batch, whose edge and vertex kinds run on a second
+stream beside the faces, so that stage times do not add up, on the time of
+its whole step), then (batches) ``geom_blocks`` on the build's time. It caches
 the choice as JSON keyed by the device and the workload's shape.
 """
 from __future__ import annotations
@@ -49,7 +51,7 @@ def signature(nf_list, grids) -> str:
     tri_cells = faces / max(1.0, cells ** (2.0 / 3.0))  # triangles per cell of surface area (rough)
     return (f"{getattr(dev, 'gcnArchName', dev.name)}|n={len(grids)}|F=2^{round(math.log2(max(faces, 1)))}"
             f"|cells=2^{round(math.log2(max(cells, 1)))}|band={band:g}|tpc=2^{round(math.log2(max(tri_cells, 1e-9)))}"
-            f"|v3")
+            f"|v4")
 
 
 def load(sig: str):
@@ -104,6 +106,24 @@ def _forward_time(t):
     return sum(t[k] for k in FORWARD_STAGES)
 
 
+def _score(t):
+    # a batch's measurements carry its whole step's time (kinds overlapped)
+    return t["step"] if "step" in t else _forward_time(t)
+
+
+def _step_time(run, reps):
+    import torch
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def _search(measure, base, reps, build=False):
     """measure(options) -> per-stage ms per call; returns (choice, timings).
     build: measure also times the build (its stage), and geom_blocks is tuned."""
@@ -113,13 +133,13 @@ def _search(measure, base, reps, build=False):
     rows = tuple(min(CANDIDATES, key=lambda c: _kind_times(timings[f"rows={c}"])[k]) for k in range(3))
     best_grid, best_t = base.scan_grid or 2, None
     for g in GRID_CANDIDATES:
-        t = _forward_time(measure(_with(base, rows=rows, grid=g), reps))
+        t = _score(measure(_with(base, rows=rows, grid=g), reps))
         timings[f"grid={g}"] = t
         if best_t is None or t < best_t:
             best_grid, best_t = g, t
     best_absorb, best_t = 0.05, None
     for a in ABSORB_CANDIDATES:
-        t = _forward_time(measure(_with(base, rows=rows, grid=best_grid, absorb=a), reps))
+        t = _score(measure(_with(base, rows=rows, grid=best_grid, absorb=a), reps))
         timings[f"absorb={a}"] = t
         if best_t is None or t < best_t:
             best_absorb, best_t = a, t
@@ -152,7 +172,9 @@ def tune_batch(batch, reps=3, use_cache=True):
     if choice is None:
         def measure(opt, reps):
             rebuild(opt)
-            return _stage_times(batch.step, reps)
+            t = _stage_times(batch.step, reps)
+            t["step"] = _step_time(batch.step, max(10, reps))  # stage timing off: kinds overlapped
+            return t
         choice, timings = _search(measure, base, reps, build=True)
         save(sig, choice, timings)
     rebuild(options_for(choice, base))

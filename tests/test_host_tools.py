@@ -45,6 +45,28 @@ def test_search_picks_each_minimum_in_turn():
     assert autotune.options_for(choice).geom_blocks == 256
 
 
+def test_batch_search_scores_grid_and_absorb_by_step():
+    """A batch's measurements carry its whole step's time ("step"): the grid and
+    the absorption cap are chosen on it, not on the sum of the stages, which
+    overlap in a batch (here the stage sum favours grid 2 and cap 0.2, the step
+    grid 1 and cap 0.1)."""
+    def stages(opt):
+        t = fake_stage_times(opt)
+        t["init_keys"] = 0.0 if abs(opt.absorb_cells - 0.2) < 1e-6 else 0.05
+        return t
+
+    def with_step(opt):
+        t = stages(opt)
+        t["step"] = 2.0 + abs(opt.absorb_cells - 0.1) + {1: 0.0, 2: 0.1, 3: 0.2}.get(opt.scan_grid, 0.1)
+        return t
+
+    base = P.make_options()
+    assert autotune._search(lambda opt, reps: stages(opt), base, 1)[0][1:3] == (2, 0.2)
+    choice, timings = autotune._search(lambda opt, reps: with_step(opt), base, 1, build=True)
+    assert choice[1:3] == (1, 0.1)
+    assert timings["absorb=0.1"] == pytest.approx(2.0)
+
+
 def test_cache_round_trip(tmp_path, monkeypatch):
     path = tmp_path / "tune.json"
     monkeypatch.setenv("CSC_AUTOTUNE_CACHE", str(path))

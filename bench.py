@@ -589,7 +589,9 @@ def summarize_counters(args):
              f"WRITE_SIZE {cw[copy_name]:.0f} KiB -> scale {write_scale:.4f}",
              "kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes/launch (scaled)"]
     for stage, sym in symbol_of.items():
-        names = [k for k in fetch if (sym + "(") in k]
+        # a plain kernel name, or any instance of a template of that name (the sign
+        # pass: k_sign<true> when the batch keeps its store empty, else k_sign<false>)
+        names = sorted((k for k in fetch if (sym + "(") in k or (sym + "<") in k), key=lambda k: -write.get(k, 0.0))
         if not names:
             continue
         k = names[0]

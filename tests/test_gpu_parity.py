@@ -344,3 +344,39 @@ def test_autograd_function():
     scale = vertex_term_scale(f, oracle.OracleMesh(v, f).edges, v.shape[0], band.feat.cpu().numpy(),
                               2.0 * band.sdf.cpu().numpy())
     assert_same_sums(verts.grad.cpu().numpy(), ref.cpu().numpy(), scale)
+
+
+def test_single_mesh_kept_empty_store():
+    """keep_store_empty through the single-mesh entry point: a workspace filled
+    with 0xFF once, then scans (one writing the dense field too, one after the
+    count diagnostic, one after the vertices moved) that never fill the store
+    themselves, each equal bit for bit to a scan that fills its own store."""
+    v, f = meshgen.icosphere(4, 0.35, 1e-3, 11)
+    g = Grid.unit(96, 3)
+    print(f"[case] kept-empty store, single mesh F={f.shape[0]} n={g.n}", flush=True)
+    verts, tris = torch.from_numpy(v).cuda(), torch.from_numpy(f).cuda()
+    kept = P.csc_build_features(verts, tris, g, P.make_options(keep_store_empty=1))
+    # room for the bricks the moved vertices reach
+    nbytes, _ = P.csc_scan_convert_workspace_for(kept, 2 * int(kept.info()["n_bricks"]))
+    ws = torch.full((max(nbytes, 1),), 255, dtype=torch.uint8, device="cuda")
+
+    def reference():
+        fresh = P.csc_build_features(verts, tris, g)
+        band = to_np(P.csc_scan_convert(fresh))
+        fresh.free()
+        return band
+
+    n = int(np.prod(g.n))
+    for it in range(4):
+        if it == 2:
+            P.csc_scan_convert_count(kept, ws)
+        if it == 3:
+            verts.sub_(0.5).mul_(1.01).add_(0.5)
+            P.csc_build_features(verts, tris, g, P.make_options(keep_store_empty=1), reuse=kept)
+        dense = torch.empty(n, dtype=torch.float32, device="cuda") if it == 1 else None
+        band = P.csc_scan_convert(kept, ws, dense=dense)
+        got, ref = to_np(band), reference()
+        assert all(np.array_equal(a, b) for a, b in zip(got, ref)), it
+        if dense is not None:
+            d = dense.cpu().numpy()
+            assert np.array_equal(d[got[0]], got[1])

@@ -51,10 +51,9 @@ __global__ void k_zero_i64(int64_t* p, int n) {
 // Per face: its mesh, index range and repeated-corner checks, global indices. A
 // face with a bad index is replaced by three copies of its mesh's first vertex so
 // that every later access stays in bounds (the build then reports the error).
-__device__ inline void globalize_face(const int32_t* __restrict__ T, int64_t f, const int32_t* __restrict__ f_off,
-                                      const int32_t* __restrict__ v_off, int n_meshes, int32_t* tg,
-                                      int32_t* face_mesh, int32_t* owned, int64_t* stats) {
-  const int m = find_segment(f_off, n_meshes + 1, f);
+__device__ inline void globalize_face(const int32_t* __restrict__ T, int64_t f, int m,
+                                      const int32_t* __restrict__ v_off, int32_t* tg, int32_t* face_mesh,
+                                      int32_t* owned, int64_t* stats) {
   const int32_t nvm = v_off[m + 1] - v_off[m], vo = v_off[m];
   int32_t a = T[3 * f], b = T[3 * f + 1], c = T[3 * f + 2];
   if (a < 0 || b < 0 || c < 0 || a >= nvm || b >= nvm || c >= nvm) {
@@ -73,15 +72,31 @@ __device__ inline void globalize_face(const int32_t* __restrict__ T, int64_t f, 
   owned[3 * f + 2] = c < a ? 1 : 0;
 }
 
+// the largest m with off[m] <= x (off ascending, off[n_meshes] > x), stepping up
+// from m0 <= that m
+__device__ inline int segment_from(const int32_t* __restrict__ off, int m0, int64_t x) {
+  int m = m0;
+  while ((int64_t)off[m + 1] <= x) m++;
+  return m;
+}
+
 // the input passes in one launch: finite coordinates (thread i < 3 nv); global
-// indices and owned half-edges of face i < nf; mesh of vertex i < nv
+// indices and owned half-edges of face i < nf; mesh of vertex i < nv. The meshes
+// of the block's first face and vertex are searched once; each thread steps up
+// from there (a block rarely crosses a mesh boundary).
 __global__ void k_inputs(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ T, int64_t nf,
                          const int32_t* __restrict__ f_off, const int32_t* __restrict__ v_off, int n_meshes,
                          int32_t* tg, int32_t* face_mesh, int32_t* owned, int32_t* vert_mesh, int64_t* stats) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  __shared__ int s_mf, s_mv;
+  const int64_t b0 = blockIdx.x * (int64_t)blockDim.x, i = b0 + threadIdx.x;
+  if (threadIdx.x == 0) {
+    s_mf = b0 < nf ? find_segment(f_off, n_meshes + 1, b0) : 0;
+    s_mv = b0 < nv ? find_segment(v_off, n_meshes + 1, b0) : 0;
+  }
+  __syncthreads();
   if (i < 3 * nv && !isfinite(V[i])) atomicOr(err_word(stats), ERR_NONFINITE);
-  if (i < nf) globalize_face(T, i, f_off, v_off, n_meshes, tg, face_mesh, owned, stats);
-  if (i < nv) vert_mesh[i] = find_segment(v_off, n_meshes + 1, i);
+  if (i < nf) globalize_face(T, i, segment_from(f_off, s_mf, i), v_off, tg, face_mesh, owned, stats);
+  if (i < nv) vert_mesh[i] = segment_from(v_off, s_mv, i);
 }
 
 struct FillJob {

@@ -70,13 +70,15 @@ def load_traffic(workload: str, kernel: str):
     return ent.get("bytes_per_launch")
 
 
-def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
+def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv, kept_store=False):
     """Bytes the method itself must move per launch of each single-kernel stage.
     atomics: packed atomicMin counts [faces, edges, vertices] of the
-    one-thread-per-polyhedron launches, then of the overflow launches."""
+    one-thread-per-polyhedron launches, then of the overflow launches.
+    kept_store: the key store is kept empty between scans (keep_store_empty): it
+    is not filled, and the sign pass writes each key it consumed back."""
     F, E = info["n_faces"], info["n_edges"]
-    if stage == "init_keys":
-        return 8 * info["max_band_cells"]  # every key of the allocated bricks
+    if stage == "init_keys":  # every key of the allocated bricks, or only the nine overflow counters
+        return 72 if kept_store else 8 * info["max_band_cells"]
     if stage == "scan_faces":   # per face its corners and unit normal (36 + 12 B), one u64 per atomic
         return 48 * F + 8 * atomics[0]
     if stage == "scan_edges":   # per edge polyhedron its record, endpoints and two normals (16 + 24 + 24 B)
@@ -85,8 +87,8 @@ def algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv):
         return 28 * info["n_vertex_polyhedra"] + 8 * atomics[2]
     if stage.endswith("_big"):  # overflow launches: their atomics (geometry counted above)
         return 8 * atomics[3 + ["scan_faces_big", "scan_edges_big", "scan_vertices_big"].index(stage)]
-    if stage == "sign":         # one key read and (sdf, id, cell) written per band cell
-        return 20 * band_cells
+    if stage == "sign":         # one key read and (sdf, id, cell) written per band cell (+ the key emptied)
+        return (28 if kept_store else 20) * band_cells
     if stage == "backward":     # (sdf, id, cell) read (the loss's 2*SDF formed inside), 3 floats per weighted vertex
         return 12 * band_cells + 12 * vert_refs
     raise KeyError(stage)
@@ -387,7 +389,7 @@ def parse_rows(text):
 def batch_algorithmic_bytes(stage, nf, nv, n_epoly, n_vpoly, atomics, band_cells, vert_refs, max_band_cells):
     info = {"n_faces": nf, "n_edges": 3 * nf // 2, "n_edge_polyhedra": n_epoly, "n_vertex_polyhedra": n_vpoly,
             "max_band_cells": max_band_cells}
-    return algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv)
+    return algorithmic_bytes(stage, info, atomics, band_cells, vert_refs, nv, kept_store=True)  # Batch keeps it
 
 
 def bench_batch(args):

@@ -98,6 +98,17 @@ def test_roofline_arithmetic():
     assert main["forward_frac"] == fwd["frac"]
 
 
+def test_algorithmic_bytes_of_a_kept_empty_store():
+    """With the key store kept empty (as a Batch does) the store is not filled and
+    the sign pass also writes each consumed key back."""
+    info = {"n_faces": 4, "n_edges": 6, "max_band_cells": 512 * 3}
+    assert bench.algorithmic_bytes("init_keys", info, [0] * 6, 100, 0, 4) == 8 * 512 * 3
+    assert bench.algorithmic_bytes("init_keys", info, [0] * 6, 100, 0, 4, kept_store=True) == 72
+    assert bench.algorithmic_bytes("sign", info, [0] * 6, 100, 0, 4) == 20 * 100
+    assert bench.algorithmic_bytes("sign", info, [0] * 6, 100, 0, 4, kept_store=True) == 28 * 100
+    assert bench.batch_algorithmic_bytes("init_keys", 4, 4, 0, 0, [0] * 6, 100, 0, 512 * 3) == 72
+
+
 def test_brick_cells_and_forward_bytes():
     assert bench.brick_cells({"max_band_cells": 512 * 7, "n_bricks": 7}) == 512
     assert bench.forward_bytes(10, 20, 30, [1, 2, 3, 4, 5, 6], 100) == 12 * 10 + 12 * 20 + 16 * 30 + 8 * 21 + 16 * 100

@@ -51,6 +51,23 @@ def test_weld_equals_oracle(name, shuffle):
     assert np.array_equal(vd.view(np.uint32), vo.view(np.uint32))
 
 
+def test_weld_large_soup():
+    """The flat soup of the L9 icosphere (15.7M corners: enough for the radix
+    sort's 8192-pair tiles, used from 12.6M pairs) welds back to that mesh, whose
+    2.6M positions are all distinct: vertices numbered by first appearance in
+    corner order, positions bit for bit."""
+    v, f = meshgen.icosphere(9, 0.35)
+    print("[case] weld icosphere L9 soup", f.shape, flush=True)
+    vd, td = device_weld(v[f])
+    ids, first = np.unique(f.ravel(), return_index=True)
+    order = ids[np.argsort(first, kind="stable")]
+    rank = np.empty(v.shape[0], np.int64)
+    rank[order] = np.arange(order.size)
+    assert vd.shape == v.shape
+    assert np.array_equal(td, rank[f].astype(np.int32))
+    assert np.array_equal(vd.view(np.uint32), v[order].view(np.uint32))
+
+
 def test_weld_signed_zero_and_single_triangle():
     soup = np.array([[[0.0, 0.5, -0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]],
                      [[-0.0, 0.5, 0.0], [0.0, 1.0, 0.0], [-1.0, 0.0, 0.0]]], dtype=np.float32)

@@ -27,7 +27,7 @@ import json
 import math
 import os
 
-CANDIDATES = (8, 16, 32, 64, 128, 1 << 24)
+CANDIDATES = (8, 16, 24, 32, 40, 48, 64, 96, 128, 1 << 24)
 GRID_CANDIDATES = (1, 2, 3)
 ABSORB_CANDIDATES = (-1.0, 0.02, 0.05, 0.1, 0.2)
 GEOM_CANDIDATES = (0, 128, 256, 512)
@@ -51,7 +51,7 @@ def signature(nf_list, grids) -> str:
     tri_cells = faces / max(1.0, cells ** (2.0 / 3.0))  # triangles per cell of surface area (rough)
     return (f"{getattr(dev, 'gcnArchName', dev.name)}|n={len(grids)}|F=2^{round(math.log2(max(faces, 1)))}"
             f"|cells=2^{round(math.log2(max(cells, 1)))}|band={band:g}|tpc=2^{round(math.log2(max(tri_cells, 1e-9)))}"
-            f"|v4")
+            f"|v5")
 
 
 def load(sig: str):

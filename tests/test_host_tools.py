@@ -15,7 +15,7 @@ def fake_stage_times(opt):
     """Per-stage ms of a made-up workload: faces fastest at 32 rows, edges at 8,
     vertices with no overflow pass; grid 2 and absorb 0.1 fastest."""
     rows = tuple(opt.small_rows)
-    cost = {8: 3.0, 16: 2.0, 32: 1.0, 64: 1.5, 128: 2.5, 1 << 24: 4.0}
+    cost = {8: 3.0, 16: 2.0, 24: 1.5, 32: 1.0, 40: 1.2, 48: 1.3, 64: 1.5, 96: 2.0, 128: 2.5, 1 << 24: 4.0}
     t = {k: 0.0 for k in autotune.FORWARD_STAGES}
     t["scan_faces"] = cost[rows[0]]
     t["scan_edges"] = {8: 0.5}.get(rows[1], 1.0)

@@ -18,7 +18,8 @@ kind's one-lane launch plus its overflow launch), then ``scan_grid`` and
 ``absorb_cells`` one after the other on the time of the whole forward pass
 (scans and sign; for a batch, whose edge and vertex kinds run on a second
 stream beside the faces, so that stage times do not add up, on the time of
-its whole step), then (batches) ``geom_blocks`` on the build's time. It caches
+its whole step, on which a batch's rows per kind are refined as well), then
+(batches) ``geom_blocks`` on the build's time. It caches
 the choice as JSON keyed by the device and the workload's shape.
 """
 from __future__ import annotations
@@ -51,7 +52,7 @@ def signature(nf_list, grids) -> str:
     tri_cells = faces / max(1.0, cells ** (2.0 / 3.0))  # triangles per cell of surface area (rough)
     return (f"{getattr(dev, 'gcnArchName', dev.name)}|n={len(grids)}|F=2^{round(math.log2(max(faces, 1)))}"
             f"|cells=2^{round(math.log2(max(cells, 1)))}|band={band:g}|tpc=2^{round(math.log2(max(tri_cells, 1e-9)))}"
-            f"|v5")
+            f"|v6")
 
 
 def load(sig: str):
@@ -131,6 +132,19 @@ def _search(measure, base, reps, build=False):
     for c in CANDIDATES:
         timings[f"rows={c}"] = measure(_with(base, rows=(c, c, c)), reps)
     rows = tuple(min(CANDIDATES, key=lambda c: _kind_times(timings[f"rows={c}"])[k]) for k in range(3))
+    if build:
+        # a batch: its kinds overlap on two streams, so each kind's rows are
+        # refined, one kind after the other, on the whole step
+        rows = list(rows)
+        for k in range(3):
+            best_t = None
+            for c in CANDIDATES:
+                r = tuple(c if j == k else rows[j] for j in range(3))
+                t = _score(measure(_with(base, rows=r), reps))
+                timings[f"rows{k}={c}"] = t
+                if best_t is None or t < best_t:
+                    rows[k], best_t = c, t
+        rows = tuple(rows)
     best_grid, best_t = base.scan_grid or 2, None
     for g in GRID_CANDIDATES:
         t = _score(measure(_with(base, rows=rows, grid=g), reps))
@@ -173,7 +187,7 @@ def tune_batch(batch, reps=3, use_cache=True):
         def measure(opt, reps):
             rebuild(opt)
             t = _stage_times(batch.step, reps)
-            t["step"] = _step_time(batch.step, max(10, reps))  # stage timing off: kinds overlapped
+            t["step"] = _step_time(batch.step, max(20, reps))  # stage timing off: kinds overlapped
             return t
         choice, timings = _search(measure, base, reps, build=True)
         save(sig, choice, timings)

@@ -67,6 +67,20 @@ def test_batch_search_scores_grid_and_absorb_by_step():
     assert timings["absorb=0.1"] == pytest.approx(2.0)
 
 
+def test_batch_search_refines_rows_by_step():
+    """For a batch the rows per kind are refined on the whole step: here the
+    faces' own stage times favour 32 rows and the step 40."""
+    def with_step(opt):
+        t = fake_stage_times(opt)
+        t["step"] = 2.0 + {40: 0.0}.get(opt.small_rows[0], 0.1) + 0.01 * (opt.small_rows[1] != 8)
+        return t
+    rows = autotune._search(lambda opt, reps: fake_stage_times(opt), P.make_options(), 1)[0][0]
+    assert rows[0] == 32
+    choice, timings = autotune._search(lambda opt, reps: with_step(opt), P.make_options(), 1, build=True)
+    assert choice[0][:2] == (40, 8)
+    assert timings["rows0=40"] == pytest.approx(2.0)
+
+
 def test_cache_round_trip(tmp_path, monkeypatch):
     path = tmp_path / "tune.json"
     monkeypatch.setenv("CSC_AUTOTUNE_CACHE", str(path))

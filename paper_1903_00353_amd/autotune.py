@@ -187,7 +187,7 @@ def tune_batch(batch, reps=3, use_cache=True):
         def measure(opt, reps):
             rebuild(opt)
             t = _stage_times(batch.step, reps)
-            t["step"] = _step_time(batch.step, max(20, reps))  # stage timing off: kinds overlapped
+            t["step"] = _step_time(batch.step, max(40, reps))  # stage timing off: kinds overlapped
             return t
         choice, timings = _search(measure, base, reps, build=True)
         save(sig, choice, timings)
